@@ -1,0 +1,377 @@
+"""Pins that tie the FP64 oracle to facts fixed outside it (CPU only).
+
+Each test checks the oracle against something other than itself: the paper's
+printed worked example, closed forms, a brute-force LP, a textbook special
+case (convolution on a uniform mesh), identities of the Kronecker structure,
+the operation-count bounds of section 2.3, invariances of the problem, and the
+entropic gap bound.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import clib, closed_form as cf, dense
+from paper_2605_26659_amd import workloads as wl
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_problem(seed, n, m, ties=False):
+    rng = np.random.default_rng(seed)
+    x = np.sort(rng.uniform(0, 1, n))
+    y = np.sort(rng.uniform(0, 1, m))
+    if ties:
+        k = min(n, m) // 3
+        y[rng.choice(m, k, replace=False)] = x[rng.choice(n, k, replace=False)]
+        y = np.sort(y)
+        x[: n // 4] = np.round(x[: n // 4], 2)
+        x = np.sort(x)
+    return x, y
+
+
+# ----------------------------------------------------------------------------
+# Worked example (section 2.2)
+# ----------------------------------------------------------------------------
+
+def _gold():
+    with open(os.path.join(GOLD, "worked_example.json")) as fh:
+        return json.load(fh)
+
+
+def test_worked_example_kernel_matrix():
+    g = _gold()
+    x, y = np.array(g["x"], float), np.array(g["y"], float)
+    K = dense.kernel_matrix(x, y, 1.0)
+    np.testing.assert_allclose(-np.log(K), np.array(g["K_exponents"], float), atol=1e-12)
+
+
+def test_worked_example_dividing_index_and_blocks():
+    g = _gold()
+    x, y = np.array(g["x"], float), np.array(g["y"], float)
+    zeta = clib.dividing_index(x, y)
+    assert list(zeta) == g["zeta"]
+    K = dense.kernel_matrix(x, y, 1.0)
+    n, m = K.shape
+    for i in range(n):
+        for j in range(m):
+            lo = g["K_L_exponents"][i][j]
+            up = g["K_U_exponents"][i][j]
+            in_lower = j < zeta[i]              # column j+1 <= zeta(i+1), 1-based
+            assert (lo is not None) == in_lower
+            assert (up is not None) == (not in_lower)
+            e = lo if lo is not None else up
+            assert abs(-np.log(K[i, j]) - e) < 1e-12
+
+
+def test_worked_example_vector_representation():
+    g = _gold()
+    x, y = np.array(g["x"], float), np.array(g["y"], float)
+    zeta, r, eta, rp, etap, _ = clib.vector_rep(x, y, 1.0)
+    assert list(zeta) == g["zeta"]
+    np.testing.assert_allclose(-np.log(r), g["r_exponents"], atol=1e-12)
+    np.testing.assert_allclose(-np.log(rp), g["rprime_exponents"], atol=1e-12)
+    for got, want in zip(eta, g["eta_exponents"]):
+        np.testing.assert_allclose(-np.log(got) if len(got) else [], want, atol=1e-12)
+    for got, want in zip(etap, g["etaprime_exponents"]):
+        np.testing.assert_allclose(-np.log(got) if len(got) else [], want, atol=1e-12)
+
+
+def test_worked_example_reconstruction():
+    """Rebuild K_L row by row (scale previous row by r_i, append eta_{i+1})."""
+    g = _gold()
+    x, y = np.array(g["x"], float), np.array(g["y"], float)
+    eps = 1.3
+    zeta, r, eta, rp, etap, _ = clib.vector_rep(x, y, eps)
+    K = dense.kernel_matrix(x, y, eps)
+    n, m = K.shape
+    KL = np.zeros((n, m)); KU = np.zeros((n, m))
+    row = np.array([])
+    for i in range(n):
+        row = (row * r[i - 1] if i > 0 else row)
+        row = np.concatenate([row, eta[i]])
+        KL[i, : len(row)] = row
+    row = np.array([])
+    for i in range(n - 1, -1, -1):
+        row = (row * rp[i] if i < n - 1 else row)
+        row = np.concatenate([etap[i], row])
+        KU[i, m - len(row):] = row
+    np.testing.assert_allclose(KL + KU, K, rtol=1e-15, atol=0)
+    assert np.all((KL == 0) | (KU == 0))
+
+
+# ----------------------------------------------------------------------------
+# Operation counts (section 2.3, eq. number of multiplications / additions)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_operation_counts(seed):
+    n = 40 + seed * 7
+    x, y = _rand_problem(seed, n, n, ties=seed % 2 == 1)
+    eps = 0.2
+    psi = np.random.default_rng(seed).uniform(0.1, 1, n)
+    out, nmul, nadd, zeta = clib.rep_matvec(x, y, psi, eps)
+    np.testing.assert_allclose(out, dense.matvec(x, y, psi, eps), rtol=1e-13)
+    z1, zN = int(zeta[0]), int(zeta[-1])
+    bound_mul = 3 * n + zN - z1 - 2
+    bound_add = 2 * n + zN - z1 - 2
+    assert nmul <= bound_mul and nadd <= bound_add
+    assert bound_mul < 4 * n and bound_add < 3 * n
+    if z1 >= 1 and zN < n:
+        assert (nmul, nadd) == (bound_mul, bound_add)
+
+
+def test_operation_counts_generic_case_exact():
+    x = np.linspace(0.05, 0.95, 30)
+    y = np.linspace(0.0, 1.0, 30)          # zeta(1) >= 1 and zeta(N) < N
+    psi = np.linspace(1, 2, 30)
+    out, nmul, nadd, zeta = clib.rep_matvec(x, y, psi, 0.1)
+    assert zeta[0] >= 1 and zeta[-1] < 30
+    assert nmul == 3 * 30 + zeta[-1] - zeta[0] - 2
+    assert nadd == 2 * 30 + zeta[-1] - zeta[0] - 2
+
+
+# ----------------------------------------------------------------------------
+# Dense product: special cases and cross-checks
+# ----------------------------------------------------------------------------
+
+def test_uniform_mesh_is_a_convolution():
+    """On x = y uniform with spacing h, K psi is psi convolved with e^{-|k|h/eps}."""
+    n, h, eps = 301, 1.0 / 300, 0.02
+    x = np.arange(n) * h
+    rng = np.random.default_rng(3)
+    psi = rng.uniform(0.5, 1.5, n)
+    kern = np.exp(-np.abs(np.arange(-(n - 1), n)) * h / eps)
+    want = np.convolve(psi, kern)[n - 1: 2 * n - 1]
+    got = np.exp(dense.logmatvec(x, x, 0.02 * np.log(psi), eps) / eps)
+    np.testing.assert_allclose(got, want, rtol=1e-13)
+    got_c = np.exp(clib.finom_logmatvec(x, x, eps * np.log(psi), eps) / eps)
+    np.testing.assert_allclose(got_c, want, rtol=1e-13)
+
+
+def test_log_and_linear_dense_agree():
+    x, y = _rand_problem(5, 70, 90)
+    psi = np.random.default_rng(5).uniform(0.2, 2, 90)
+    eps = 0.05
+    np.testing.assert_allclose(np.exp(dense.logmatvec(x, y, eps * np.log(psi), eps) / eps),
+                               dense.matvec(x, y, psi, eps), rtol=1e-13)
+
+
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 1e-3])
+@pytest.mark.parametrize("case", ["random", "ties", "n>m", "n<m", "graded"])
+def test_c_recurrences_equal_dense_product(eps, case):
+    """eq. (p-DP)/(q-DP) in log form reproduce the dense product (FINOM is exact)."""
+    if case == "graded":
+        x, y = wl.mesh_square_law(700), wl.mesh_chebyshev(650)
+    else:
+        n, m = {"random": (500, 500), "ties": (400, 400), "n>m": (600, 211),
+                "n<m": (123, 777)}[case]
+        x, y = _rand_problem(11, n, m, ties=case == "ties")
+    rng = np.random.default_rng(7)
+    g = eps * rng.normal(0, 30, len(y))     # potentials spanning many decades
+    want = dense.logmatvec(x, y, g, eps)
+    got = clib.finom_logmatvec(x, y, g, eps)
+    assert np.max(np.abs(got - want)) / eps <= 1e-12
+    got_d = clib.dense_logmatvec(x, y, g, eps)
+    assert np.max(np.abs(got_d - want)) / eps <= 1e-12
+
+
+def test_single_point_meshes():
+    for n, m in [(1, 1), (1, 9), (9, 1)]:
+        x, y = _rand_problem(2, n, m)
+        g = np.linspace(-0.1, 0.1, m)
+        want = dense.logmatvec(x, y, g, 0.05)
+        np.testing.assert_allclose(clib.finom_logmatvec(x, y, g, 0.05), want, rtol=0, atol=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# Closed-form W1, LP, monotone coupling
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(5))
+def test_closed_form_w1_equals_lp(seed):
+    rng = np.random.default_rng(100 + seed)
+    n, m = rng.integers(1, 9, size=2)
+    x = np.sort(rng.uniform(0, 1, n)); y = np.sort(rng.uniform(0, 1, m))
+    u = wl.normalise(rng.uniform(0.1, 1, n)); v = wl.normalise(rng.uniform(0.1, 1, m))
+    w = cf.w1_closed_form(x, u, y, v)
+    assert abs(cf.w1_lp(x, u, y, v) - w) <= 1e-12
+    P = cf.monotone_coupling(u, v)
+    np.testing.assert_allclose(P.sum(1), u, atol=1e-15)
+    np.testing.assert_allclose(P.sum(0), v, atol=1e-15)
+    assert abs(np.sum(P * dense.cost_matrix(x, y)) - w) <= 1e-12
+
+
+def test_closed_form_w1_dirac_shift():
+    # W1(delta_a, delta_b) = |a - b|; a shifted uniform measure moves by the shift.
+    assert abs(cf.w1_closed_form([0.2], [1.0], [0.7], [1.0]) - 0.5) < 1e-15
+    x = np.linspace(0, 1, 11)
+    u = np.full(11, 1 / 11)
+    assert abs(cf.w1_closed_form(x, u, x + 0.3, u) - 0.3) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# Dense Sinkhorn (Algorithm 1 semantics)
+# ----------------------------------------------------------------------------
+
+def test_dense_sinkhorn_entropic_gap_and_marginals():
+    p = wl.config_small_1d(n=128)
+    r = dense.sinkhorn_1d(p.x, p.y, p.u, p.v, p.eps, 1e-9, 20000)
+    assert r.converged and r.err <= 1e-9
+    # u-side exactly satisfied after the phi update
+    s = dense.logmatvec(p.x, p.y, r.g, p.eps)
+    np.testing.assert_allclose(np.exp((r.f + s) / p.eps), p.u, rtol=1e-13)
+    G = dense.plan_1d(p.x, p.y, r.f, r.g, p.eps)
+    assert abs(G.sum(0) - p.v).sum() <= 1e-9 * 1.01
+    lo, hi = cf.entropic_w1_bounds(p.x, p.u, p.y, p.v, p.eps, r.err)
+    assert lo <= r.w1 <= hi
+    assert abs(np.sum(G * dense.cost_matrix(p.x, p.y)) - r.w1) <= 1e-15
+
+
+def test_eps_to_zero_limit():
+    rng = np.random.default_rng(9)
+    x = np.sort(rng.uniform(0, 1, 48)); y = np.sort(rng.uniform(0, 1, 40))
+    u = wl.normalise(rng.uniform(0.1, 1, 48)); v = wl.normalise(rng.uniform(0.1, 1, 40))
+    wstar = cf.w1_closed_form(x, u, y, v)
+    gaps = []
+    for eps in [1e-1, 3e-2, 1e-2]:
+        r = dense.sinkhorn_1d(x, y, u, v, eps, 1e-12, 200000)
+        lo, hi = cf.entropic_w1_bounds(x, u, y, v, eps, r.err)
+        assert lo <= r.w1 <= hi
+        gaps.append(r.w1 - wstar)
+    assert gaps[0] > gaps[1] > gaps[2] >= -1e-10
+
+
+def test_iteration_cap_and_zero_iterations():
+    p = wl.config_small_1d(n=64)
+    r0 = dense.sinkhorn_1d(p.x, p.y, p.u, p.v, p.eps, 0.0, 0)
+    assert r0.iters == 0
+    np.testing.assert_allclose(r0.f, p.eps * np.log(1 / 64))
+    r3 = dense.sinkhorn_1d(p.x, p.y, p.u, p.v, p.eps, 0.0, 3)
+    assert r3.iters == 3 and not r3.converged
+
+
+def test_c_algorithm1_matches_dense_iterates():
+    """Algorithm 1 with the recurrences = dense Sinkhorn, same l, same potentials."""
+    for eps, n, m in [(0.01, 300, 257), (0.003, 200, 200)]:
+        rng = np.random.default_rng(int(eps * 1e4) + n)
+        x = np.sort(rng.uniform(0, 1, n)); y = np.sort(rng.uniform(0, 1, m))
+        u = wl.normalise(rng.uniform(0.1, 1, n)); v = wl.normalise(rng.uniform(0.1, 1, m))
+        d = dense.sinkhorn_1d(x, y, u, v, eps, 1e-7, 3000)
+        f, g, it, err = clib.sinkhorn_1d(x, y, u, v, eps, 1e-7, 3000)
+        assert it == d.iters
+        assert np.max(np.abs(f - d.f)) / eps <= 1e-10
+        assert np.max(np.abs(g - d.g)) / eps <= 1e-10
+        assert abs(err - d.err) <= 1e-12 * max(1.0, d.err) + 1e-15
+        fd, gd, itd, errd = clib.dense_sinkhorn_1d(x, y, u, v, eps, 1e-7, 3000)
+        assert itd == d.iters and np.max(np.abs(fd - d.f)) / eps <= 1e-10
+
+
+def test_paper_table_plan_difference_is_rounding_level():
+    """Tables 1-2 report ||Gamma_FINOM - Gamma_Sinkhorn||_F ~ 1e-17 at N = 500."""
+    for prob in (wl.paper_chebyshev_1d(500, iters=200), wl.paper_random_1d(500, iters=200)):
+        fd, gd, itd, _ = clib.dense_sinkhorn_1d(prob.x, prob.y, prob.u, prob.v, prob.eps, 0.0, 200)
+        f, g, it, _ = clib.sinkhorn_1d(prob.x, prob.y, prob.u, prob.v, prob.eps, 0.0, 200)
+        dG = dense.plan_1d(prob.x, prob.y, f, g, prob.eps) - dense.plan_1d(prob.x, prob.y, fd, gd, prob.eps)
+        assert np.linalg.norm(dG) <= 1e-15
+
+
+# ----------------------------------------------------------------------------
+# Invariances
+# ----------------------------------------------------------------------------
+
+def test_shift_scale_swap_invariances():
+    rng = np.random.default_rng(21)
+    x = np.sort(rng.uniform(0, 1, 60)); y = np.sort(rng.uniform(0, 1, 50))
+    u = wl.normalise(rng.uniform(0.1, 1, 60)); v = wl.normalise(rng.uniform(0.1, 1, 50))
+    eps, tol = 0.02, 1e-12
+    base = dense.sinkhorn_1d(x, y, u, v, eps, tol, 100000)
+    sh = dense.sinkhorn_1d(x + 3.25, y + 3.25, u, v, eps, tol, 100000)
+    assert sh.iters == base.iters and abs(sh.w1 - base.w1) <= 1e-12 * base.w1
+    sc = dense.sinkhorn_1d(2.5 * x, 2.5 * y, u, v, 2.5 * eps, tol, 100000)
+    assert abs(sc.w1 - 2.5 * base.w1) <= 1e-12 * base.w1
+    sw = dense.sinkhorn_1d(y, x, v, u, eps, tol, 100000)
+    assert abs(sw.w1 - base.w1) <= 2.0 * tol + 1e-14
+
+
+# ----------------------------------------------------------------------------
+# 2D: Kronecker structure (section 3) and product measures
+# ----------------------------------------------------------------------------
+
+def test_kronecker_identity():
+    rng = np.random.default_rng(4)
+    x1, x2 = np.sort(rng.uniform(0, 1, 5)), np.sort(rng.uniform(0, 1, 4))
+    y1, y2 = np.sort(rng.uniform(0, 1, 3)), np.sort(rng.uniform(0, 1, 6))
+    eps = 0.3
+    Kx = dense.kernel_matrix(x1, x2, eps)
+    Ky = dense.kernel_matrix(y1, y2, eps)
+    XR, YR = np.meshgrid(x1, y1, indexing="ij")
+    XC, YC = np.meshgrid(x2, y2, indexing="ij")
+    px, py = XR.ravel(order="F"), YR.ravel(order="F")
+    qx, qy = XC.ravel(order="F"), YC.ravel(order="F")
+    K = np.exp(-(np.abs(px[:, None] - qx[None, :]) + np.abs(py[:, None] - qy[None, :])) / eps)
+    np.testing.assert_allclose(K, np.kron(Ky, Kx), rtol=1e-15)
+    Psi = rng.uniform(0.1, 1, (4, 6))
+    np.testing.assert_allclose(K @ Psi.ravel(order="F"), (Kx @ Psi @ Ky.T).ravel(order="F"),
+                               rtol=1e-14)
+    Phi = rng.uniform(0.1, 1, (5, 3))
+    np.testing.assert_allclose(K.T @ Phi.ravel(order="F"), (Kx.T @ Phi @ Ky).ravel(order="F"),
+                               rtol=1e-14)
+
+
+def test_axis_by_axis_equals_full_and_c_sweeps():
+    rng = np.random.default_rng(8)
+    x1, x2 = np.sort(rng.uniform(0, 1, 7)), np.sort(rng.uniform(0, 1, 9))
+    y1, y2 = np.sort(rng.uniform(0, 1, 8)), np.sort(rng.uniform(0, 1, 5))
+    eps = 0.01
+    G = eps * rng.normal(0, 20, (9, 5))
+    full = dense.logmatvec_2d_full(x1, y1, x2, y2, G, eps)
+    axis = dense.logmatvec_2d(x1, y1, x2, y2, G, eps)
+    assert np.max(np.abs(full - axis)) / eps <= 1e-12
+    c = clib.finom_logmatvec_2d(x1, y1, x2, y2, G, eps)
+    assert np.max(np.abs(c - full)) / eps <= 1e-12
+
+
+def test_2d_product_measures_factorise():
+    """u = u_x (x) u_y and v = v_x (x) v_y: the 2D iterate at step l is the
+    product of the two 1D iterates and <C, Gamma> splits into the 1D costs."""
+    rng = np.random.default_rng(12)
+    x1, x2 = np.sort(rng.uniform(0, 1, 9)), np.sort(rng.uniform(0, 1, 8))
+    y1, y2 = np.sort(rng.uniform(0, 1, 7)), np.sort(rng.uniform(0, 1, 10))
+    ux, vx = wl.normalise(rng.uniform(.1, 1, 9)), wl.normalise(rng.uniform(.1, 1, 8))
+    uy, vy = wl.normalise(rng.uniform(.1, 1, 7)), wl.normalise(rng.uniform(.1, 1, 10))
+    eps, L = 0.05, 17
+    rx = dense.sinkhorn_1d(x1, x2, ux, vx, eps, 0.0, L)
+    ry = dense.sinkhorn_1d(y1, y2, uy, vy, eps, 0.0, L)
+    r2 = dense.sinkhorn_2d(x1, y1, x2, y2, np.outer(ux, uy), np.outer(vx, vy), eps, 0.0, L,
+                           full=True)
+    np.testing.assert_allclose(r2.f, rx.f[:, None] + ry.f[None, :], atol=1e-14 * 50)
+    np.testing.assert_allclose(r2.g, rx.g[:, None] + ry.g[None, :], atol=1e-14 * 50)
+    assert abs(r2.w1 - (rx.w1 + ry.w1)) <= 1e-14 * 10
+    r2a = dense.sinkhorn_2d(x1, y1, x2, y2, np.outer(ux, uy), np.outer(vx, vy), eps, 0.0, L)
+    assert abs(r2a.w1 - r2.w1) <= 1e-14 * 10
+
+
+def test_2d_lp_and_entropic_bounds_tiny():
+    rng = np.random.default_rng(31)
+    x1 = np.sort(rng.uniform(0, 1, 3)); y1 = np.sort(rng.uniform(0, 1, 3))
+    x2 = np.sort(rng.uniform(0, 1, 3)); y2 = np.sort(rng.uniform(0, 1, 2))
+    u = wl.normalise(rng.uniform(.1, 1, (3, 3))); v = wl.normalise(rng.uniform(.1, 1, (3, 2)))
+    XR, YR = np.meshgrid(x1, y1, indexing="ij"); XC, YC = np.meshgrid(x2, y2, indexing="ij")
+    w = cf.w1_lp_points(XR.ravel("F"), YR.ravel("F"), u.ravel("F"),
+                        XC.ravel("F"), YC.ravel("F"), v.ravel("F"))
+    eps = 0.01
+    r = dense.sinkhorn_2d(x1, y1, x2, y2, u, v, eps, 1e-12, 200000, full=True)
+    gap = eps * min(cf.entropy(u), cf.entropy(v))
+    assert w - 2 * r.err <= r.w1 <= w + gap + 2 * r.err
+
+
+def test_c_algorithm2_matches_dense():
+    p = wl.paper_random_2d(12, iters=40)
+    r = dense.sinkhorn_2d(p.x1, p.y1, p.x2, p.y2, p.u, p.v, p.eps, 0.0, 40)
+    F, G, it, err = clib.sinkhorn_2d(p.x1, p.y1, p.x2, p.y2, p.u, p.v, p.eps, 0.0, 40)
+    assert it == r.iters == 40
+    assert np.max(np.abs(F - r.f)) / p.eps <= 1e-10
+    assert np.max(np.abs(G - r.g)) / p.eps <= 1e-10
+    assert abs(err - r.err) <= 1e-12
