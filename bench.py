@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: FINOM Sinkhorn solves on one MI355X.
+
+Workload (one step = one full solve of the hot path: setup, Algorithm 1 loop
+to tolerance, <C, Gamma>): 1D entropic W1, n = m = 2^20 graded meshes
+(x = t^2, y = Chebyshev-clustered), 3-component Gaussian-mixture masses with a
+1e-6 floor, eps = 1e-3, tol 1e-6, FP32-mantissa scans with FP64 state.
+
+Prints one JSON line: grid-point iterations per second (grid points =
+(n + m)/2, iterations = completed Sinkhorn iterations), p50/p99 solve
+latency, the FP64-scan mode and the dense baseline at the same workload, the
+roofline of the dominant kernel and the CPU oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per grid point per iteration with FP64 state and
+# coordinates: K^T phi half reads f, x, y, v, g_old and writes g (16n + 32m);
+# K psi half reads g, y, x, u and writes f (24n + 16m).
+BYTES_KT = (16, 32)
+BYTES_K = (24, 16)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(prob, seconds):
+    """The oracle timed on host cores on a bounded sample of the workload.
+
+    kind 'oracle': the dense FP64 definition (eps ln K e^{g/eps}, OpenMP over
+    rows) on as many sampled rows as fit the time budget; one Sinkhorn
+    iteration needs n + m such rows, so grid-pt*iters/s = rows/s * points /
+    (n + m). Also times Algorithm 1 on the CPU (single thread) for a few
+    iterations of the full workload.
+    """
+    from oracle import clib
+    clib.build(force=False)
+    threads = min(16, os.cpu_count() or 1)
+    n, m = len(prob.x), len(prob.y)
+    g = prob.eps * np.log(prob.v)
+    rows = 64
+    t_used = 0.0
+    done_rows = 0
+    rng = np.random.default_rng(0)
+    while t_used < seconds * 0.5:
+        idx = np.sort(rng.integers(0, n, rows))
+        t0 = time.perf_counter()
+        clib.dense_logmatvec(prob.x, prob.y, g, prob.eps, rows=idx, threads=threads)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        done_rows += rows
+        rows = min(rows * 2, 1 << 14)
+    pts = 0.5 * (n + m)
+    dense_rate = done_rows / t_used * pts / (n + m)
+    # Algorithm 1 on the CPU: a few iterations on the full problem
+    iters = 1
+    t0 = time.perf_counter()
+    while True:
+        clib.sinkhorn_1d(prob.x, prob.y, prob.u, prob.v, prob.eps, 0.0, iters)
+        dt = time.perf_counter() - t0
+        if dt > seconds * 0.3 or iters >= 64:
+            break
+        iters *= 2
+        t0 = time.perf_counter()
+    alg1_rate = pts * iters / dt
+    return {
+        "value": dense_rate, "unit": "grid-pt*iters/s", "cores": threads, "kind": "oracle",
+        "sample": f"dense FP64 oracle, {done_rows} sampled rows x {m} columns of the "
+                  f"n=m={n} graded workload in {t_used:.1f} s",
+        "cpu_algorithm1": {"value": alg1_rate, "unit": "grid-pt*iters/s", "cores": 1,
+                           "sample": f"{iters} iterations of Algorithm 1 (FP64 log-form "
+                                     f"recurrences, C) on the full workload in {dt:.2f} s"},
+        "cpu_model": _cpu_model(),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported "
+              "(independent problems shard trivially; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2605_26659_amd import dense_matvec, sinkhorn_w1_1d, workloads as wl
+
+    prob = wl.config_graded_1d(args.n, args.eps, tol=args.tol)
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+    x, y, u, v = dev(prob.x), dev(prob.y), dev(prob.u), dev(prob.v)
+    f = torch.empty_like(x)
+    g = torch.empty_like(y)
+    prec = 1 if args.precision == "fp32" else 0
+    pts = 0.5 * (len(prob.x) + len(prob.y))
+
+    def solve(p=prec):
+        res, _, _ = sinkhorn_w1_1d(x, y, u, v, prob.eps, prob.tol, prob.itr_max, precision=p,
+                                   f_out=f, g_out=g)
+        return res
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    lat, its, loops, sweeps = [], [], [], []
+    last = None
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        last = solve()
+        lat.append(time.perf_counter() - t0)
+        its.append(last["iters"])
+        loops.append(last["loop_ms"])
+        sweeps.append(last["sweeps"])
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    value = pts * sum(its) / total
+
+    # dominant kernels: the half-iteration sweeps; average launch duration from
+    # the loop's HIP events divided by the sweeps executed
+    n, m = len(prob.x), len(prob.y)
+    bytes_iter = (BYTES_KT[0] + BYTES_K[0]) * n + (BYTES_KT[1] + BYTES_K[1]) * m
+    per_sweep_bytes = bytes_iter / 2.0
+    sweep_ms = sum(loops) / max(1, sum(sweeps))
+    achieved = per_sweep_bytes / (sweep_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "half-iteration sweep (k_tile_aggregate + k_sweep)",
+                "avg_sweep_us": sweep_ms * 1e3,
+                "algorithmic_bytes_per_sweep": per_sweep_bytes}
+
+    extra = {}
+    if not args.no_fp64_compare:
+        r64 = solve(0 if prec == 1 else 1)
+        t0 = time.perf_counter()
+        r64 = solve(0 if prec == 1 else 1)
+        dt = time.perf_counter() - t0
+        key = "fp64_scans" if prec == 1 else "fp32_scans"
+        extra[key] = {"value": pts * r64["iters"] / dt, "iters": r64["iters"],
+                      "w1": r64["w1"], "marginal_err": r64["marginal_err"],
+                      "w1_rel_diff_vs_headline": abs(r64["w1"] - last["w1"]) / r64["w1"]}
+    if not args.no_dense:
+        gin = torch.as_tensor(prob.eps * np.log(prob.v), dtype=torch.float64, device="cuda")
+        out = torch.empty_like(x)
+        dense_matvec(x, y, prob.eps, gin, out, domain=1, precision=prec, skip_checks=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 2
+        e0.record()
+        for _ in range(reps):
+            dense_matvec(x, y, prob.eps, gin, out, domain=1, precision=prec, skip_checks=True)
+        e1.record()
+        torch.cuda.synchronize()
+        per_product_s = e0.elapsed_time(e1) / reps * 1e-3
+        dense_rate = pts / (2.0 * per_product_s)
+        extra["dense_sinkhorn_gpu"] = {
+            "value": dense_rate, "unit": "grid-pt*iters/s",
+            "per_iteration_s": 2 * per_product_s,
+            "time_to_tol_s": 2 * per_product_s * its[-1],
+            "note": "dense on-the-fly-exp products; iterates equal FINOM's, so time to "
+                    "tolerance = per-iteration time x FINOM's iteration count"}
+        extra["speedup_vs_dense"] = value / dense_rate
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, args.cpu_seconds)
+
+    lat_ms = np.array(lat) * 1e3
+    line = {
+        "metric": "FINOM grid-pt*iters/s vs dense Sinkhorn at 1e-6 tol; p50/p99 solve latency",
+        "value": value, "unit": "grid-pt*iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == 1 else "f64", "data": "synthetic",
+        "config": {"workload": f"1D W1 graded meshes n=m={args.n} (x=t^2, y=Chebyshev), "
+                               f"3-GMM masses, eps={args.eps:g}, tol={args.tol:g}",
+                   "n": args.n, "m": args.n, "eps": args.eps, "tol": args.tol,
+                   "scan_mantissa": args.precision, "state": "f64"},
+        "iters_per_solve": its[-1], "w1": last["w1"], "marginal_err": last["marginal_err"],
+        "p50_latency_ms": float(np.percentile(lat_ms, 50)),
+        "p99_latency_ms": float(np.percentile(lat_ms, 99)),
+        "roofline": roofline, "cpu_baseline": cpu, **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,12 @@
+"""MI355X-native FINOM: fast Sinkhorn for entropic W1 on non-uniform meshes.
+
+The numerical work happens in ``libfinom.so`` (hand-written HIP for gfx950,
+C ABI in ``include/finom.h``); this package only marshals arguments to it and
+generates seeded synthetic workloads.
+"""
+from ._binding import (  # noqa: F401
+    FINOM_E_ADMIT, FINOM_E_ARG, FINOM_E_HIP, FINOM_E_MASS, FINOM_E_NOMEM,
+    FINOM_E_NUMERIC, FINOM_E_UNSORTED, FINOM_NOT_CONVERGED, FINOM_OK, FinomError,
+    LIB_PATH, declared_functions, dense_matvec, finom_matvec, finom_release,
+    finom_version, load, sinkhorn_w1_1d, sinkhorn_w1_2d, strerror,
+)

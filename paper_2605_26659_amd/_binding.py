@@ -1,0 +1,213 @@
+"""ctypes binding to libfinom.so (argument marshalling only).
+
+Every numerical step runs in the HIP library. Tensors are torch CUDA
+(HIP) float64 tensors; the stream is torch's current stream unless one is
+given. If the library is not built, importing the entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from pathlib import Path
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libfinom.so"
+HEADER = _PKG.parent / "include" / "finom.h"
+
+FINOM_OK = 0
+FINOM_NOT_CONVERGED = 1
+FINOM_E_ARG = -1
+FINOM_E_UNSORTED = -2
+FINOM_E_MASS = -3
+FINOM_E_NOMEM = -4
+FINOM_E_HIP = -5
+FINOM_E_ADMIT = -6
+FINOM_E_NUMERIC = -7
+
+
+class FinomError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("domain", C.c_int32),
+                ("skip_checks", C.c_int32), ("graph_iters", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("w1", C.c_double), ("marginal_err", C.c_double), ("iters", C.c_int64),
+                ("converged", C.c_int32), ("status", C.c_int32), ("loop_ms", C.c_double),
+                ("sweeps", C.c_int64)]
+
+    def as_dict(self):
+        return {"w1": self.w1, "marginal_err": self.marginal_err, "iters": int(self.iters),
+                "converged": bool(self.converged), "status": int(self.status),
+                "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps)}
+
+
+_lib = None
+_vp = C.c_void_p
+_i64 = C.c_int64
+_d = C.c_double
+
+
+def declared_functions():
+    """Names of the functions include/finom.h declares."""
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if not n.startswith("FINOM")))
+
+
+def load(path: os.PathLike | None = None):
+    """Load the library (no GPU call is made)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2605_26659_amd.build` "
+                           "(there is no CPU fallback)")
+    L = C.CDLL(str(p))
+    L.finom_matvec.argtypes = [_vp, _i64, _vp, _i64, _d, _vp, _vp, C.POINTER(Opts), _vp]
+    L.dense_matvec.argtypes = L.finom_matvec.argtypes
+    L.sinkhorn_w1_1d.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _d, _d, _i64, C.POINTER(Opts),
+                                 _vp, _vp, C.POINTER(Result), _vp]
+    L.finom_strerror.restype = C.c_char_p
+    L.finom_strerror.argtypes = [C.c_int]
+    L.finom_version.restype = C.c_char_p
+    L.finom_release.restype = None
+    if hasattr(L, "sinkhorn_w1_2d"):
+        L.sinkhorn_w1_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _d, _d,
+                                     _i64, C.POINTER(Opts), _vp, _vp, C.POINTER(Result), _vp]
+    if path is None:
+        _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().finom_strerror(int(status)).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+# ----------------------------------------------------------------------------
+# torch plumbing
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(int(s.cuda_stream))
+
+
+def _dev(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _opts(precision=0, domain=0, skip_checks=False, graph_iters=0):
+    return Opts(int(precision), int(domain), int(bool(skip_checks)), int(graph_iters))
+
+
+def _check(st, where, allow_warn=True):
+    if st < 0 or (st > 0 and not allow_warn):
+        raise FinomError(st, where)
+    return st
+
+
+# ----------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ----------------------------------------------------------------------------
+
+def finom_matvec(x_rows, y_cols, eps, inp, out=None, *, precision=0, domain=0,
+                 skip_checks=False, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(x_rows.numel(), dtype=torch.float64, device=x_rows.device)
+    st = load().finom_matvec(_dev(x_rows, "x_rows"), x_rows.numel(), _dev(y_cols, "y_cols"),
+                             y_cols.numel(), float(eps), _dev(inp, "in"), _dev(out, "out"),
+                             C.byref(_opts(precision, domain, skip_checks)), _stream_ptr(stream))
+    _check(st, "finom_matvec")
+    return out
+
+
+def dense_matvec(x_rows, y_cols, eps, inp, out=None, *, precision=0, domain=0,
+                 skip_checks=False, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(x_rows.numel(), dtype=torch.float64, device=x_rows.device)
+    st = load().dense_matvec(_dev(x_rows, "x_rows"), x_rows.numel(), _dev(y_cols, "y_cols"),
+                             y_cols.numel(), float(eps), _dev(inp, "in"), _dev(out, "out"),
+                             C.byref(_opts(precision, domain, skip_checks)), _stream_ptr(stream))
+    _check(st, "dense_matvec")
+    return out
+
+
+def sinkhorn_w1_1d(x, y, u, v, eps, tol, itr_max, *, precision=0, skip_checks=False,
+                   graph_iters=0, f_out=None, g_out=None, want_potentials=True, stream=None):
+    """Returns (result dict, f, g); f, g are eps ln phi / eps ln psi (device)."""
+    torch = _torch()
+    if want_potentials:
+        if f_out is None:
+            f_out = torch.empty(x.numel(), dtype=torch.float64, device=x.device)
+        if g_out is None:
+            g_out = torch.empty(y.numel(), dtype=torch.float64, device=y.device)
+    res = Result()
+    st = load().sinkhorn_w1_1d(_dev(x, "x"), x.numel(), _dev(y, "y"), y.numel(), _dev(u, "u"),
+                               _dev(v, "v"), float(eps), float(tol), int(itr_max),
+                               C.byref(_opts(precision, 0, skip_checks, graph_iters)),
+                               _dev(f_out, "f_out") if f_out is not None else None,
+                               _dev(g_out, "g_out") if g_out is not None else None,
+                               C.byref(res), _stream_ptr(stream))
+    _check(st, "sinkhorn_w1_1d")
+    return res.as_dict(), f_out, g_out
+
+
+def sinkhorn_w1_2d(x1, y1, x2, y2, u, v, eps, tol, itr_max, *, precision=0, skip_checks=False,
+                   graph_iters=0, f_out=None, g_out=None, want_potentials=True, stream=None):
+    """u is (len(x1), len(y1)) and v is (len(x2), len(y2)), both stored
+    column-major (the paper's grid order): pass ``t.T.contiguous().T``-style
+    tensors or flat column-major vectors. Returns (result, F, G) as flat
+    column-major vectors."""
+    torch = _torch()
+    n1, m1, n2, m2 = x1.numel(), y1.numel(), x2.numel(), y2.numel()
+    if want_potentials:
+        if f_out is None:
+            f_out = torch.empty(n1 * m1, dtype=torch.float64, device=x1.device)
+        if g_out is None:
+            g_out = torch.empty(n2 * m2, dtype=torch.float64, device=x1.device)
+    res = Result()
+    st = load().sinkhorn_w1_2d(_dev(x1, "x1"), n1, _dev(y1, "y1"), m1, _dev(x2, "x2"), n2,
+                               _dev(y2, "y2"), m2, _dev(u, "u"), _dev(v, "v"), float(eps),
+                               float(tol), int(itr_max),
+                               C.byref(_opts(precision, 0, skip_checks, graph_iters)),
+                               _dev(f_out, "f_out") if f_out is not None else None,
+                               _dev(g_out, "g_out") if g_out is not None else None,
+                               C.byref(res), _stream_ptr(stream))
+    _check(st, "sinkhorn_w1_2d")
+    return res.as_dict(), f_out, g_out
+
+
+def finom_release():
+    load().finom_release()
+
+
+def finom_version() -> str:
+    return load().finom_version().decode()

@@ -1,0 +1,213 @@
+// Host-side helpers: error mapping, the per-stream workspace arena, sweep
+// descriptors and their upload, kernel dispatch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "finom_kernels.hpp"
+
+namespace finom {
+
+constexpr int kBlock = 256;
+constexpr int kIptF32 = 8;    // T = 2048 merged elements per tile
+constexpr int kIptF64 = 4;    // T = 1024
+constexpr int kIptCost = 2;   // T = 512, FP64 moment sums (four LDS arrays)
+constexpr double kLn2 = 0.69314718055994530942;
+
+struct HipError {
+    hipError_t e;
+};
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t _e = (x);                       \
+        if (_e != hipSuccess) throw HipError{_e};  \
+    } while (0)
+
+inline unsigned blocks_for(long long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+inline int ntiles_for(long long R, long long C, int T) { return (int)((R + C + T - 1) / T); }
+inline int tile_size(int precision) { return kBlock * (precision == 1 ? kIptF32 : kIptF64); }
+inline int cost_tile_size() { return kBlock * kIptCost; }
+inline size_t ext_bytes(int precision) { return precision == 1 ? sizeof(Ext<float>) : sizeof(Ext<double>); }
+
+// ---------------------------------------------------------------------------
+// Workspace: per stream, a list of device blocks and pinned host blocks.
+// A call carves what it needs with a bump pointer; when it overflows, another
+// block is added. At the start of the next call on the stream the blocks are
+// merged into one (after the stream has drained), so steady state is one
+// device block and one host block with no allocation per call.
+// ---------------------------------------------------------------------------
+struct Block {
+    char* p;
+    size_t cap;
+};
+
+struct Arena {
+    std::vector<Block> dblk, hblk;
+    size_t dused = 0, hused = 0;
+    hipEvent_t upload_done = nullptr;
+};
+
+Arena* arena_for(void* stream);
+void arena_release_all();
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Alloc {
+    Arena* a;
+    hipStream_t s;
+    explicit Alloc(void* stream) : a(arena_for(stream)), s((hipStream_t)stream) { begin(); }
+
+    void begin()
+    {
+        if (a->upload_done) HIPCHK(hipEventSynchronize(a->upload_done));
+        else HIPCHK(hipEventCreateWithFlags(&a->upload_done, hipEventDisableTiming));
+        if (a->dblk.size() > 1 || a->hblk.size() > 1) {
+            HIPCHK(hipStreamSynchronize(s));
+            merge(a->dblk, false);
+            merge(a->hblk, true);
+        }
+        a->dused = 0;
+        a->hused = 0;
+    }
+    static void merge(std::vector<Block>& v, bool host)
+    {
+        if (v.size() <= 1) return;
+        size_t tot = 0;
+        for (auto& b : v) {
+            tot += b.cap;
+            if (host) hipHostFree(b.p);
+            else hipFree(b.p);
+        }
+        v.clear();
+        Block b{nullptr, tot};
+        if (host) {
+            if (hipHostMalloc((void**)&b.p, tot, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
+        } else {
+            if (hipMalloc((void**)&b.p, tot) != hipSuccess) throw std::bad_alloc();
+        }
+        v.push_back(b);
+    }
+    static char* carve(std::vector<Block>& v, size_t& used, size_t bytes, size_t align, bool host)
+    {
+        bytes = align_up(std::max<size_t>(bytes, 1), align);
+        if (!v.empty()) {
+            size_t off = align_up(used, align);
+            if (off + bytes <= v.back().cap) {
+                used = off + bytes;
+                return v.back().p + off;
+            }
+        }
+        size_t cap = std::max(bytes, v.empty() ? (size_t)(host ? (1u << 20) : (16u << 20)) : v.back().cap);
+        Block b{nullptr, cap};
+        if (host) {
+            if (hipHostMalloc((void**)&b.p, cap, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
+        } else {
+            if (hipMalloc((void**)&b.p, cap) != hipSuccess) throw std::bad_alloc();
+        }
+        v.push_back(b);
+        used = bytes;
+        return b.p;
+    }
+    template <typename T>
+    T* dev(size_t count) { return reinterpret_cast<T*>(carve(a->dblk, a->dused, sizeof(T) * count, 256, false)); }
+    template <typename T>
+    T* host(size_t count) { return reinterpret_cast<T*>(carve(a->hblk, a->hused, sizeof(T) * count, 64, true)); }
+    void uploaded() { HIPCHK(hipEventRecord(a->upload_done, s)); }
+};
+
+// ---------------------------------------------------------------------------
+// Sweeps
+// ---------------------------------------------------------------------------
+struct SweepDev {
+    const WorkItem* work = nullptr;        // all tiles
+    int nwork = 0;
+    const WorkItem* work_multi = nullptr;  // tiles of lines with more than one tile
+    int nwork_multi = 0;
+    const LineDesc* lines = nullptr;
+    void* agg = nullptr;
+    void* carry = nullptr;
+    unsigned int* line_ctr = nullptr;
+};
+
+// kind: 0 = scan in the call's precision (plain sums), 1 = FP64 cost tile
+// (plain sums), 2 = FP64 cost tile with moment sums.
+struct Sweep {
+    std::vector<LineDesc> lines;
+    int kind = 0;
+    int epi = EPI_STORE_LOG2;
+    SweepDev dev;
+    int total_tiles() const
+    {
+        int t = 0;
+        for (auto& l : lines) t += l.ntiles;
+        return t;
+    }
+    int ns() const { return kind == 2 ? 4 : 2; }
+};
+
+inline LineDesc make_line(const double* xr, long long R, const double* yc, long long C,
+                          const int* zeta, const int* trs, int T, double eps)
+{
+    LineDesc L;
+    memset(&L, 0, sizeof(L));
+    L.xr = xr;
+    L.yc = yc;
+    L.zeta = zeta;
+    L.trs = trs;
+    L.R = R;
+    L.C = C;
+    L.gstride = 1;
+    L.ostride = 1;
+    L.kappa = 1.0 / (eps * kLn2);
+    L.in_scale = L.kappa;
+    L.out_scale = eps * kLn2;
+    L.ntiles = ntiles_for(R, C, T);
+    return L;
+}
+
+// Assigns agg slots and per-problem partial slots (tiles of problem p in this
+// sweep, in line order), fills work lists and uploads from pinned memory.
+void upload_sweep(Alloc& al, Sweep& sw, size_t ext_b);
+
+void launch_sweep(int precision, int inm, const Sweep& sw, ProbState* ps, double* partial,
+                  hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Mesh-pair partition: dividing index + merge-path tile rows at tile size T
+// ---------------------------------------------------------------------------
+struct Part {
+    const double* xr = nullptr;
+    long long R = 0;
+    const double* yc = nullptr;
+    long long C = 0;
+    int* zeta = nullptr;
+    int* trs = nullptr;
+    int T = 0;
+    int ntiles = 0;
+};
+
+Part make_part(Alloc& al, const double* xr, long long R, const double* yc, long long C, int T,
+               hipStream_t s);
+// Reuses an existing dividing index with another tile size.
+Part make_part_like(Alloc& al, const Part& base, int T, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Validation and mass preparation
+// ---------------------------------------------------------------------------
+void enqueue_sorted_check(const double* a, long long n, int* dflag, hipStream_t s);
+void enqueue_log2_mass(const double* a, long long n, double* la, int* dflag, hipStream_t s);
+void enqueue_sum(Alloc& al, const double* a, long long n, double* dsum, hipStream_t s);
+void enqueue_fill(double* a, long long n, double v, hipStream_t s);
+void enqueue_scale(const double* a, double* b, long long n, double f, hipStream_t s);
+
+int map_exception();
+
+}  // namespace finom

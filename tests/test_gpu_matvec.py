@@ -1,0 +1,141 @@
+"""finom_matvec / dense_matvec (HIP) against the FP64 dense oracle.
+
+FINOM is exact: its product equals the dense product up to rounding
+(section 2.3; the paper's tables report plan differences at rounding level).
+Checked element by element at sizes that span several merge-path tiles with a
+ragged tail, on random, tied, duplicated and graded meshes, n != m, and
+eps in {1e-1, 1e-2, 1e-3}; at 2^20 on sampled rows.
+"""
+import numpy as np
+import pytest
+
+from oracle import clib, dense
+from paper_2605_26659_amd import workloads as wl
+
+from gpuhelp import TOL_F32, TOL_F64, dev, host, rand_meshes, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "random": lambda: rand_meshes(1, 3001, 2777),
+    "ties": lambda: rand_meshes(2, 2500, 2500, ties=True),
+    "dups": lambda: rand_meshes(3, 2049, 1500, dup=True),
+    "n>>m": lambda: rand_meshes(4, 5000, 37),
+    "n<<m": lambda: rand_meshes(5, 41, 5003),
+    "graded": lambda: (wl.mesh_square_law(4100), wl.mesh_chebyshev(3900)),
+    "one-tile": lambda: rand_meshes(6, 300, 200),
+}
+
+
+def _potentials(m, eps, seed=0):
+    rng = np.random.default_rng(seed)
+    return eps * rng.normal(0.0, 25.0, m)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 1e-3])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_finom_matvec_log_domain(case, eps, precision):
+    from paper_2605_26659_amd import finom_matvec
+    x, y = CASES[case]()
+    g = _potentials(len(y), eps)
+    want = clib.dense_logmatvec(x, y, g, eps)
+    got = host(finom_matvec(dev(x), dev(y), eps, dev(g), domain=1, precision=precision))
+    err = np.max(np.abs(got - want)) / eps
+    assert err <= (TOL_F64 if precision == 0 else TOL_F32), err
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_finom_matvec_linear_domain(precision):
+    from paper_2605_26659_amd import finom_matvec
+    x, y = rand_meshes(7, 1500, 1700)
+    eps = 0.05
+    psi = np.random.default_rng(1).uniform(0.0, 2.0, len(y))
+    psi[::7] = 0.0                       # zeros are allowed in the linear domain
+    want = dense.matvec(x, y, psi, eps)
+    got = host(finom_matvec(dev(x), dev(y), eps, dev(psi), domain=0, precision=precision))
+    rel = np.max(np.abs(got - want) / want)
+    assert rel <= (TOL_F64 if precision == 0 else TOL_F32), rel
+
+
+def test_transpose_is_the_swapped_call():
+    from paper_2605_26659_amd import finom_matvec
+    x, y = rand_meshes(8, 900, 1300)
+    eps = 0.02
+    phi = np.random.default_rng(2).uniform(0.1, 1.0, len(x))
+    want = dense.kernel_matrix(x, y, eps).T @ phi
+    got = host(finom_matvec(dev(y), dev(x), eps, dev(phi), domain=0))
+    assert np.max(np.abs(got - want) / want) <= TOL_F64
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dense_matvec_matches_oracle(precision):
+    from paper_2605_26659_amd import dense_matvec
+    x, y = rand_meshes(9, 2000, 1800, ties=True)
+    eps = 0.01
+    g = _potentials(len(y), eps, 3)
+    want = clib.dense_logmatvec(x, y, g, eps)
+    got = host(dense_matvec(dev(x), dev(y), eps, dev(g), domain=1, precision=precision))
+    assert np.max(np.abs(got - want)) / eps <= (TOL_F64 if precision == 0 else TOL_F32)
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (1, 5000), (5000, 1), (2, 3)])
+def test_degenerate_sizes(n, m):
+    from paper_2605_26659_amd import finom_matvec
+    x, y = rand_meshes(10, n, m)
+    g = _potentials(m, 0.01, 4)
+    want = dense.logmatvec(x, y, g, 0.01)
+    got = host(finom_matvec(dev(x), dev(y), 0.01, dev(g), domain=1))
+    assert np.max(np.abs(got - want)) / 0.01 <= TOL_F64
+
+
+def test_minus_infinity_inputs_are_zero_mass():
+    from paper_2605_26659_amd import finom_matvec
+    x, y = rand_meshes(11, 700, 900)
+    g = _potentials(900, 0.02, 5)
+    g[100:400] = -np.inf
+    want = dense.logmatvec(x, y, g, 0.02)
+    got = host(finom_matvec(dev(x), dev(y), 0.02, dev(g), domain=1))
+    assert np.max(np.abs(got - want)) / 0.02 <= TOL_F64
+
+
+def test_error_paths():
+    from paper_2605_26659_amd import FINOM_E_ARG, FINOM_E_UNSORTED, FinomError, finom_matvec
+    torch = torch_cuda()
+    x, y = rand_meshes(12, 100, 100)
+    g = np.zeros(100)
+    xb = x.copy()
+    xb[50], xb[51] = xb[51], xb[50] + 1e-3
+    with pytest.raises(FinomError) as e:
+        finom_matvec(dev(xb), dev(y), 0.1, dev(g), domain=1)
+    assert e.value.status == FINOM_E_UNSORTED
+    xn = x.copy(); xn[3] = np.nan
+    with pytest.raises(FinomError) as e:
+        finom_matvec(dev(xn), dev(y), 0.1, dev(g), domain=1)
+    assert e.value.status == FINOM_E_UNSORTED
+    with pytest.raises(FinomError) as e:
+        finom_matvec(dev(x), dev(y), -1.0, dev(g), domain=1)
+    assert e.value.status == FINOM_E_ARG
+    with pytest.raises(FinomError) as e:
+        finom_matvec(dev(x), dev(y), 0.1, dev(g), domain=3)
+    assert e.value.status == FINOM_E_ARG
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_full_size_graded_sampled_rows(eps, precision):
+    """n = m = 2^20 graded meshes (the throughput workload): sampled rows
+    against the dense definition, computed row by row on the CPU."""
+    from paper_2605_26659_amd import finom_matvec
+    p = wl.config_graded_1d(1 << 20, eps)
+    rng = np.random.default_rng(77)
+    g = eps * np.log(p.v) + eps * rng.normal(0, 3.0, len(p.y))
+    got = host(finom_matvec(dev(p.x), dev(p.y), eps, dev(g), domain=1, precision=precision))
+    rows = np.unique(np.concatenate([rng.integers(0, len(p.x), 48), [0, 1, len(p.x) - 1],
+                                     np.arange(4095, 4100)]))
+    want = clib.dense_logmatvec(p.x, p.y, g, eps, rows=rows)
+    err = np.max(np.abs(got[rows] - want)) / eps
+    # The oracle adds 2^20 FP64 terms left to right: its own rounding error
+    # grows like sqrt(m) * 2^-53 per term magnitude, ~1e-12 here; the bound is
+    # four times that.
+    assert err <= (4e-12 if precision == 0 else TOL_F32), err
