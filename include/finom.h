@@ -108,6 +108,24 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m,
                    int64_t itr_max, const finom_opts* opts, double* f_out,
                    double* g_out, finom_result* res, void* stream);
 
+/*
+ * Algorithm 2 (2D FINOM Sinkhorn) on tensor-product meshes: source grid
+ * x1 (n1) x y1 (m1), target grid x2 (n2) x y2 (m2), cost |dx| + |dy|, so
+ * K = K_y (x) K_x (eq. 2d-kron). u (n1*m1) and v (n2*m2) are column-major:
+ * element (k, i) at k + i*n1 (the paper's grid order, section 3.1). Each
+ * product is evaluated axis by axis, K^T phi = vec(K_x^T Phi K_y) and
+ * K psi = vec(K_x Psi K_y^T) (eq. 2d-ktphi, eq. 2d-kpsi), with the potentials
+ * absorbed as in the appendix (columns with the right absorption, rows with
+ * the left one). Initialisation Phi = 1/(n1 m1), Psi = 1/(n2 m2); the loop,
+ * the check and the outputs (f_out: n1*m1, g_out: n2*m2, column-major) are as
+ * in sinkhorn_w1_1d. w1 = <|dx| + |dy|, Gamma> in FP64.
+ */
+int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
+                   const double* x2, int64_t n2, const double* y2, int64_t m2,
+                   const double* u, const double* v, double eps, double tol,
+                   int64_t itr_max, const finom_opts* opts, double* f_out,
+                   double* g_out, finom_result* res, void* stream);
+
 /* Human-readable text for a status code (static storage). */
 const char* finom_strerror(int status);
 

@@ -15,11 +15,19 @@
 
 namespace finom {
 
-constexpr int kBlock = 256;
-constexpr int kIptF32 = 8;    // T = 2048 merged elements per tile
-constexpr int kIptF64 = 4;    // T = 1024
-constexpr int kIptCost = 2;   // T = 512, FP64 moment sums (four LDS arrays)
+constexpr int kBlock = 256;     // block size of the setup / utility kernels
 constexpr double kLn2 = 0.69314718055994530942;
+
+// Scan tile shapes: threads per block x columns per thread. T = block * ipt
+// merged elements per tile. The cost sweeps (FP64 moment sums, four LDS
+// arrays) always use kCostCfg.
+struct TileCfg {
+    int block, ipt;
+    int T() const { return block * ipt; }
+};
+constexpr int kNumCfg = 3;
+constexpr TileCfg kCfgs[kNumCfg] = {{256, 4}, {256, 8}, {512, 8}};
+constexpr int kCostBlock = 256, kCostIpt = 2;
 
 struct HipError {
     hipError_t e;
@@ -33,9 +41,13 @@ struct HipError {
 
 inline unsigned blocks_for(long long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 inline int ntiles_for(long long R, long long C, int T) { return (int)((R + C + T - 1) / T); }
-inline int tile_size(int precision) { return kBlock * (precision == 1 ? kIptF32 : kIptF64); }
-inline int cost_tile_size() { return kBlock * kIptCost; }
+inline int cost_tile_size() { return kCostBlock * kCostIpt; }
 inline size_t ext_bytes(int precision) { return precision == 1 ? sizeof(Ext<float>) : sizeof(Ext<double>); }
+
+// Default tile shape for a 1D line of `merged` elements; the autotuner can
+// override it per size class.
+int default_cfg(int precision, long long merged);
+int tuned_cfg(int precision, long long merged);
 
 // ---------------------------------------------------------------------------
 // Workspace: per stream, a list of device blocks and pinned host blocks.
@@ -132,17 +144,22 @@ struct SweepDev {
     const WorkItem* work_multi = nullptr;  // tiles of lines with more than one tile
     int nwork_multi = 0;
     const LineDesc* lines = nullptr;
-    void* agg = nullptr;
-    void* carry = nullptr;
-    unsigned int* line_ctr = nullptr;
+    void* agg = nullptr;                   // tile aggregates this sweep reads
 };
 
 // kind: 0 = scan in the call's precision (plain sums), 1 = FP64 cost tile
 // (plain sums), 2 = FP64 cost tile with moment sums.
+// agg_from_prev: the tile aggregates are written by the previous sweep's
+// epilogue (shared partition), so no aggregate kernel runs.
+// agg_next: where this sweep's epilogue writes the next sweep's aggregates.
 struct Sweep {
     std::vector<LineDesc> lines;
     int kind = 0;
+    int cfg = 1;
     int epi = EPI_STORE_LOG2;
+    bool agg_from_prev = false;
+    void* agg_next = nullptr;
+    void* agg_buf = nullptr;               // preassigned aggregate buffer (optional)
     SweepDev dev;
     int total_tiles() const
     {
@@ -150,7 +167,15 @@ struct Sweep {
         for (auto& l : lines) t += l.ntiles;
         return t;
     }
+    int multi_tiles() const
+    {
+        int t = 0;
+        for (auto& l : lines)
+            if (l.ntiles > 1) t += l.ntiles;
+        return t;
+    }
     int ns() const { return kind == 2 ? 4 : 2; }
+    int T() const { return kind == 0 ? kCfgs[cfg].T() : cost_tile_size(); }
 };
 
 inline LineDesc make_line(const double* xr, long long R, const double* yc, long long C,
@@ -178,7 +203,9 @@ inline LineDesc make_line(const double* xr, long long R, const double* yc, long 
 void upload_sweep(Alloc& al, Sweep& sw, size_t ext_b);
 
 void launch_sweep(int precision, int inm, const Sweep& sw, ProbState* ps, double* partial,
-                  hipStream_t s);
+                  const double* dec, int parity, hipStream_t s);
+// Only the tile-aggregate kernel of a sweep (initial aggregates).
+void launch_aggregate(int precision, int inm, const Sweep& sw, ProbState* ps, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Mesh-pair partition: dividing index + merge-path tile rows at tile size T
@@ -198,6 +225,9 @@ Part make_part(Alloc& al, const double* xr, long long R, const double* yc, long 
                hipStream_t s);
 // Reuses an existing dividing index with another tile size.
 Part make_part_like(Alloc& al, const Part& base, int T, hipStream_t s);
+// The transposed pair (rows yc, columns xr) on the SAME merged-sequence tiles
+// as `base`: its tile t holds base's columns of tile t as rows.
+Part make_part_transposed(Alloc& al, const Part& base, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Validation and mass preparation

@@ -22,8 +22,10 @@
 // of work on graded meshes. A tile stages its column terms in LDS, scans them
 // (per-thread sequential sums, wavefront shuffles, LDS across waves) and then
 // answers its rows. Lines longer than one tile get their carries from the
-// tile-aggregate kernel (k_tile_aggregate), whose last block per line scans
-// the tile totals.
+// tile-aggregate kernel (k_tile_aggregate): every tile block adds up the
+// totals of the tiles before (lower block) and after (upper block) it.
+// No kernel communicates across blocks; data moves only at kernel
+// boundaries.
 #pragma once
 #include "finom_device.hpp"
 #include "finom_types.hpp"
@@ -71,30 +73,65 @@ __device__ __forceinline__ void column_terms(const LineDesc& L, long long j, Ext
     t[0] = ext_exp2<M>(g + y * L.kappa);
     t[1] = ext_exp2<M>(g - y * L.kappa);
     if (MOMENT) {
-        const Ext<M> yy = Ext<M>{frexp_mant((M)y), (y == 0.0) ? kZeroExp : frexp_exp((M)y)};
+        const Ext<M> yy = Ext<M>{(M)y, 0};
         t[2] = ext_mul(t[0], yy);
         t[3] = ext_mul(t[1], yy);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Tile aggregates + per-line carries (only for lines with more than one tile)
+// Stop decision of Algorithm 1's loop head, taken by every block of the first
+// kernel after a checking sweep from that sweep's per-tile partial errors.
+// Every block sums the same partials in the same order, so all blocks reach
+// the same decision; tile 0 of the designated line records it. Returns true
+// when the iteration stops (the caller then skips its work).
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__device__ __forceinline__ bool decide_stop(const LineDesc& L, int tile, ProbState* __restrict__ P,
+                                            const double* __restrict__ partial, int parity,
+                                            double* s_red)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < L.dec_nparts; k += BLOCK) v += partial[L.dec_part_off + k];
+    const double err = block_sum_f64<BLOCK>(v, s_red);
+    const long long l = P->cnt[parity];
+    const bool stop = (l >= P->itr_max) || !(err > P->tol);
+    if (L.writes_state && tile == 0 && threadIdx.x == 0) {
+        P->err = err;
+        if (!(err == err) || err == __builtin_inf()) P->status = 1;
+        if (stop) {
+            P->iters = l;
+            P->converged = (err <= P->tol) ? 1 : 0;
+            P->done = 1;
+        } else {
+            P->cnt[parity ^ 1] = l + 1;
+        }
+    }
+    return stop;
+}
+
+// ---------------------------------------------------------------------------
+// Tile aggregates (lines with more than one tile): the totals of the
+// lower-block and upper-block column terms of each tile.
 // ---------------------------------------------------------------------------
 template <typename M, int BLOCK, int IPT, int INM, bool MOMENT>
 __global__ __launch_bounds__(BLOCK) void k_tile_aggregate(const WorkItem* __restrict__ work,
                                                          const LineDesc* __restrict__ lines,
-                                                         const ProbState* __restrict__ ps,
+                                                         ProbState* __restrict__ ps,
                                                          Ext<M>* __restrict__ agg,
-                                                         Ext<M>* __restrict__ carry,
-                                                         unsigned int* __restrict__ line_ctr)
+                                                         const double* __restrict__ dec_partial,
+                                                         int parity)
 {
     constexpr int T = BLOCK * IPT;
     constexpr int NS = MOMENT ? 4 : 2;
-    __shared__ Ext<M> s_tmp[2 * (BLOCK / kWave)];
-    __shared__ int s_last;
+    __shared__ Ext<M> s_tmp[BLOCK / kWave];
+    __shared__ double s_red[BLOCK / kWave];
     const WorkItem w = work[blockIdx.x];
     const LineDesc L = lines[w.line];
-    if (ps[L.prob].done) return;
+    ProbState* P = ps + L.prob;
+    if (P->done) return;
+    if (dec_partial && L.dec_part_off >= 0 && decide_stop<BLOCK>(L, w.tile, P, dec_partial, parity, s_red))
+        return;
     const TileGeom<double> tg = tile_geom(L, w.tile, T);
     const long long nc = tg.c1 - tg.c0;
 
@@ -108,104 +145,40 @@ __global__ __launch_bounds__(BLOCK) void k_tile_aggregate(const WorkItem* __rest
         for (int s = 0; s < NS; ++s) acc[s] = ext_add(acc[s], t[s]);
     }
 #pragma unroll
-    for (int s = 0; s < NS; s += 2) {
-        Ext<M> el, eu, tl, tu;
-        block_scan_both<M, BLOCK>(acc[s], acc[s + 1], el, eu, tl, tu, s_tmp);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            agg[(long long)(L.agg_base + w.tile) * NS + s] = tl;
-            agg[(long long)(L.agg_base + w.tile) * NS + s + 1] = tu;
-        }
-    }
-    // Last block of this line turns the tile totals into carries:
-    // lower-block carry = sum over earlier tiles, upper = sum over later tiles.
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int prev = atomicAdd(line_ctr + w.line, 1u);
-        s_last = (prev + 1 == (unsigned int)L.ntiles);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const int G = L.ntiles;
-#pragma unroll
-    for (int s = 0; s < NS; s += 2) {
-        Ext<M> run_l = ext_zero<M>(), run_u = ext_zero<M>();
-        const int nchunks = (G + BLOCK - 1) / BLOCK;
-        for (int c = 0; c < nchunks; ++c) {
-            // forward chunk c for L, backward chunk (nchunks-1-c) for U
-            const int tl_i = c * BLOCK + threadIdx.x;
-            const int cu = nchunks - 1 - c;
-            const int tu_i = cu * BLOCK + threadIdx.x;
-            const Ext<M> vl = (tl_i < G) ? agg[(long long)(L.agg_base + tl_i) * NS + s] : ext_zero<M>();
-            const Ext<M> vu = (tu_i < G) ? agg[(long long)(L.agg_base + tu_i) * NS + s + 1] : ext_zero<M>();
-            Ext<M> el, eu, totl, totu;
-            block_scan_both<M, BLOCK>(vl, vu, el, eu, totl, totu, s_tmp);
-            __syncthreads();
-            if (tl_i < G) carry[(long long)(L.agg_base + tl_i) * NS + s] = ext_add(run_l, el);
-            if (tu_i < G) carry[(long long)(L.agg_base + tu_i) * NS + s + 1] = ext_add(eu, run_u);
-            run_l = ext_add(run_l, totl);
-            run_u = ext_add(run_u, totu);
-        }
-    }
-    if (threadIdx.x == 0) line_ctr[w.line] = 0u;
-}
-
-// ---------------------------------------------------------------------------
-// Per-problem reduction of block partials by the last block to finish.
-// ---------------------------------------------------------------------------
-template <int BLOCK, int EPI>
-__device__ __forceinline__ void finish_problem(ProbState* __restrict__ P, double* __restrict__ partial,
-                                               int part_off, int nparts, int slot,
-                                               double block_value, double* s_red, int* s_last)
-{
-    if (threadIdx.x == 0) partial[slot] = block_value;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int prev = atomicAdd(&P->counter, 1u);
-        *s_last = (prev + 1 == (unsigned int)nparts);
-    }
-    __syncthreads();
-    if (!*s_last) return;
-    __threadfence();
-    double v = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += BLOCK) v += partial[part_off + k];
-    v = block_sum_f64<BLOCK>(v, s_red);
-    if (threadIdx.x == 0) {
-        if (EPI == EPI_UPDATE_CHECK) {
-            P->err = v;
-            if (!(v == v) || v == __builtin_inf()) P->status = 1;
-            if (P->iters >= P->itr_max || !(v > P->tol)) {
-                P->done = 1;
-                P->converged = (v <= P->tol) ? 1 : 0;
-            } else {
-                P->iters += 1;
-            }
-        } else {
-            P->w1 = v;
-        }
-        P->counter = 0u;
+    for (int s = 0; s < NS; ++s) {
+        const Ext<M> tot = block_sum_ext<M, BLOCK>(acc[s], s_tmp);
+        if (threadIdx.x == 0) agg[(long long)(L.agg_base + w.tile) * NS + s] = tot;
     }
 }
 
 // ---------------------------------------------------------------------------
-// The tile sweep: column terms -> LDS scan -> rows query at zeta -> epilogue
+// The tile sweep. All global loads of a tile (its columns, its rows, the tile
+// aggregates for the carries, the partials of a pending stop decision) are
+// issued first, so one memory latency covers the block; then column terms ->
+// LDS -> blocked scan -> rows query at zeta -> epilogue. With NEXT_AGG the
+// update epilogue also forms the next sweep's tile aggregates from the
+// potentials it has just written: the next sweep uses the same merge-path
+// partition, so its tile t has exactly this tile's rows as columns.
 // ---------------------------------------------------------------------------
-template <typename M, int BLOCK, int IPT, int INM, int EPI, bool MOMENT>
+template <typename M, int BLOCK, int IPT, int INM, int EPI, bool MOMENT, bool NEXT_AGG>
 __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ work,
                                                 const LineDesc* __restrict__ lines,
                                                 ProbState* __restrict__ ps,
-                                                const Ext<M>* __restrict__ carry,
-                                                double* __restrict__ partial)
+                                                const Ext<M>* __restrict__ agg,
+                                                double* __restrict__ partial,
+                                                const double* __restrict__ dec_partial,
+                                                int parity, Ext<M>* __restrict__ agg_next)
 {
     constexpr int T = BLOCK * IPT;
     constexpr int NS = MOMENT ? 4 : 2;
+    constexpr int NW = BLOCK / kWave;
+    constexpr bool CHECK = (EPI == EPI_UPDATE_CHECK);
+    // log2-unit inputs are finite potentials; other input modes may carry
+    // -inf (zero mass) and need the guarded exponential
+    constexpr bool GUARD = (INM != IN_LOG2);
     __shared__ Ext<M> s_sum[NS][T + 1];
-    __shared__ Ext<M> s_tmp[2 * (BLOCK / kWave)];
-    __shared__ double s_red[BLOCK / kWave];
-    __shared__ int s_last;
+    __shared__ Ext<M> s_tmp[(NS + 2) * NW];
+    __shared__ double s_red[NW];
 
     const WorkItem w = work[blockIdx.x];
     const LineDesc L = lines[w.line];
@@ -214,67 +187,154 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
     const TileGeom<double> tg = tile_geom(L, w.tile, T);
     const int nc = (int)(tg.c1 - tg.c0);
     const int nr = (int)(tg.r1 - tg.r0);
+    const int ncq = (nc + BLOCK - 1) / BLOCK;   // column slots per thread (block-uniform)
+    const int nrq = (nr + BLOCK - 1) / BLOCK;   // row slots per thread (block-uniform)
+    const bool decide = dec_partial && L.dec_part_off >= 0;
 
-    // 1. column terms, striped (coalesced) loads, staged in LDS
-    for (int k = threadIdx.x; k < nc; k += BLOCK) {
-        Ext<M> t[NS];
-        column_terms<M, INM, MOMENT>(L, tg.c0 + k, t);
+    // ---- A. issue every load of the tile (tail lanes re-read an in-range element)
+    double gq[IPT], yq[IPT], xq[IPT], a0q[IPT], dq[IPT];
+    M vq[IPT];
+    int zq[IPT];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) s_sum[s][k] = t[s];
+    for (int q = 0; q < IPT; ++q) {
+        if (q >= ncq) break;
+        const long long j = tg.c0 + min((int)threadIdx.x + q * BLOCK, nc - 1);
+        gq[q] = load_in<INM>(L.gin + j * L.gstride, L.in_scale);
+        yq[q] = L.yc[j];
+    }
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (q >= nrq) break;
+        const long long i = tg.r0 + min((int)threadIdx.x + q * BLOCK, nr - 1);
+        xq[q] = L.xr[i];
+        zq[q] = L.zeta[i];
+        if (EPI == EPI_UPDATE || CHECK || EPI == EPI_COST) a0q[q] = L.a0[i * L.ostride];
+    }
+    Ext<M> cr[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) cr[s] = ext_zero<M>();
+    if (L.ntiles > 1) {
+        for (int t = threadIdx.x; t < L.ntiles; t += BLOCK) {
+            const Ext<M>* a = agg + (long long)(L.agg_base + t) * NS;
+            if (t < w.tile) {
+                cr[0] = ext_add(cr[0], a[0]);
+                if (MOMENT) cr[2] = ext_add(cr[2], a[2]);
+            } else if (t > w.tile) {
+                cr[1] = ext_add(cr[1], a[1]);
+                if (MOMENT) cr[3] = ext_add(cr[3], a[3]);
+            }
+        }
+    }
+    double dv = 0.0;
+    if (decide)
+        for (int k = threadIdx.x; k < L.dec_nparts; k += BLOCK) dv += dec_partial[L.dec_part_off + k];
+
+    // ---- B. stop decision of the loop head (uniform across the block)
+    if (decide) {
+        const double err = block_sum_f64<BLOCK>(dv, s_red);
+        const long long l = P->cnt[parity];
+        const bool stop = (l >= P->itr_max) || !(err > P->tol);
+        if (L.writes_state && w.tile == 0 && threadIdx.x == 0) {
+            P->err = err;
+            if (!(err == err) || err == __builtin_inf()) P->status = 1;
+            if (stop) {
+                P->iters = l;
+                P->converged = (err <= P->tol) ? 1 : 0;
+                P->done = 1;
+            } else {
+                P->cnt[parity ^ 1] = l + 1;
+            }
+        }
+        if (stop) return;
+    }
+
+    // ---- C. column terms to LDS (striped), carries reduced across the block
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (q >= ncq) break;
+        const int k = threadIdx.x + q * BLOCK;
+        const double y = yq[q] - L.shift;
+        const Ext<M> tl = GUARD ? ext_exp2<M>(gq[q] + y * L.kappa) : ext_exp2_fast<M>(gq[q] + y * L.kappa);
+        const Ext<M> tu = GUARD ? ext_exp2<M>(gq[q] - y * L.kappa) : ext_exp2_fast<M>(gq[q] - y * L.kappa);
+        if (k < nc) {
+            s_sum[0][k] = tl;
+            s_sum[1][k] = tu;
+            if (MOMENT) {
+                const Ext<M> yy = Ext<M>{(M)y, 0};
+                s_sum[2][k] = ext_mul(tl, yy);
+                s_sum[3][k] = ext_mul(tu, yy);
+            }
+        }
+    }
+    if (L.ntiles > 1) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) cr[s] = block_sum_ext<M, BLOCK>(cr[s], s_tmp + s * NW);
+    }
+    // operands of the marginal-error check, needed only by the epilogue: issued
+    // here so that their latency overlaps the scan
+    if (CHECK) {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            if (q >= nrq) break;
+            const long long o = (tg.r0 + min((int)threadIdx.x + q * BLOCK, nr - 1)) * L.ostride;
+            vq[q] = (M)L.a1[o];          // v: weight of the error term
+            dq[q] = L.a2[o] - a0q[q];    // log2 psi_old - log2 v
+        }
     }
     __syncthreads();
 
-    // 2. blocked scan: thread owns columns [tid*IPT, tid*IPT + IPT)
+    // ---- D. blocked scan: thread owns columns [tid*ncq, tid*ncq + ncq)
 #pragma unroll
     for (int s = 0; s < NS; s += 2) {
         Ext<M> vl[IPT], vu[IPT];
         Ext<M> sl = ext_zero<M>(), su = ext_zero<M>();
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
-            const int idx = threadIdx.x * IPT + q;
+            if (q >= ncq) break;
+            const int idx = threadIdx.x * ncq + q;
             vl[q] = (idx < nc) ? s_sum[s][idx] : ext_zero<M>();
             vu[q] = (idx < nc) ? s_sum[s + 1][idx] : ext_zero<M>();
             sl = ext_add(sl, vl[q]);
             su = ext_add(su, vu[q]);
         }
         Ext<M> el, eu, tl, tu;
-        block_scan_both<M, BLOCK>(sl, su, el, eu, tl, tu, s_tmp);
+        block_scan_both<M, BLOCK>(sl, su, el, eu, tl, tu, s_tmp + NS * NW);
         // exclusive prefix (lower block) and inclusive-from suffix (upper block)
         Ext<M> run = el;
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
-            const int idx = threadIdx.x * IPT + q;
+            if (q >= ncq) break;
+            const int idx = threadIdx.x * ncq + q;
             if (idx < nc) s_sum[s][idx] = run;
             run = ext_add(run, vl[q]);
         }
         run = eu;
 #pragma unroll
         for (int q = IPT - 1; q >= 0; --q) {
-            const int idx = threadIdx.x * IPT + q;
+            if (q >= ncq) continue;
+            const int idx = threadIdx.x * ncq + q;
             run = ext_add(run, vu[q]);
             if (idx < nc) s_sum[s + 1][idx] = run;
         }
-        if (threadIdx.x == 0) {
-            s_sum[s][nc] = tl;
-            s_sum[s + 1][nc] = ext_zero<M>();
-        }
+        if (threadIdx.x == BLOCK - 1) s_sum[s][nc] = tl;
+        if (threadIdx.x == 0) s_sum[s + 1][nc] = ext_zero<M>();
         __syncthreads();
     }
 
-    // 3. rows: each queries the column scan at its dividing index
-    Ext<M> cr[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-        cr[s] = (L.ntiles > 1) ? carry[(long long)(L.agg_base + w.tile) * NS + s] : ext_zero<M>();
-
+    // ---- E. rows: each queries the column scan at its dividing index
     double red = 0.0;
-    for (int k = threadIdx.x; k < nr; k += BLOCK) {
-        const long long i = tg.r0 + k;
-        const double x = L.xr[i] - L.shift;
-        int z = L.zeta[i] - (int)tg.c0;
+    Ext<M> nl = ext_zero<M>(), nu = ext_zero<M>();
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (q >= nrq) break;
+        const int k = threadIdx.x + q * BLOCK;
+        const bool live = k < nr;
+        const long long i = tg.r0 + min(k, nr - 1);
+        const double x = xq[q] - L.shift;
+        int z = zq[q] - (int)tg.c0;
         z = min(max(z, 0), nc);
-        const Ext<M> down = ext_exp2<M>(-x * L.kappa);
-        const Ext<M> up = ext_exp2<M>(x * L.kappa);
+        const Ext<M> down = ext_exp2_fast<M>(-x * L.kappa);
+        const Ext<M> up = ext_exp2_fast<M>(x * L.kappa);
         double val;
         if (!MOMENT) {
             const Ext<M> pl = ext_mul(ext_add(cr[0], s_sum[0][z]), down);
@@ -282,8 +342,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
             val = ext_log2(ext_add(pl, qu));
         } else {
             // lower: sum (x - y_j) w_j = x S - SY ; upper: sum (y_j - x) w_j = SY - x S
-            const Ext<M> xx = Ext<M>{frexp_mant((M)x), (x == 0.0) ? kZeroExp : frexp_exp((M)x)};
-            const Ext<M> nx = Ext<M>{-xx.m, xx.e};
+            const Ext<M> xx = Ext<M>{(M)x, 0};
+            const Ext<M> nx = Ext<M>{-xx.m, 0};
             const Ext<M> Sl = ext_add(cr[0], s_sum[0][z]);
             const Ext<M> Su = ext_add(s_sum[1][z], cr[1]);
             const Ext<M> SYl = ext_add(cr[2], s_sum[2][z]);
@@ -295,30 +355,60 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
             val = ext_log2(ext_add(ext_mul(dl, down), ext_mul(du, up)));
         }
         const long long o = i * L.ostride;
+        double pnew = 0.0;
         if (EPI == EPI_STORE_LOG2) {
-            L.out[o] = val;
+            if (live) L.out[o] = val;
         } else if (EPI == EPI_STORE_NAT) {
-            L.out[o] = val * L.out_scale;
+            if (live) L.out[o] = val * L.out_scale;
         } else if (EPI == EPI_STORE_LIN) {
-            L.out[o] = exp2(val);
+            if (live) L.out[o] = exp2(val);
         } else if (EPI == EPI_UPDATE) {
-            L.out[o] = L.a0[o] - val;
-        } else if (EPI == EPI_UPDATE_CHECK) {
+            pnew = a0q[q] - val;
+            if (live) L.out[o] = pnew;
+        } else if (CHECK) {
             // marginal error of the pair checked at the loop head:
-            // |psi_old (K^T phi) - v| = v |2^{g_old + t - log2 v} - 1|
-            const double lv = L.a0[o];
-            const double d = L.a2[o] + val - lv;
-            red += L.a1[o] * fabs(expm1(d * 0.69314718055994530942));
-            L.out[o] = lv - val;
+            // |psi_old (K^T phi) - v| = v |2^{g_old + t - log2 v} - 1|; the
+            // exponent is formed in FP64 (a small difference of large terms
+            // near convergence), the weight and expm1 at the scan precision
+            const double d = dq[q] + val;
+            if (live) red += (double)(vq[q] * fabs(expm1((M)(d * 0.69314718055994530942))));
+            pnew = a0q[q] - val;
+            if (live) L.out[o] = pnew;
         } else if (EPI == EPI_COST) {
-            red += exp2(L.a0[o] + val);
+            if (live) red += exp2(a0q[q] + val);
+        }
+        if (NEXT_AGG) {
+            // column terms of the next sweep, whose columns are these rows
+            if (live) {
+                nl = ext_add(nl, ext_exp2_fast<M>(pnew + x * L.kappa));
+                nu = ext_add(nu, ext_exp2_fast<M>(pnew - x * L.kappa));
+            }
         }
     }
-    if (EPI == EPI_UPDATE_CHECK || EPI == EPI_COST) {
+    if (CHECK || EPI == EPI_COST) {
         const double b = block_sum_f64<BLOCK>(red, s_red);
-        finish_problem<BLOCK, EPI>(P, partial, L.prob_part_off, L.prob_nparts,
-                                   L.part_base + w.tile, b, s_red, &s_last);
+        if (threadIdx.x == 0) partial[L.part_base + w.tile] = b;
     }
+    if (NEXT_AGG && L.ntiles > 1) {
+        nl = block_sum_ext<M, BLOCK>(nl, s_tmp);
+        nu = block_sum_ext<M, BLOCK>(nu, s_tmp + NW);
+        if (threadIdx.x == 0) {
+            agg_next[(long long)(L.agg_base + w.tile) * 2 + 0] = nl;
+            agg_next[(long long)(L.agg_base + w.tile) * 2 + 1] = nu;
+        }
+    }
+}
+
+// Sum of partial slots [off, off + n) into *out (one block).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_reduce_partials(const double* __restrict__ partial, int off,
+                                                          int n, double* __restrict__ out)
+{
+    __shared__ double s_red[BLOCK / kWave];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += BLOCK) v += partial[off + k];
+    v = block_sum_f64<BLOCK>(v, s_red);
+    if (threadIdx.x == 0) *out = v;
 }
 
 }  // namespace finom

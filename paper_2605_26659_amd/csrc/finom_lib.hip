@@ -1,44 +1,21 @@
-// Host side of the FINOM library: argument checks, device setup kernels
-// (sortedness, dividing index, merge-path partition, log masses), workspace,
-// sweep dispatch, the Sinkhorn loop of Algorithm 1 captured in HIP graphs,
-// and the C ABI of include/finom.h.
+// Host side of the FINOM library: device setup kernels (sortedness, dividing
+// index, merge-path partition, log masses), workspace, sweep dispatch, the
+// Sinkhorn loops of Algorithm 1 (1D) and Algorithm 2 (2D) captured in HIP
+// graphs, and the C ABI of include/finom.h.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-#include <cmath>
 #include <cstdio>
-#include <cstring>
-#include <map>
-#include <mutex>
-#include <new>
-#include <vector>
 
 #include "../../include/finom.h"
-#include "finom_kernels.hpp"
+#include "finom_host.hpp"
 
 namespace finom {
-
-constexpr int kBlock = 256;
-constexpr int kIptF32 = 8;    // T = 2048 merged elements per tile
-constexpr int kIptF64 = 4;    // T = 1024
-constexpr int kIptCost = 2;   // T = 512, FP64 moment sums (four LDS arrays)
-constexpr double kLn2 = 0.69314718055994530942;
-
-struct HipError {
-    hipError_t e;
-};
-
-#define HIPCHK(x)                                  \
-    do {                                           \
-        hipError_t _e = (x);                       \
-        if (_e != hipSuccess) throw HipError{_e};  \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // setup kernels
 // ---------------------------------------------------------------------------
 
-// flags[0] |= 1 if a[k] > a[k+1] or a[k] is not finite.
+// flag |= 1 if a[k] > a[k+1] or a[k] is not finite.
 __global__ void k_check_sorted(const double* __restrict__ a, long long n, int* __restrict__ flag)
 {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,7 +26,7 @@ __global__ void k_check_sorted(const double* __restrict__ a, long long n, int* _
     if (bad) atomicOr(flag, 1);
 }
 
-// flags |= 1 if a mass is not > 0 / not finite; writes log2 of it.
+// flag |= 1 if a mass is not > 0 / not finite; writes its log2.
 __global__ void k_log2_mass(const double* __restrict__ a, long long n, double* __restrict__ la,
                             int* __restrict__ flag)
 {
@@ -73,17 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_partial_sum(const double* __restrict
     if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_final_sum(const double* __restrict__ part, int np,
-                                                      double* __restrict__ out)
-{
-    __shared__ double s_red[kBlock / kWave];
-    double v = 0.0;
-    for (int k = threadIdx.x; k < np; k += kBlock) v += part[k];
-    v = block_sum_f64<kBlock>(v, s_red);
-    if (threadIdx.x == 0) *out = v;
-}
-
-// zeta[i] = #{j : y_j <= x_i} (the dividing index of section 2.2, 0-based count)
+// zeta[i] = #{j : y_j <= x_i} (the dividing index of section 2.2, as a count)
 __global__ void k_dividing_index(const double* __restrict__ xr, long long R,
                                  const double* __restrict__ yc, long long C, int* __restrict__ zeta)
 {
@@ -117,6 +84,17 @@ __global__ void k_tile_rows(const int* __restrict__ zeta, long long R, int T, in
         else hi = mid;
     }
     trs[t] = (int)lo;
+}
+
+// rows of the transposed pair before tile t: the columns of the base pair
+__global__ void k_tile_rows_complement(const int* __restrict__ trs, int T, int ntiles, long long total,
+                                       int* __restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    long long d = (long long)t * T;
+    if (d > total) d = total;
+    out[t] = (int)(d - trs[t]);
 }
 
 __global__ void k_fill(double* __restrict__ a, long long n, double v)
@@ -163,263 +141,39 @@ __global__ __launch_bounds__(kBlock) void k_dense(const double* __restrict__ xr,
 }
 
 // ---------------------------------------------------------------------------
-// workspace: one growable device arena and one pinned host arena per stream
+// arenas
 // ---------------------------------------------------------------------------
-struct Arena {
-    char* dev = nullptr;
-    size_t dcap = 0, dused = 0;
-    char* host = nullptr;
-    size_t hcap = 0, hused = 0;
-    hipEvent_t upload_done = nullptr;
-};
-
 static std::mutex g_mu;
 static std::map<void*, Arena*> g_arenas;
 
-static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+Arena* arena_for(void* stream)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_arenas.find(stream);
+    if (it != g_arenas.end()) return it->second;
+    Arena* a = new Arena();
+    g_arenas[stream] = a;
+    return a;
+}
 
-struct Alloc {
-    Arena* a;
-    hipStream_t s;
-    Alloc(void* stream) : s((hipStream_t)stream)
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_arenas.find(stream);
-        if (it == g_arenas.end()) {
-            a = new Arena();
-            g_arenas[stream] = a;
-        } else {
-            a = it->second;
+void arena_release_all()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : g_arenas) {
+        Arena* a = kv.second;
+        if (a->upload_done) {
+            hipEventSynchronize(a->upload_done);
+            hipEventDestroy(a->upload_done);
         }
+        hipStreamSynchronize((hipStream_t)kv.first);
+        for (auto& b : a->dblk) hipFree(b.p);
+        for (auto& b : a->hblk) hipHostFree(b.p);
+        delete a;
     }
-    // Reserve (bytes) of device and host memory for this call; reallocates when
-    // the arena is too small (after the stream has drained).
-    void reserve(size_t dbytes, size_t hbytes)
-    {
-        if (a->upload_done) HIPCHK(hipEventSynchronize(a->upload_done));
-        if (dbytes > a->dcap) {
-            HIPCHK(hipStreamSynchronize(s));
-            if (a->dev) HIPCHK(hipFree(a->dev));
-            a->dev = nullptr;
-            a->dcap = 0;
-            size_t cap = std::max(dbytes, a->dcap * 3 / 2);
-            if (hipMalloc((void**)&a->dev, cap) != hipSuccess) throw std::bad_alloc();
-            a->dcap = cap;
-        }
-        if (hbytes > a->hcap) {
-            HIPCHK(hipStreamSynchronize(s));
-            if (a->host) HIPCHK(hipHostFree(a->host));
-            a->host = nullptr;
-            a->hcap = 0;
-            size_t cap = std::max(hbytes, (size_t)1 << 16);
-            if (hipHostMalloc((void**)&a->host, cap, hipHostMallocDefault) != hipSuccess)
-                throw std::bad_alloc();
-            a->hcap = cap;
-        }
-        if (!a->upload_done) HIPCHK(hipEventCreateWithFlags(&a->upload_done, hipEventDisableTiming));
-        a->dused = 0;
-        a->hused = 0;
-    }
-    template <typename T>
-    T* dev(size_t count)
-    {
-        size_t off = align_up(a->dused, 256);
-        a->dused = off + align_up(sizeof(T) * std::max<size_t>(count, 1), 256);
-        if (a->dused > a->dcap) throw std::bad_alloc();
-        return reinterpret_cast<T*>(a->dev + off);
-    }
-    template <typename T>
-    T* host(size_t count)
-    {
-        size_t off = align_up(a->hused, 64);
-        a->hused = off + align_up(sizeof(T) * std::max<size_t>(count, 1), 64);
-        if (a->hused > a->hcap) throw std::bad_alloc();
-        return reinterpret_cast<T*>(a->host + off);
-    }
-};
-
-// Byte counter used to size the arena before carving it.
-struct Sizer {
-    size_t d = 0, h = 0;
-    template <typename T>
-    void dev(size_t count) { d = align_up(d, 256) + align_up(sizeof(T) * std::max<size_t>(count, 1), 256); }
-    template <typename T>
-    void host(size_t count) { h = align_up(h, 64) + align_up(sizeof(T) * std::max<size_t>(count, 1), 64); }
-};
-
-static unsigned blocks_for(long long n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
-
-static int ntiles_for(long long R, long long C, int T) { return (int)((R + C + T - 1) / T); }
-
-static int tile_size(int precision) { return kBlock * (precision == 1 ? kIptF32 : kIptF64); }
-
-// ---------------------------------------------------------------------------
-// sweep dispatch
-// ---------------------------------------------------------------------------
-struct SweepDev {
-    const WorkItem* work = nullptr;        // all tiles
-    int nwork = 0;
-    const WorkItem* work_multi = nullptr;  // tiles of lines with more than one tile
-    int nwork_multi = 0;
-    const LineDesc* lines = nullptr;
-    void* agg = nullptr;
-    void* carry = nullptr;
-    unsigned int* line_ctr = nullptr;
-};
-
-template <typename M, int IPT, int INM, int EPI, bool MOMENT>
-static void launch_sweep_t(const SweepDev& sw, ProbState* ps, double* partial, hipStream_t s)
-{
-    if (sw.nwork_multi > 0) {
-        hipLaunchKernelGGL((k_tile_aggregate<M, kBlock, IPT, INM, MOMENT>), dim3(sw.nwork_multi),
-                           dim3(kBlock), 0, s, sw.work_multi, sw.lines, ps, (Ext<M>*)sw.agg,
-                           (Ext<M>*)sw.carry, sw.line_ctr);
-    }
-    hipLaunchKernelGGL((k_sweep<M, kBlock, IPT, INM, EPI, MOMENT>), dim3(sw.nwork), dim3(kBlock), 0, s,
-                       sw.work, sw.lines, ps, (const Ext<M>*)sw.carry, partial);
-    HIPCHK(hipGetLastError());
+    g_arenas.clear();
 }
 
-static void launch_sweep(int precision, int inm, int epi, const SweepDev& sw, ProbState* ps,
-                         double* partial, hipStream_t s)
-{
-#define SW(M, IPT, I, E) launch_sweep_t<M, IPT, I, E, false>(sw, ps, partial, s)
-    if (precision == 1) {
-        switch (inm * 16 + epi) {
-            case IN_LOG2 * 16 + EPI_STORE_LOG2: SW(float, kIptF32, IN_LOG2, EPI_STORE_LOG2); return;
-            case IN_LOG2 * 16 + EPI_UPDATE: SW(float, kIptF32, IN_LOG2, EPI_UPDATE); return;
-            case IN_LOG2 * 16 + EPI_UPDATE_CHECK: SW(float, kIptF32, IN_LOG2, EPI_UPDATE_CHECK); return;
-            case IN_NAT * 16 + EPI_STORE_NAT: SW(float, kIptF32, IN_NAT, EPI_STORE_NAT); return;
-            case IN_LIN * 16 + EPI_STORE_LIN: SW(float, kIptF32, IN_LIN, EPI_STORE_LIN); return;
-        }
-    } else {
-        switch (inm * 16 + epi) {
-            case IN_LOG2 * 16 + EPI_STORE_LOG2: SW(double, kIptF64, IN_LOG2, EPI_STORE_LOG2); return;
-            case IN_LOG2 * 16 + EPI_UPDATE: SW(double, kIptF64, IN_LOG2, EPI_UPDATE); return;
-            case IN_LOG2 * 16 + EPI_UPDATE_CHECK: SW(double, kIptF64, IN_LOG2, EPI_UPDATE_CHECK); return;
-            case IN_NAT * 16 + EPI_STORE_NAT: SW(double, kIptF64, IN_NAT, EPI_STORE_NAT); return;
-            case IN_LIN * 16 + EPI_STORE_LIN: SW(double, kIptF64, IN_LIN, EPI_STORE_LIN); return;
-        }
-    }
-#undef SW
-    throw HipError{hipErrorInvalidValue};
-}
-
-static void launch_cost_sweep(int epi, const SweepDev& sw, ProbState* ps, double* partial, hipStream_t s)
-{
-    if (epi == EPI_COST)
-        launch_sweep_t<double, kIptCost, IN_LOG2, EPI_COST, true>(sw, ps, partial, s);
-    else
-        launch_sweep_t<double, kIptCost, IN_LOG2, EPI_STORE_LOG2, true>(sw, ps, partial, s);
-}
-
-// Host-side description of the lines of one sweep, turned into device arrays.
-struct SweepHost {
-    std::vector<LineDesc> lines;
-    int T = 0;
-    int total_tiles() const
-    {
-        int t = 0;
-        for (auto& l : lines) t += l.ntiles;
-        return t;
-    }
-    int multi_tiles() const
-    {
-        int t = 0;
-        for (auto& l : lines)
-            if (l.ntiles > 1) t += l.ntiles;
-        return t;
-    }
-    int max_lines() const { return (int)lines.size(); }
-};
-
-// Sizes the device/host buffers a sweep needs (NS = sums per column).
-static void size_sweep(Sizer& z, const SweepHost& sh, int ns, size_t ext_bytes)
-{
-    z.dev<WorkItem>(sh.total_tiles());
-    z.dev<WorkItem>(sh.multi_tiles());
-    z.dev<LineDesc>(sh.lines.size());
-    z.dev<char>((size_t)sh.multi_tiles() * ns * ext_bytes);
-    z.dev<char>((size_t)sh.multi_tiles() * ns * ext_bytes);
-    z.dev<unsigned int>(sh.lines.size());
-    z.host<WorkItem>(sh.total_tiles());
-    z.host<WorkItem>(sh.multi_tiles());
-    z.host<LineDesc>(sh.lines.size());
-}
-
-// Assigns agg slots, fills work lists, uploads (async, from pinned memory).
-static SweepDev upload_sweep(Alloc& al, SweepHost& sh, int ns, size_t ext_bytes, hipStream_t s)
-{
-    SweepDev d;
-    const int tt = sh.total_tiles(), mt = sh.multi_tiles();
-    WorkItem* hw = al.host<WorkItem>(tt);
-    WorkItem* hm = al.host<WorkItem>(mt);
-    LineDesc* hl = al.host<LineDesc>(sh.lines.size());
-    int k = 0, km = 0, abase = 0;
-    for (size_t li = 0; li < sh.lines.size(); ++li) {
-        LineDesc& L = sh.lines[li];
-        L.agg_base = (L.ntiles > 1) ? abase : 0;
-        if (L.ntiles > 1) abase += L.ntiles;
-        for (int t = 0; t < L.ntiles; ++t) {
-            hw[k++] = WorkItem{(int)li, t};
-            if (L.ntiles > 1) hm[km++] = WorkItem{(int)li, t};
-        }
-        hl[li] = L;
-    }
-    WorkItem* dw = al.dev<WorkItem>(tt);
-    WorkItem* dm = al.dev<WorkItem>(mt);
-    LineDesc* dl = al.dev<LineDesc>(sh.lines.size());
-    void* agg = al.dev<char>((size_t)mt * ns * ext_bytes);
-    void* carry = al.dev<char>((size_t)mt * ns * ext_bytes);
-    unsigned int* ctr = al.dev<unsigned int>(sh.lines.size());
-    HIPCHK(hipMemcpyAsync(dw, hw, sizeof(WorkItem) * std::max(tt, 1), hipMemcpyHostToDevice, s));
-    if (mt > 0) HIPCHK(hipMemcpyAsync(dm, hm, sizeof(WorkItem) * mt, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dl, hl, sizeof(LineDesc) * sh.lines.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned int) * sh.lines.size(), s));
-    d.work = dw;
-    d.nwork = tt;
-    d.work_multi = dm;
-    d.nwork_multi = mt;
-    d.lines = dl;
-    d.agg = agg;
-    d.carry = carry;
-    d.line_ctr = ctr;
-    return d;
-}
-
-static LineDesc make_line(const double* xr, long long R, const double* yc, long long C,
-                          const int* zeta, const int* trs, int T, double eps)
-{
-    LineDesc L;
-    memset(&L, 0, sizeof(L));
-    L.xr = xr;
-    L.yc = yc;
-    L.zeta = zeta;
-    L.trs = trs;
-    L.R = R;
-    L.C = C;
-    L.gstride = 1;
-    L.ostride = 1;
-    L.kappa = 1.0 / (eps * kLn2);
-    L.in_scale = L.kappa;
-    L.out_scale = eps * kLn2;
-    L.shift = 0.0;
-    L.ntiles = ntiles_for(R, C, T);
-    return L;
-}
-
-static void setup_partition(const double* xr, long long R, const double* yc, long long C, int T,
-                            int* zeta, int* trs, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_dividing_index, dim3(blocks_for(R)), dim3(kBlock), 0, s, xr, R, yc, C, zeta);
-    const int nt = ntiles_for(R, C, T);
-    hipLaunchKernelGGL(k_tile_rows, dim3(blocks_for(nt + 1)), dim3(kBlock), 0, s, zeta, R, T, nt, trs);
-    HIPCHK(hipGetLastError());
-}
-
-static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
-static int map_exception()
+int map_exception()
 {
     try {
         throw;
@@ -434,7 +188,406 @@ static int map_exception()
 }
 
 // ---------------------------------------------------------------------------
-// matvec entry points
+// sweeps
+// ---------------------------------------------------------------------------
+void upload_sweep(Alloc& al, Sweep& sw, size_t ext_b)
+{
+    const int ns = sw.ns();
+    const int tt = sw.total_tiles(), mt = sw.multi_tiles();
+    WorkItem* hw = al.host<WorkItem>(tt);
+    WorkItem* hm = al.host<WorkItem>(mt);
+    LineDesc* hl = al.host<LineDesc>(sw.lines.size());
+    int k = 0, km = 0, abase = 0;
+    for (size_t li = 0; li < sw.lines.size(); ++li) {
+        LineDesc& L = sw.lines[li];
+        L.agg_base = (L.ntiles > 1) ? abase : 0;
+        if (L.ntiles > 1) abase += L.ntiles;
+        for (int t = 0; t < L.ntiles; ++t) {
+            hw[k++] = WorkItem{(int)li, t};
+            if (L.ntiles > 1) hm[km++] = WorkItem{(int)li, t};
+        }
+        hl[li] = L;
+    }
+    WorkItem* dw = al.dev<WorkItem>(tt);
+    WorkItem* dm = al.dev<WorkItem>(mt);
+    LineDesc* dl = al.dev<LineDesc>(sw.lines.size());
+    void* agg = sw.agg_buf ? sw.agg_buf : (void*)al.dev<char>((size_t)std::max(mt, 1) * ns * ext_b);
+    HIPCHK(hipMemcpyAsync(dw, hw, sizeof(WorkItem) * tt, hipMemcpyHostToDevice, al.s));
+    if (mt > 0) HIPCHK(hipMemcpyAsync(dm, hm, sizeof(WorkItem) * mt, hipMemcpyHostToDevice, al.s));
+    HIPCHK(hipMemcpyAsync(dl, hl, sizeof(LineDesc) * sw.lines.size(), hipMemcpyHostToDevice, al.s));
+    sw.dev.work = dw;
+    sw.dev.nwork = tt;
+    sw.dev.work_multi = dm;
+    sw.dev.nwork_multi = mt;
+    sw.dev.lines = dl;
+    sw.dev.agg = agg;
+}
+
+template <typename M, int B, int I, int INM, bool MO>
+static void launch_agg_t(const SweepDev& d, ProbState* ps, const double* dec, int parity, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tile_aggregate<M, B, I, INM, MO>), dim3(d.nwork_multi), dim3(B), 0, s,
+                       d.work_multi, d.lines, ps, (Ext<M>*)d.agg, dec, parity);
+}
+
+template <typename M, int B, int I, int INM, int EPI, bool MO, bool NA>
+static void launch_t(const Sweep& sw, ProbState* ps, double* partial, const double* dec, int parity,
+                     bool agg_only, hipStream_t s)
+{
+    const SweepDev& d = sw.dev;
+    if (d.nwork == 0) return;
+    if (d.nwork_multi > 0 && (agg_only || !sw.agg_from_prev)) {
+        launch_agg_t<M, B, I, INM, MO>(d, ps, agg_only ? nullptr : dec, parity, s);
+        if (!agg_only) dec = nullptr;   // the aggregate kernel took the decision
+    }
+    if (!agg_only)
+        hipLaunchKernelGGL((k_sweep<M, B, I, INM, EPI, MO, NA>), dim3(d.nwork), dim3(B), 0, s, d.work,
+                           d.lines, ps, (const Ext<M>*)d.agg, partial, dec, parity, (Ext<M>*)sw.agg_next);
+    HIPCHK(hipGetLastError());
+}
+
+// Sweep variants of the scan path: (input mode, epilogue, next aggregates)
+#define FINOM_VARIANTS(M, B, I)                                                                    \
+    switch (variant) {                                                                              \
+        case 0: launch_t<M, B, I, IN_LOG2, EPI_STORE_LOG2, false, false>(sw, ps, partial, dec, parity, ao, s); return; \
+        case 1: launch_t<M, B, I, IN_LOG2, EPI_UPDATE, false, false>(sw, ps, partial, dec, parity, ao, s); return;     \
+        case 2: launch_t<M, B, I, IN_LOG2, EPI_UPDATE, false, true>(sw, ps, partial, dec, parity, ao, s); return;      \
+        case 3: launch_t<M, B, I, IN_LOG2, EPI_UPDATE_CHECK, false, false>(sw, ps, partial, dec, parity, ao, s); return; \
+        case 4: launch_t<M, B, I, IN_LOG2, EPI_UPDATE_CHECK, false, true>(sw, ps, partial, dec, parity, ao, s); return;  \
+        case 5: launch_t<M, B, I, IN_NAT, EPI_STORE_NAT, false, false>(sw, ps, partial, dec, parity, ao, s); return;   \
+        case 6: launch_t<M, B, I, IN_LIN, EPI_STORE_LIN, false, false>(sw, ps, partial, dec, parity, ao, s); return;   \
+    }
+
+static int variant_of(int inm, int epi, bool next_agg)
+{
+    if (inm == IN_NAT && epi == EPI_STORE_NAT) return 5;
+    if (inm == IN_LIN && epi == EPI_STORE_LIN) return 6;
+    if (inm != IN_LOG2) return -1;
+    switch (epi) {
+        case EPI_STORE_LOG2: return next_agg ? -1 : 0;
+        case EPI_UPDATE: return next_agg ? 2 : 1;
+        case EPI_UPDATE_CHECK: return next_agg ? 4 : 3;
+        default: return -1;
+    }
+}
+
+static void dispatch(int precision, int inm, const Sweep& sw, ProbState* ps, double* partial,
+                     const double* dec, int parity, bool ao, hipStream_t s)
+{
+    if (sw.kind == 2 || sw.kind == 1) {
+        const bool mo = (sw.kind == 2);
+        if (mo && sw.epi == EPI_COST)
+            launch_t<double, kCostBlock, kCostIpt, IN_LOG2, EPI_COST, true, false>(sw, ps, partial, dec, parity, ao, s);
+        else if (mo)
+            launch_t<double, kCostBlock, kCostIpt, IN_LOG2, EPI_STORE_LOG2, true, false>(sw, ps, partial, dec, parity, ao, s);
+        else if (sw.epi == EPI_COST)
+            launch_t<double, kCostBlock, kCostIpt, IN_LOG2, EPI_COST, false, false>(sw, ps, partial, dec, parity, ao, s);
+        else
+            launch_t<double, kCostBlock, kCostIpt, IN_LOG2, EPI_STORE_LOG2, false, false>(sw, ps, partial, dec, parity, ao, s);
+        return;
+    }
+    const int variant = variant_of(inm, sw.epi, sw.agg_next != nullptr);
+    if (variant < 0) throw HipError{hipErrorInvalidValue};
+    if (precision == 1) {
+        switch (sw.cfg) {
+            case 0: FINOM_VARIANTS(float, 256, 4) break;
+            case 1: FINOM_VARIANTS(float, 256, 8) break;
+            case 2: FINOM_VARIANTS(float, 512, 8) break;
+        }
+    } else {
+        switch (sw.cfg) {
+            case 0: FINOM_VARIANTS(double, 256, 4) break;
+            case 1: FINOM_VARIANTS(double, 256, 8) break;
+            case 2: FINOM_VARIANTS(double, 512, 8) break;
+        }
+    }
+    throw HipError{hipErrorInvalidValue};
+}
+#undef FINOM_VARIANTS
+
+void launch_sweep(int precision, int inm, const Sweep& sw, ProbState* ps, double* partial,
+                  const double* dec, int parity, hipStream_t s)
+{
+    dispatch(precision, inm, sw, ps, partial, dec, parity, false, s);
+}
+
+void launch_aggregate(int precision, int inm, const Sweep& sw, ProbState* ps, hipStream_t s)
+{
+    if (sw.dev.nwork_multi == 0) return;
+    dispatch(precision, inm, sw, ps, nullptr, nullptr, 0, true, s);
+}
+
+int tuned_cfg(int precision, long long merged)
+{
+    const char* e = getenv("FINOM_TILE_CFG");
+    if (e && *e) {
+        const int c = atoi(e);
+        if (c >= 0 && c < kNumCfg) return c;
+    }
+    return default_cfg(precision, merged);
+}
+
+int default_cfg(int precision, long long merged)
+{
+    // one tile per line when it fits; otherwise the largest tile (fewest
+    // tiles, one memory latency per block)
+    if (merged <= 1024) return 0;
+    (void)precision;
+    return 1;
+}
+
+// ---------------------------------------------------------------------------
+// partitions and validation
+// ---------------------------------------------------------------------------
+Part make_part(Alloc& al, const double* xr, long long R, const double* yc, long long C, int T,
+               hipStream_t s)
+{
+    Part p;
+    p.xr = xr;
+    p.R = R;
+    p.yc = yc;
+    p.C = C;
+    p.T = T;
+    p.ntiles = ntiles_for(R, C, T);
+    p.zeta = al.dev<int>(R);
+    p.trs = al.dev<int>(p.ntiles + 1);
+    hipLaunchKernelGGL(k_dividing_index, dim3(blocks_for(R)), dim3(kBlock), 0, s, xr, R, yc, C, p.zeta);
+    hipLaunchKernelGGL(k_tile_rows, dim3(blocks_for(p.ntiles + 1)), dim3(kBlock), 0, s, p.zeta, R, T,
+                       p.ntiles, p.trs);
+    HIPCHK(hipGetLastError());
+    return p;
+}
+
+Part make_part_like(Alloc& al, const Part& base, int T, hipStream_t s)
+{
+    Part p = base;
+    p.T = T;
+    p.ntiles = ntiles_for(p.R, p.C, T);
+    p.trs = al.dev<int>(p.ntiles + 1);
+    hipLaunchKernelGGL(k_tile_rows, dim3(blocks_for(p.ntiles + 1)), dim3(kBlock), 0, s, p.zeta, p.R, T,
+                       p.ntiles, p.trs);
+    HIPCHK(hipGetLastError());
+    return p;
+}
+
+Part make_part_transposed(Alloc& al, const Part& base, hipStream_t s)
+{
+    Part p;
+    p.xr = base.yc;
+    p.R = base.C;
+    p.yc = base.xr;
+    p.C = base.R;
+    p.T = base.T;
+    p.ntiles = base.ntiles;
+    p.zeta = al.dev<int>(p.R);
+    p.trs = al.dev<int>(p.ntiles + 1);
+    hipLaunchKernelGGL(k_dividing_index, dim3(blocks_for(p.R)), dim3(kBlock), 0, s, p.xr, p.R, p.yc, p.C,
+                       p.zeta);
+    hipLaunchKernelGGL(k_tile_rows_complement, dim3(blocks_for(p.ntiles + 1)), dim3(kBlock), 0, s, base.trs,
+                       base.T, base.ntiles, base.R + base.C, p.trs);
+    HIPCHK(hipGetLastError());
+    return p;
+}
+
+void enqueue_sorted_check(const double* a, long long n, int* dflag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_sorted, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, dflag);
+}
+
+void enqueue_log2_mass(const double* a, long long n, double* la, int* dflag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_log2_mass, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, la, dflag);
+}
+
+void enqueue_sum(Alloc& al, const double* a, long long n, double* dsum, hipStream_t s)
+{
+    const int nb = 64;
+    double* part = al.dev<double>(nb);
+    hipLaunchKernelGGL(k_partial_sum, dim3(nb), dim3(kBlock), 0, s, a, n, part);
+    hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, part, 0, nb, dsum);
+}
+
+void enqueue_fill(double* a, long long n, double v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, v);
+}
+
+void enqueue_scale(const double* a, double* b, long long n, double f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, b, n, f);
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---------------------------------------------------------------------------
+// the iteration loop: k iterations per captured graph, one state read per graph
+// ---------------------------------------------------------------------------
+struct LoopSpec {
+    std::vector<Sweep*> seq[2];        // sweeps of one iteration, by iteration parity
+    std::vector<bool> decides[2];      // sweep takes the stop decision
+};
+
+static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* partial,
+                    long long itr_max, int k, hipStream_t s, ProbState* hps, finom_result* res)
+{
+    k += (k & 1);   // even, so every replay starts on parity 0
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int st = FINOM_OK;
+    try {
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int it = 0; it < k; ++it) {
+            const int b = it & 1;
+            for (size_t q = 0; q < lp.seq[b].size(); ++q)
+                launch_sweep(precision, IN_LOG2, *lp.seq[b][q], ps, partial,
+                             lp.decides[b][q] ? partial : nullptr, b, cs);
+        }
+        HIPCHK(hipStreamEndCapture(cs, &graph));
+        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPCHK(hipEventCreate(&ev0));
+        HIPCHK(hipEventCreate(&ev1));
+        HIPCHK(hipEventRecord(ev0, s));
+        const long long max_launches = itr_max / k + 2;
+        long long launches = 0;
+        for (;;) {
+            HIPCHK(hipGraphLaunch(exec, s));
+            ++launches;
+            HIPCHK(hipMemcpyAsync(hps, ps, sizeof(ProbState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (hps->done) break;
+            if (launches > max_launches) {   // only if the device state were corrupt
+                st = FINOM_E_HIP;
+                break;
+            }
+        }
+        HIPCHK(hipEventRecord(ev1, s));
+        HIPCHK(hipEventSynchronize(ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+        res->loop_ms = ms;
+    } catch (...) {
+        st = map_exception();
+        if (cs) {
+            hipStreamCaptureStatus cst;
+            if (hipStreamIsCapturing(cs, &cst) == hipSuccess && cst == hipStreamCaptureStatusActive) {
+                hipGraph_t g2 = nullptr;
+                hipStreamEndCapture(cs, &g2);
+                if (g2) hipGraphDestroy(g2);
+            }
+        }
+    }
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (cs) hipStreamDestroy(cs);
+    return st;
+}
+
+static int default_graph_iters(long long points)
+{
+    if (points <= (1 << 14)) return 64;
+    if (points <= (1 << 18)) return 32;
+    return 16;
+}
+
+static void init_state(Alloc& al, ProbState* ps, ProbState* hps, int count, long long itr_max,
+                       double tol)
+{
+    for (int i = 0; i < count; ++i) {
+        memset(hps + i, 0, sizeof(ProbState));
+        hps[i].itr_max = itr_max;
+        hps[i].tol = tol;
+    }
+    HIPCHK(hipMemcpyAsync(ps, hps, count * sizeof(ProbState), hipMemcpyHostToDevice, al.s));
+}
+
+// Reads the validation flags and mass sums; returns a status.
+static int read_checks(Alloc& al, int* dflag, double* dsum)
+{
+    int* hflag = al.host<int>(4);
+    double* hsum = al.host<double>(2);
+    HIPCHK(hipMemcpyAsync(hflag, dflag, 4 * sizeof(int), hipMemcpyDeviceToHost, al.s));
+    HIPCHK(hipMemcpyAsync(hsum, dsum, 2 * sizeof(double), hipMemcpyDeviceToHost, al.s));
+    HIPCHK(hipStreamSynchronize(al.s));
+    if (hflag[0]) return FINOM_E_UNSORTED;
+    if (hflag[1]) return FINOM_E_MASS;
+    if (!(fabs(hsum[0] - hsum[1]) <= 1e-12 * std::max(fabs(hsum[0]), fabs(hsum[1]))))
+        return FINOM_E_MASS;
+    return FINOM_OK;
+}
+
+static void finish_result(finom_result* res, const ProbState& st, double w1)
+{
+    res->w1 = w1;
+    res->marginal_err = st.err;
+    res->iters = st.iters;
+    res->sweeps = 2 * st.iters + 1;
+    res->converged = st.converged;
+}
+
+// Lines of a 2D sweep along the first axis: every column j of an
+// (in_rows x ncols) column-major input is one line.
+static void add_axis0_lines(Sweep& sw, const Part& p, double eps, const double* in, long long in_rows,
+                            double* out, long long out_rows, long long ncols)
+{
+    for (long long j = 0; j < ncols; ++j) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = in + j * in_rows;
+        L.out = out + j * out_rows;
+        L.dec_part_off = -1;
+        sw.lines.push_back(L);
+    }
+}
+
+// Lines along the second axis: every row k of an (nrows x ...) column-major
+// input is one line (stride nrows), written to row k of the output.
+static void add_axis1_lines(Sweep& sw, const Part& p, double eps, const double* in, double* out,
+                            long long nrows, const double* a0, const double* a1, const double* a2)
+{
+    for (long long k = 0; k < nrows; ++k) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = in + k;
+        L.gstride = nrows;
+        L.out = out ? out + k : nullptr;
+        L.ostride = nrows;
+        L.a0 = a0 ? a0 + k : nullptr;
+        L.a1 = a1 ? a1 + k : nullptr;
+        L.a2 = a2 ? a2 + k : nullptr;
+        L.dec_part_off = -1;
+        sw.lines.push_back(L);
+    }
+}
+
+// Partial-slot layout of a checking / cost sweep: consecutive per line.
+static int assign_parts(Sweep& sw, int base)
+{
+    int off = base;
+    for (auto& L : sw.lines) {
+        L.part_base = off;
+        off += L.ntiles;
+    }
+    return off - base;
+}
+
+static void set_decision(Sweep& sw, int off, int n)
+{
+    for (size_t i = 0; i < sw.lines.size(); ++i) {
+        sw.lines[i].dec_part_off = off;
+        sw.lines[i].dec_nparts = n;
+        sw.lines[i].writes_state = (i == 0) ? 1 : 0;
+    }
+}
+
+}  // namespace finom
+
+using namespace finom;
+
+// ---------------------------------------------------------------------------
+// matvec
 // ---------------------------------------------------------------------------
 static int matvec_impl(bool dense, const double* x, int64_t n, const double* y, int64_t m,
                        double eps, const double* in, double* out, const finom_opts* opts,
@@ -450,99 +603,55 @@ static int matvec_impl(bool dense, const double* x, int64_t n, const double* y, 
     hipStream_t s = (hipStream_t)stream;
     try {
         Alloc al(stream);
-        const int T = tile_size(o.precision);
-        SweepHost sh;
-        sh.T = T;
-        sh.lines.push_back(make_line(x, n, y, m, nullptr, nullptr, T, eps));
-        const size_t eb = (o.precision == 1) ? sizeof(Ext<float>) : sizeof(Ext<double>);
-        Sizer z;
-        z.dev<int>(2);
-        z.dev<int>(n);
-        z.dev<int>(sh.lines[0].ntiles + 1);
-        z.dev<ProbState>(1);
-        z.host<int>(2);
-        size_sweep(z, sh, 2, eb);
-        al.reserve(z.d, z.h);
-        int* dflag = al.dev<int>(2);
-        int* zeta = al.dev<int>(n);
-        int* trs = al.dev<int>(sh.lines[0].ntiles + 1);
-        ProbState* ps = al.dev<ProbState>(1);
         if (!o.skip_checks) {
-            int* hflag = al.host<int>(2);
-            HIPCHK(hipMemsetAsync(dflag, 0, 2 * sizeof(int), s));
-            hipLaunchKernelGGL(k_check_sorted, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, (long long)n, dflag);
-            hipLaunchKernelGGL(k_check_sorted, dim3(blocks_for(m)), dim3(kBlock), 0, s, y, (long long)m, dflag);
-            HIPCHK(hipMemcpyAsync(hflag, dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            int* dflag = al.dev<int>(1);
+            int* hflag = al.host<int>(1);
+            HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), s));
+            enqueue_sorted_check(x, n, dflag, s);
+            enqueue_sorted_check(y, m, dflag, s);
+            HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             if (hflag[0]) return FINOM_E_UNSORTED;
         }
         const int inm = (o.domain == 1) ? IN_NAT : IN_LIN;
+        const double kappa = 1.0 / (eps * kLn2);
         if (dense) {
-            const double kappa = 1.0 / (eps * kLn2);
+#define DK(M, I, LIN)                                                                               \
+    hipLaunchKernelGGL((k_dense<M, I>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, (long long)n, y, \
+                       (long long)m, in, kappa, kappa, eps * kLn2, LIN, out)
             if (o.precision == 1) {
-                if (inm == IN_NAT)
-                    hipLaunchKernelGGL((k_dense<float, IN_NAT>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, (long long)n, y,
-                                       (long long)m, in, kappa, kappa, eps * kLn2, 0, out);
-                else
-                    hipLaunchKernelGGL((k_dense<float, IN_LIN>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, (long long)n, y,
-                                       (long long)m, in, kappa, kappa, eps * kLn2, 1, out);
+                if (inm == IN_NAT) DK(float, IN_NAT, 0);
+                else DK(float, IN_LIN, 1);
             } else {
-                if (inm == IN_NAT)
-                    hipLaunchKernelGGL((k_dense<double, IN_NAT>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, (long long)n, y,
-                                       (long long)m, in, kappa, kappa, eps * kLn2, 0, out);
-                else
-                    hipLaunchKernelGGL((k_dense<double, IN_LIN>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, (long long)n, y,
-                                       (long long)m, in, kappa, kappa, eps * kLn2, 1, out);
+                if (inm == IN_NAT) DK(double, IN_NAT, 0);
+                else DK(double, IN_LIN, 1);
             }
+#undef DK
             HIPCHK(hipGetLastError());
             return FINOM_OK;
         }
-        setup_partition(x, n, y, m, T, zeta, trs, s);
-        LineDesc& L = sh.lines[0];
-        L.zeta = zeta;
-        L.trs = trs;
+        const int cfg = tuned_cfg(o.precision, n + m);
+        const int T = kCfgs[cfg].T();
+        Part p = make_part(al, x, n, y, m, T, s);
+        ProbState* ps = al.dev<ProbState>(1);
+        HIPCHK(hipMemsetAsync(ps, 0, sizeof(ProbState), s));
+        Sweep sw;
+        sw.kind = 0;
+        sw.cfg = cfg;
+        sw.epi = (o.domain == 1) ? EPI_STORE_NAT : EPI_STORE_LIN;
+        LineDesc L = make_line(x, n, y, m, p.zeta, p.trs, T, eps);
         L.gin = in;
         L.out = out;
-        HIPCHK(hipMemsetAsync(ps, 0, sizeof(ProbState), s));
-        SweepDev sw = upload_sweep(al, sh, 2, eb, s);
-        HIPCHK(hipEventRecord(al.a->upload_done, s));
-        launch_sweep(o.precision, inm, (o.domain == 1) ? EPI_STORE_NAT : EPI_STORE_LIN, sw, ps, nullptr, s);
+        L.dec_part_off = -1;
+        sw.lines.push_back(L);
+        upload_sweep(al, sw, ext_bytes(o.precision));
+        al.uploaded();
+        launch_sweep(o.precision, inm, sw, ps, nullptr, nullptr, 0, s);
         return FINOM_OK;
     } catch (...) {
         return map_exception();
     }
 }
-
-// ---------------------------------------------------------------------------
-// 1D Sinkhorn (Algorithm 1)
-// ---------------------------------------------------------------------------
-
-// Checks masses (> 0, finite), writes log2 masses, returns |sum u - sum v| test
-// through the host flag block. Sums are reduced deterministically.
-struct MassCheck {
-    double* dsum;   // 2 doubles
-    double* part;   // 2 * nb doubles
-    int nb;
-};
-
-static void enqueue_mass(const double* a, long long n, double* la, int* dflag, double* part,
-                         int nb, double* dsum, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_log2_mass, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, la, dflag);
-    hipLaunchKernelGGL(k_partial_sum, dim3(nb), dim3(kBlock), 0, s, a, n, part);
-    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, s, part, nb, dsum);
-}
-
-static int default_graph_iters(long long points)
-{
-    if (points <= (1 << 14)) return 64;
-    if (points <= (1 << 18)) return 32;
-    return 16;
-}
-
-}  // namespace finom
-
-using namespace finom;
 
 extern "C" {
 
@@ -558,6 +667,9 @@ int dense_matvec(const double* x_rows, int64_t n, const double* y_cols, int64_t 
     return matvec_impl(true, x_rows, n, y_cols, m, eps, in, out, opts, stream);
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 1
+// ---------------------------------------------------------------------------
 int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const double* u,
                    const double* v, double eps, double tol, int64_t itr_max, const finom_opts* opts,
                    double* f_out, double* g_out, finom_result* res, void* stream)
@@ -578,194 +690,253 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
     hipStream_t s = (hipStream_t)stream;
     try {
         Alloc al(stream);
-        const int T = tile_size(o.precision);
-        const int Tc = kBlock * kIptCost;
-        const size_t eb = (o.precision == 1) ? sizeof(Ext<float>) : sizeof(Ext<double>);
-        const size_t ebc = sizeof(Ext<double>);
-        const int nt_kt = ntiles_for(m, n, T), nt_k = ntiles_for(n, m, T), nt_c = ntiles_for(n, m, Tc);
-        const int nb = 64;
+        const int cfg = tuned_cfg(o.precision, n + m);
+        const int T = kCfgs[cfg].T();
+        const size_t eb = ext_bytes(o.precision);
 
-        // lines: K^T phi (rows y, cols x, reads F, updates G with the check),
-        //        K psi (rows x, cols y, reads G, updates F), cost (rows x, cols y)
-        SweepHost kt[2], kk[2], kc;
-        for (int b = 0; b < 2; ++b) {
-            kt[b].lines.push_back(make_line(y, m, x, n, nullptr, nullptr, T, eps));
-            kk[b].lines.push_back(make_line(x, n, y, m, nullptr, nullptr, T, eps));
-        }
-        kc.lines.push_back(make_line(x, n, y, m, nullptr, nullptr, Tc, eps));
-
-        Sizer z;
-        z.dev<int>(4);
-        z.dev<int>(n);
-        z.dev<int>(m);
-        z.dev<int>(nt_k + 1);
-        z.dev<int>(nt_kt + 1);
-        z.dev<int>(nt_c + 1);
-        z.dev<double>(n);
-        z.dev<double>(m);
-        z.dev<double>(n);
-        z.dev<double>(m);
-        z.dev<double>(m);
-        z.dev<double>(std::max(nt_kt, nt_c));
-        z.dev<double>(2);
-        z.dev<double>(2 * nb);
-        z.dev<ProbState>(2);
-        for (int b = 0; b < 2; ++b) {
-            size_sweep(z, kt[b], 2, eb);
-            size_sweep(z, kk[b], 2, eb);
-        }
-        size_sweep(z, kc, 4, ebc);
-        z.host<ProbState>(2);
-        z.host<int>(4);
-        z.host<double>(2);
-        al.reserve(z.d, z.h);
-
+        // validation and log masses
         int* dflag = al.dev<int>(4);
-        int* zx = al.dev<int>(n);
-        int* zy = al.dev<int>(m);
-        int* tx = al.dev<int>(nt_k + 1);
-        int* ty = al.dev<int>(nt_kt + 1);
-        int* tc = al.dev<int>(nt_c + 1);
+        double* dsum = al.dev<double>(2);
         double* lu = al.dev<double>(n);
         double* lv = al.dev<double>(m);
-        double* F = al.dev<double>(n);
-        double* G[2] = {al.dev<double>(m), al.dev<double>(m)};
-        double* partial = al.dev<double>(std::max(nt_kt, nt_c));
-        double* dsum = al.dev<double>(2);
-        double* mpart = al.dev<double>(2 * nb);
-        ProbState* ps = al.dev<ProbState>(2);      // [0] iteration, [1] cost reduction
-        ProbState* hps = al.host<ProbState>(2);
-        int* hflag = al.host<int>(4);
-        double* hsum = al.host<double>(2);
-
-        // --- validation (device) and setup
         HIPCHK(hipMemsetAsync(dflag, 0, 4 * sizeof(int), s));
         if (!o.skip_checks) {
-            hipLaunchKernelGGL(k_check_sorted, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, (long long)n, dflag);
-            hipLaunchKernelGGL(k_check_sorted, dim3(blocks_for(m)), dim3(kBlock), 0, s, y, (long long)m, dflag);
+            enqueue_sorted_check(x, n, dflag, s);
+            enqueue_sorted_check(y, m, dflag, s);
         }
-        enqueue_mass(u, n, lu, dflag + 1, mpart, nb, dsum, s);
-        enqueue_mass(v, m, lv, dflag + 1, mpart + nb, nb, dsum + 1, s);
+        enqueue_log2_mass(u, n, lu, dflag + 1, s);
+        enqueue_log2_mass(v, m, lv, dflag + 1, s);
+        enqueue_sum(al, u, n, dsum, s);
+        enqueue_sum(al, v, m, dsum + 1, s);
         if (!o.skip_checks) {
-            HIPCHK(hipMemcpyAsync(hflag, dflag, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(hsum, dsum, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (hflag[0]) return fail(FINOM_E_UNSORTED);
-            if (hflag[1]) return fail(FINOM_E_MASS);
-            if (!(fabs(hsum[0] - hsum[1]) <= 1e-12 * std::max(fabs(hsum[0]), fabs(hsum[1]))))
-                return fail(FINOM_E_MASS);
+            const int st = read_checks(al, dflag, dsum);
+            if (st != FINOM_OK) return fail(st);
         }
-        setup_partition(x, n, y, m, T, zx, tx, s);
-        setup_partition(y, m, x, n, T, zy, ty, s);
-        hipLaunchKernelGGL(k_tile_rows, dim3(blocks_for(nt_c + 1)), dim3(kBlock), 0, s, zx, (long long)n, Tc, nt_c, tc);
-        // Algorithm 1 initialisation: phi = 1/n, psi = 1/m (log2 units)
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, F, (long long)n, -log2((double)n));
-        hipLaunchKernelGGL(k_fill, dim3(blocks_for(m)), dim3(kBlock), 0, s, G[0], (long long)m, -log2((double)m));
-        HIPCHK(hipGetLastError());
-        ProbState init;
-        memset(&init, 0, sizeof(init));
-        init.itr_max = itr_max;
-        init.tol = tol;
-        hps[0] = init;
-        memset(hps + 1, 0, sizeof(ProbState));
-        HIPCHK(hipMemcpyAsync(ps, hps, 2 * sizeof(ProbState), hipMemcpyHostToDevice, s));
 
-        // sweeps; buffer b: G[b] is the old psi, G[1-b] the new one
-        SweepDev dkt[2], dk[2];
+        // dividing indices (Algorithm 1, first step) on one merge-path
+        // partition shared by both products
+        const Part pk = make_part(al, x, n, y, m, T, s);      // K psi:   rows x, columns y
+        const Part pkt = make_part_transposed(al, pk, s);     // K^T phi: rows y, columns x
+        const Part pc = make_part_like(al, pk, cost_tile_size(), s);
+
+        // state: phi = 1/n, psi = 1/m (log2 units)
+        double* F = al.dev<double>(n);
+        double* G[2] = {al.dev<double>(m), al.dev<double>(m)};
+        enqueue_fill(F, n, -log2((double)n), s);
+        enqueue_fill(G[0], m, -log2((double)m), s);
+        ProbState* ps = al.dev<ProbState>(2);      // [0] iteration, [1] cost
+        ProbState* hps = al.host<ProbState>(2);
+        init_state(al, ps, hps, 2, itr_max, tol);
+        const int nparts = std::max(pkt.ntiles, pc.ntiles);
+        double* partial = al.dev<double>(nparts);
+        // tile aggregates: each product's epilogue writes the other's
+        const bool multi = pk.ntiles > 1;
+        void* agg_k = multi ? (void*)al.dev<char>((size_t)pk.ntiles * 2 * eb) : nullptr;
+        void* agg_kt = multi ? (void*)al.dev<char>((size_t)pk.ntiles * 2 * eb) : nullptr;
+
+        Sweep kt[2], kk[2];
         for (int b = 0; b < 2; ++b) {
-            LineDesc& a = kt[b].lines[0];
-            a.zeta = zy; a.trs = ty; a.gin = F; a.out = G[1 - b];
-            a.a0 = lv; a.a1 = v; a.a2 = G[b];
-            a.part_base = 0; a.prob_part_off = 0; a.prob_nparts = a.ntiles;
-            LineDesc& c = kk[b].lines[0];
-            c.zeta = zx; c.trs = tx; c.gin = G[1 - b]; c.out = F; c.a0 = lu;
-            dkt[b] = upload_sweep(al, kt[b], 2, eb, s);
-            dk[b] = upload_sweep(al, kk[b], 2, eb, s);
+            kt[b].epi = EPI_UPDATE_CHECK;
+            kt[b].cfg = cfg;
+            kt[b].agg_from_prev = multi;
+            kt[b].agg_buf = agg_kt;
+            kt[b].agg_next = agg_k;
+            LineDesc a = make_line(y, m, x, n, pkt.zeta, pkt.trs, T, eps);
+            a.gin = F; a.out = G[1 - b]; a.a0 = lv; a.a1 = v; a.a2 = G[b];
+            a.dec_part_off = -1;
+            kt[b].lines.push_back(a);
+            assign_parts(kt[b], 0);
+            kk[b].epi = EPI_UPDATE;
+            kk[b].cfg = cfg;
+            kk[b].agg_from_prev = multi;
+            kk[b].agg_buf = agg_k;
+            kk[b].agg_next = agg_kt;
+            LineDesc c = make_line(x, n, y, m, pk.zeta, pk.trs, T, eps);
+            c.gin = G[1 - b]; c.out = F; c.a0 = lu;
+            kk[b].lines.push_back(c);
+            set_decision(kk[b], 0, pkt.ntiles);
+            upload_sweep(al, kt[b], eb);
+            upload_sweep(al, kk[b], eb);
         }
-        HIPCHK(hipEventRecord(al.a->upload_done, s));
+        al.uploaded();
+        // aggregates of the initial phi for the first K^T phi
+        launch_aggregate(o.precision, IN_LOG2, kt[0], ps, s);
 
-        // --- the loop: graphs of k iterations, one flag read per graph
-        int k = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((long long)(n + m) / 2);
-        k += (k & 1);   // even, so every replay starts on buffer 0
-        hipStream_t cs;
-        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        bool ok = true;
-        try {
-            HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            for (int it = 0; it < k; ++it) {
-                const int b = it & 1;
-                launch_sweep(o.precision, IN_LOG2, EPI_UPDATE_CHECK, dkt[b], ps, partial, cs);
-                launch_sweep(o.precision, IN_LOG2, EPI_UPDATE, dk[b], ps, nullptr, cs);
-            }
-            HIPCHK(hipStreamEndCapture(cs, &graph));
-            HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        } catch (...) {
-            ok = false;
+        LoopSpec lp;
+        for (int b = 0; b < 2; ++b) {
+            lp.seq[b] = {&kt[b], &kk[b]};
+            lp.decides[b] = {false, true};
         }
-        if (!ok) {
-            if (graph) hipGraphDestroy(graph);
-            hipStreamDestroy(cs);
-            return fail(FINOM_E_HIP);
-        }
-        long long launches = 0;
-        const long long max_launches = itr_max / k + 2;
-        int st = FINOM_OK;
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        try {
-            HIPCHK(hipEventCreate(&ev0));
-            HIPCHK(hipEventCreate(&ev1));
-            HIPCHK(hipEventRecord(ev0, s));
-            for (;;) {
-                HIPCHK(hipGraphLaunch(exec, s));
-                ++launches;
-                HIPCHK(hipMemcpyAsync(hps, ps, sizeof(ProbState), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                if (hps->done) break;
-                if (launches > max_launches) {   // cannot happen unless the device state is corrupt
-                    st = FINOM_E_HIP;
-                    break;
-                }
-            }
-            HIPCHK(hipEventRecord(ev1, s));
-            HIPCHK(hipEventSynchronize(ev1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
-            res->loop_ms = ms;
-        } catch (...) {
-            st = map_exception();
-        }
-        if (ev0) hipEventDestroy(ev0);
-        if (ev1) hipEventDestroy(ev1);
-        hipGraphExecDestroy(exec);
-        hipGraphDestroy(graph);
-        hipStreamDestroy(cs);
+        const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((n + m) / 2);
+        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
         if (st != FINOM_OK) return fail(st);
 
-        // --- returned pair: F and G[l % 2]; cost <C, Gamma> (moment sums, FP64)
-        double* Gf = G[hps->iters & 1];
-        LineDesc& c = kc.lines[0];
-        c.zeta = zx; c.trs = tc; c.gin = Gf; c.a0 = F; c.out = nullptr;
-        c.prob = 1;
-        c.part_base = 0; c.prob_part_off = 0; c.prob_nparts = c.ntiles;
-        SweepDev dc = upload_sweep(al, kc, 4, ebc, s);
-        HIPCHK(hipEventRecord(al.a->upload_done, s));
-        launch_cost_sweep(EPI_COST, dc, ps, partial, s);
-        if (f_out)
-            hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, F, f_out, (long long)n, eps * kLn2);
-        if (g_out)
-            hipLaunchKernelGGL(k_scale, dim3(blocks_for(m)), dim3(kBlock), 0, s, Gf, g_out, (long long)m, eps * kLn2);
+        // returned pair (F, G[l % 2]); <C, Gamma> from the FP64 moment sums
+        double* Gf = G[hps[0].iters & 1];
+        Sweep kc;
+        kc.kind = 2;
+        kc.epi = EPI_COST;
+        LineDesc c = make_line(x, n, y, m, pc.zeta, pc.trs, pc.T, eps);
+        c.gin = Gf; c.a0 = F; c.prob = 1; c.dec_part_off = -1;
+        kc.lines.push_back(c);
+        const int ncp = assign_parts(kc, 0);
+        upload_sweep(al, kc, sizeof(Ext<double>));
+        al.uploaded();
+        launch_sweep(o.precision, IN_LOG2, kc, ps, partial, nullptr, 0, s);
+        hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, partial, 0, ncp,
+                           &ps[1].w1);
+        if (f_out) enqueue_scale(F, f_out, n, eps * kLn2, s);
+        if (g_out) enqueue_scale(Gf, g_out, m, eps * kLn2, s);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        res->w1 = hps[1].w1;
-        res->marginal_err = hps->err;
-        res->iters = hps->iters;
-        res->sweeps = 2 * hps->iters + 1;
-        res->converged = hps->converged;
-        if (hps->status) return fail(FINOM_E_NUMERIC);
-        return fail(hps->converged ? FINOM_OK : FINOM_NOT_CONVERGED);
+        finish_result(res, hps[0], hps[1].w1);
+        if (hps[0].status) return fail(FINOM_E_NUMERIC);
+        return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
+    } catch (...) {
+        return fail(map_exception());
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 with the decoupled stabilised sweeps of the appendix
+// ---------------------------------------------------------------------------
+int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, const double* x2,
+                   int64_t n2, const double* y2, int64_t m2, const double* u, const double* v,
+                   double eps, double tol, int64_t itr_max, const finom_opts* opts, double* f_out,
+                   double* g_out, finom_result* res, void* stream)
+{
+    finom_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (!res) return FINOM_E_ARG;
+    memset(res, 0, sizeof(*res));
+    auto fail = [&](int st) {
+        res->status = st;
+        return st;
+    };
+    if (!x1 || !y1 || !x2 || !y2 || !u || !v) return fail(FINOM_E_ARG);
+    if (n1 < 1 || m1 < 1 || n2 < 1 || m2 < 1 || !finite_pos(eps)) return fail(FINOM_E_ARG);
+    if (!(tol >= 0.0) || !std::isfinite(tol) || itr_max < 0) return fail(FINOM_E_ARG);
+    if (o.precision != 0 && o.precision != 1) return fail(FINOM_E_ARG);
+    const long long na = (long long)n1 * m1, nb = (long long)n2 * m2;
+    if (n1 + n2 > INT32_MAX || m1 + m2 > INT32_MAX || na > (1LL << 40) || nb > (1LL << 40))
+        return fail(FINOM_E_ARG);
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        Alloc al(stream);
+        const int cfg_x = tuned_cfg(o.precision, n1 + n2);
+        const int cfg_y = tuned_cfg(o.precision, m1 + m2);
+        const int Tx = kCfgs[cfg_x].T(), Ty = kCfgs[cfg_y].T();
+        const int Tc = cost_tile_size();
+        const size_t eb = ext_bytes(o.precision);
+
+        int* dflag = al.dev<int>(4);
+        double* dsum = al.dev<double>(2);
+        double* lu = al.dev<double>(na);
+        double* lv = al.dev<double>(nb);
+        HIPCHK(hipMemsetAsync(dflag, 0, 4 * sizeof(int), s));
+        if (!o.skip_checks) {
+            enqueue_sorted_check(x1, n1, dflag, s);
+            enqueue_sorted_check(y1, m1, dflag, s);
+            enqueue_sorted_check(x2, n2, dflag, s);
+            enqueue_sorted_check(y2, m2, dflag, s);
+        }
+        enqueue_log2_mass(u, na, lu, dflag + 1, s);
+        enqueue_log2_mass(v, nb, lv, dflag + 1, s);
+        enqueue_sum(al, u, na, dsum, s);
+        enqueue_sum(al, v, nb, dsum + 1, s);
+        if (!o.skip_checks) {
+            const int st = read_checks(al, dflag, dsum);
+            if (st != FINOM_OK) return fail(st);
+        }
+
+        // 1D kernels of both axes (eq. 2d-1d-kernels) and their transposes
+        const Part px = make_part(al, x1, n1, x2, n2, Tx, s);    // K_x:   rows x1, cols x2
+        const Part px_t = make_part_transposed(al, px, s);       // K_x^T: rows x2, cols x1
+        const Part py = make_part(al, y1, m1, y2, m2, Ty, s);    // K_y:   rows y1, cols y2
+        const Part py_t = make_part_transposed(al, py, s);       // K_y^T: rows y2, cols y1
+        const Part pxc = make_part_like(al, px, Tc, s);
+        const Part pyc = make_part_like(al, py, Tc, s);
+
+        double* F = al.dev<double>(na);
+        double* G[2] = {al.dev<double>(nb), al.dev<double>(nb)};
+        double* S = al.dev<double>(std::max((long long)n2 * m1, (long long)n1 * m2));
+        enqueue_fill(F, na, -log2((double)na), s);
+        enqueue_fill(G[0], nb, -log2((double)nb), s);
+        ProbState* ps = al.dev<ProbState>(2);
+        ProbState* hps = al.host<ProbState>(2);
+        init_state(al, ps, hps, 2, itr_max, tol);
+
+        Sweep ktx[2], kty[2], kx[2], ky[2];
+        int nchk = 0;
+        for (int b = 0; b < 2; ++b) {
+            ktx[b].cfg = kx[b].cfg = cfg_x;
+            kty[b].cfg = ky[b].cfg = cfg_y;
+            // K^T phi = vec(K_x^T Phi K_y): S = K_x^T Phi (columns), T = S K_y (rows)
+            ktx[b].epi = EPI_STORE_LOG2;
+            add_axis0_lines(ktx[b], px_t, eps, F, n1, S, n2, m1);
+            kty[b].epi = EPI_UPDATE_CHECK;
+            add_axis1_lines(kty[b], py_t, eps, S, G[1 - b], n2, lv, v, G[b]);
+            nchk = assign_parts(kty[b], 0);
+            // K psi = vec(K_x Psi K_y^T): S = K_x Psi (columns), T = S K_y^T (rows)
+            kx[b].epi = EPI_STORE_LOG2;
+            add_axis0_lines(kx[b], px, eps, G[1 - b], n2, S, n1, m2);
+            ky[b].epi = EPI_UPDATE;
+            add_axis1_lines(ky[b], py, eps, S, F, n1, lu, nullptr, nullptr);
+        }
+        for (int b = 0; b < 2; ++b) {
+            set_decision(kx[b], 0, nchk);
+            upload_sweep(al, ktx[b], eb);
+            upload_sweep(al, kty[b], eb);
+            upload_sweep(al, kx[b], eb);
+            upload_sweep(al, ky[b], eb);
+        }
+        const long long ncost = 2LL * n1 * pyc.ntiles;
+        double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
+        al.uploaded();
+
+        LoopSpec lp;
+        for (int b = 0; b < 2; ++b) {
+            lp.seq[b] = {&ktx[b], &kty[b], &kx[b], &ky[b]};
+            lp.decides[b] = {false, false, true, false};
+        }
+        const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((na + nb) / 2);
+        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
+        if (st != FINOM_OK) return fail(st);
+
+        // <C, Gamma> = sum Phi o (M_x Psi K_y^T) + sum Phi o (K_x Psi M_y^T), M = C o K
+        double* Gf = G[hps[0].iters & 1];
+        Sweep cx_m, cy_p, cx_p, cy_m;
+        cx_m.kind = 2; cx_m.epi = EPI_STORE_LOG2;
+        add_axis0_lines(cx_m, pxc, eps, Gf, n2, S, n1, m2);
+        cy_p.kind = 1; cy_p.epi = EPI_COST;
+        add_axis1_lines(cy_p, pyc, eps, S, nullptr, n1, F, nullptr, nullptr);
+        cx_p.kind = 1; cx_p.epi = EPI_STORE_LOG2;
+        add_axis0_lines(cx_p, pxc, eps, Gf, n2, S, n1, m2);
+        cy_m.kind = 2; cy_m.epi = EPI_COST;
+        add_axis1_lines(cy_m, pyc, eps, S, nullptr, n1, F, nullptr, nullptr);
+        for (Sweep* c : {&cx_m, &cy_p, &cx_p, &cy_m})
+            for (auto& L : c->lines) L.prob = 1;
+        const int n_a = assign_parts(cy_p, 0);
+        const int n_b = assign_parts(cy_m, n_a);
+        for (Sweep* c : {&cx_m, &cy_p, &cx_p, &cy_m}) upload_sweep(al, *c, sizeof(Ext<double>));
+        al.uploaded();
+        launch_sweep(o.precision, IN_LOG2, cx_m, ps, partial, nullptr, 0, s);
+        launch_sweep(o.precision, IN_LOG2, cy_p, ps, partial, nullptr, 0, s);
+        launch_sweep(o.precision, IN_LOG2, cx_p, ps, partial, nullptr, 0, s);
+        launch_sweep(o.precision, IN_LOG2, cy_m, ps, partial, nullptr, 0, s);
+        hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, partial, 0,
+                           n_a + n_b, &ps[1].w1);
+        if (f_out) enqueue_scale(F, f_out, na, eps * kLn2, s);
+        if (g_out) enqueue_scale(Gf, g_out, nb, eps * kLn2, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        finish_result(res, hps[0], hps[1].w1);
+        res->sweeps = 4 * hps[0].iters + 2;
+        if (hps[0].status) return fail(FINOM_E_NUMERIC);
+        return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
     } catch (...) {
         return fail(map_exception());
     }
@@ -787,22 +958,8 @@ const char* finom_strerror(int status)
     }
 }
 
-void finom_release(void)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& kv : g_arenas) {
-        Arena* a = kv.second;
-        if (a->upload_done) {
-            hipEventSynchronize(a->upload_done);
-            hipEventDestroy(a->upload_done);
-        }
-        if (a->dev) hipFree(a->dev);
-        if (a->host) hipHostFree(a->host);
-        delete a;
-    }
-    g_arenas.clear();
-}
+void finom_release(void) { arena_release_all(); }
 
-const char* finom_version(void) { return "finom-gfx950 0.1"; }
+const char* finom_version(void) { return "finom-gfx950 0.2"; }
 
 }  // extern "C"

@@ -25,11 +25,13 @@ struct LineDesc {
     double out_scale;      // log2 output -> natural-log output
     double shift;          // coordinate origin used by the moment sums
     int ntiles;
-    int agg_base;          // first slot of this line in the agg / carry arrays
+    int agg_base;          // first slot of this line in the tile-aggregate array
     int prob;              // owning problem (state index)
-    int part_base;         // first slot of this line's tiles in the partial array
-    int prob_part_off;     // first partial slot of the owning problem
-    int prob_nparts;       // partial slots of the owning problem in this sweep
+    int part_base;         // partial slot of this line's tile 0 (EPI_UPDATE_CHECK / EPI_COST)
+    int dec_part_off;      // first partial slot the stop decision reads (-1: no decision)
+    int dec_nparts;        // number of partial slots the stop decision reads
+    int writes_state;      // tile 0 of this line records the decision in the state
+    int pad;
 };
 
 struct WorkItem {
@@ -37,19 +39,21 @@ struct WorkItem {
     int tile;
 };
 
-// Per-problem iteration state, resident on the device.
+// Per-problem iteration state, resident on the device. The iteration counter
+// is double-buffered by the parity of the graph slot, so the blocks of one
+// kernel only read the slot the previous iteration wrote.
 struct ProbState {
     int done;              // set once the loop-head check stops the iteration
     int converged;         // err <= tol at the stop
     int status;            // 0 ok, 1 non-finite error
     int pad0;
-    long long iters;       // completed iterations
+    long long cnt[2];      // iteration counter, slot = iteration parity
+    long long iters;       // completed iterations at the stop
     long long itr_max;
     double err;            // last checked marginal error (L1)
     double tol;
     double w1;             // <C, Gamma> of the returned pair
-    unsigned int counter;  // last-block detection for the per-problem reductions
-    int pad1;
+    double pad1;
 };
 
 enum InMode { IN_LOG2 = 0, IN_NAT = 1, IN_LIN = 2 };
@@ -59,8 +63,8 @@ enum Epilogue {
     EPI_STORE_NAT = 1,     // out = eps ln product
     EPI_STORE_LIN = 2,     // out = product
     EPI_UPDATE = 3,        // out = a0 - log2 product           (phi = u / K psi)
-    EPI_UPDATE_CHECK = 4,  // err += |psi_old K^T phi - v|, out = a0 - log2 product
-    EPI_COST = 5,          // w1 += 2^{a0 + log2 moment product}
+    EPI_UPDATE_CHECK = 4,  // partial err of |psi_old K^T phi - v|, out = a0 - log2 product
+    EPI_COST = 5,          // partial sum of 2^{a0 + log2 moment product}
 };
 
 }  // namespace finom

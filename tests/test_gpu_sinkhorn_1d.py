@@ -57,7 +57,12 @@ def test_fp32_and_fp64_converge_to_the_oracle_plan(precision):
     row = np.exp((f + s) / p.eps)
     col = np.exp((g + t) / p.eps)
     assert np.sum(np.abs(row - p.u)) <= (1e-12 if precision == 0 else 1e-6)
-    assert np.sum(np.abs(col - p.v)) <= max(tol, 1e-6) * 1.001
+    # The loop head decides with its own estimate of the error; in the FP32
+    # path each entry of K^T phi carries a relative error of a few units of
+    # 2^-24 (exp2/log2 ulps and the rounding of the sums), so the true error
+    # of the returned pair may exceed tol by up to 4 * 2^-24 * ln 2 * sum(v).
+    slack = 1e-3 * tol if precision == 0 else 4 * 2.0 ** -24 * np.log(2) * p.v.sum()
+    assert np.sum(np.abs(col - p.v)) <= tol + slack
     if precision == 0:
         assert res["iters"] == ito
 
@@ -154,5 +159,6 @@ def test_repeated_calls_are_deterministic():
     p = wl.config_small_1d(n=2500)
     r1, f1, g1 = _solve(p, precision=1, tol=1e-7, itr_max=3000)
     r2, f2, g2 = _solve(p, precision=1, tol=1e-7, itr_max=3000)
+    r1.pop("loop_ms"); r2.pop("loop_ms")
     assert r1 == r2
     assert np.array_equal(f1, f2) and np.array_equal(g1, g2)
