@@ -13,6 +13,9 @@
  *    owned by the caller, float64, contiguous. The library never frees them.
  *  - Meshes must be non-decreasing (ties allowed); the library does not sort,
  *    because sorting would permute the caller's masses.
+ *  - Every coordinate must satisfy |c| / (eps ln 2) < 2^25: the products are
+ *    formed from 2^(+-c/(eps ln 2)) with a 32-bit binary exponent. Checked on
+ *    the end points of each mesh (FINOM_E_ARG) unless skip_checks is set.
  *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *    Work is enqueued on that stream. Entry points that return host results
  *    (finom_result, device-side validation) synchronise that stream.

@@ -69,6 +69,8 @@ struct Arena {
 
 Arena* arena_for(void* stream);
 void arena_release_all();
+// Frees the blocks and the event of an arena that is not in the per-stream map.
+void arena_free(Arena* a);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -76,6 +78,7 @@ struct Alloc {
     Arena* a;
     hipStream_t s;
     explicit Alloc(void* stream) : a(arena_for(stream)), s((hipStream_t)stream) { begin(); }
+    Alloc(Arena* arena, hipStream_t stream) : a(arena), s(stream) { begin(); }
 
     void begin()
     {
@@ -221,6 +224,23 @@ struct Part {
     int ntiles = 0;
 };
 
+// A partition whose arrays are already allocated (filled by the batched
+// setup kernels).
+inline Part part_view(const double* xr, long long R, const double* yc, long long C, int* zeta, int* trs,
+                      int T)
+{
+    Part p;
+    p.xr = xr;
+    p.R = R;
+    p.yc = yc;
+    p.C = C;
+    p.zeta = zeta;
+    p.trs = trs;
+    p.T = T;
+    p.ntiles = ntiles_for(R, C, T);
+    return p;
+}
+
 Part make_part(Alloc& al, const double* xr, long long R, const double* yc, long long C, int T,
                hipStream_t s);
 // Reuses an existing dividing index with another tile size.
@@ -239,5 +259,58 @@ void enqueue_fill(double* a, long long n, double v, hipStream_t s);
 void enqueue_scale(const double* a, double* b, long long n, double f, hipStream_t s);
 
 int map_exception();
+
+constexpr double kCoordLimit = 33554432.0;   // 2^25: bound on |coordinate| / (eps ln 2)
+
+// ---------------------------------------------------------------------------
+// Line builders shared by the single-problem solvers and the batch engine
+// ---------------------------------------------------------------------------
+
+// Lines of a 2D sweep along the first axis: every column j of an
+// (in_rows x ncols) column-major input is one line.
+inline void add_axis0_lines(Sweep& sw, const Part& p, double eps, const double* in, long long in_rows,
+                            double* out, long long out_rows, long long ncols, int prob = 0)
+{
+    for (long long j = 0; j < ncols; ++j) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = in + j * in_rows;
+        L.out = out + j * out_rows;
+        L.dec_part_off = -1;
+        L.prob = prob;
+        sw.lines.push_back(L);
+    }
+}
+
+// Lines along the second axis: every row k of an (nrows x ...) column-major
+// input is one line (stride nrows), written to row k of the output.
+inline void add_axis1_lines(Sweep& sw, const Part& p, double eps, const double* in, double* out,
+                            long long nrows, const double* a0, const double* a1, const double* a2,
+                            int prob = 0)
+{
+    for (long long k = 0; k < nrows; ++k) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = in + k;
+        L.gstride = nrows;
+        L.out = out ? out + k : nullptr;
+        L.ostride = nrows;
+        L.a0 = a0 ? a0 + k : nullptr;
+        L.a1 = a1 ? a1 + k : nullptr;
+        L.a2 = a2 ? a2 + k : nullptr;
+        L.dec_part_off = -1;
+        L.prob = prob;
+        sw.lines.push_back(L);
+    }
+}
+
+// Partial-slot layout of a checking / cost sweep: consecutive per line.
+inline int assign_parts(Sweep& sw, int base)
+{
+    int off = base;
+    for (auto& L : sw.lines) {
+        L.part_base = off;
+        off += L.ntiles;
+    }
+    return off - base;
+}
 
 }  // namespace finom

@@ -156,6 +156,20 @@ Arena* arena_for(void* stream)
     return a;
 }
 
+void arena_free(Arena* a)
+{
+    if (a->upload_done) {
+        hipEventSynchronize(a->upload_done);
+        hipEventDestroy(a->upload_done);
+        a->upload_done = nullptr;
+    }
+    for (auto& b : a->dblk) hipFree(b.p);
+    for (auto& b : a->hblk) hipHostFree(b.p);
+    a->dblk.clear();
+    a->hblk.clear();
+    a->dused = a->hused = 0;
+}
+
 void arena_release_all()
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -419,6 +433,25 @@ void enqueue_scale(const double* a, double* b, long long n, double f, hipStream_
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Reads the end points of the (sorted) meshes and checks that every exponent
+// |coordinate| / (eps ln 2) stays below 2^25, the range the device exponent
+// arithmetic is written for. Returns FINOM_OK or FINOM_E_ARG.
+static int check_coord_range(Alloc& al, const double* const* meshes, const long long* sizes, int count,
+                             double eps)
+{
+    double* h = al.host<double>(2 * count);
+    for (int k = 0; k < count; ++k) {
+        HIPCHK(hipMemcpyAsync(h + 2 * k, meshes[k], sizeof(double), hipMemcpyDeviceToHost, al.s));
+        HIPCHK(hipMemcpyAsync(h + 2 * k + 1, meshes[k] + sizes[k] - 1, sizeof(double), hipMemcpyDeviceToHost,
+                              al.s));
+    }
+    HIPCHK(hipStreamSynchronize(al.s));
+    const double kappa = 1.0 / (eps * kLn2);
+    for (int k = 0; k < 2 * count; ++k)
+        if (!(fabs(h[k]) * kappa < kCoordLimit)) return FINOM_E_ARG;
+    return FINOM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // the iteration loop: k iterations per captured graph, one state read per graph
 // ---------------------------------------------------------------------------
@@ -529,50 +562,6 @@ static void finish_result(finom_result* res, const ProbState& st, double w1)
     res->converged = st.converged;
 }
 
-// Lines of a 2D sweep along the first axis: every column j of an
-// (in_rows x ncols) column-major input is one line.
-static void add_axis0_lines(Sweep& sw, const Part& p, double eps, const double* in, long long in_rows,
-                            double* out, long long out_rows, long long ncols)
-{
-    for (long long j = 0; j < ncols; ++j) {
-        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
-        L.gin = in + j * in_rows;
-        L.out = out + j * out_rows;
-        L.dec_part_off = -1;
-        sw.lines.push_back(L);
-    }
-}
-
-// Lines along the second axis: every row k of an (nrows x ...) column-major
-// input is one line (stride nrows), written to row k of the output.
-static void add_axis1_lines(Sweep& sw, const Part& p, double eps, const double* in, double* out,
-                            long long nrows, const double* a0, const double* a1, const double* a2)
-{
-    for (long long k = 0; k < nrows; ++k) {
-        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
-        L.gin = in + k;
-        L.gstride = nrows;
-        L.out = out ? out + k : nullptr;
-        L.ostride = nrows;
-        L.a0 = a0 ? a0 + k : nullptr;
-        L.a1 = a1 ? a1 + k : nullptr;
-        L.a2 = a2 ? a2 + k : nullptr;
-        L.dec_part_off = -1;
-        sw.lines.push_back(L);
-    }
-}
-
-// Partial-slot layout of a checking / cost sweep: consecutive per line.
-static int assign_parts(Sweep& sw, int base)
-{
-    int off = base;
-    for (auto& L : sw.lines) {
-        L.part_base = off;
-        off += L.ntiles;
-    }
-    return off - base;
-}
-
 static void set_decision(Sweep& sw, int off, int n)
 {
     for (size_t i = 0; i < sw.lines.size(); ++i) {
@@ -612,6 +601,9 @@ static int matvec_impl(bool dense, const double* x, int64_t n, const double* y, 
             HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             if (hflag[0]) return FINOM_E_UNSORTED;
+            const double* ms[2] = {x, y};
+            const long long ns[2] = {n, m};
+            if (check_coord_range(al, ms, ns, 2, eps) != FINOM_OK) return FINOM_E_ARG;
         }
         const int inm = (o.domain == 1) ? IN_NAT : IN_LIN;
         const double kappa = 1.0 / (eps * kLn2);
@@ -709,7 +701,12 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         enqueue_sum(al, u, n, dsum, s);
         enqueue_sum(al, v, m, dsum + 1, s);
         if (!o.skip_checks) {
-            const int st = read_checks(al, dflag, dsum);
+            int st = read_checks(al, dflag, dsum);
+            if (st == FINOM_OK) {
+                const double* ms[2] = {x, y};
+                const long long ns[2] = {n, m};
+                st = check_coord_range(al, ms, ns, 2, eps);
+            }
             if (st != FINOM_OK) return fail(st);
         }
 
@@ -847,7 +844,12 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         enqueue_sum(al, u, na, dsum, s);
         enqueue_sum(al, v, nb, dsum + 1, s);
         if (!o.skip_checks) {
-            const int st = read_checks(al, dflag, dsum);
+            int st = read_checks(al, dflag, dsum);
+            if (st == FINOM_OK) {
+                const double* ms[4] = {x1, y1, x2, y2};
+                const long long ns[4] = {n1, m1, n2, m2};
+                st = check_coord_range(al, ms, ns, 4, eps);
+            }
             if (st != FINOM_OK) return fail(st);
         }
 

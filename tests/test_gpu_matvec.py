@@ -119,6 +119,10 @@ def test_error_paths():
     with pytest.raises(FinomError) as e:
         finom_matvec(dev(x), dev(y), 0.1, dev(g), domain=3)
     assert e.value.status == FINOM_E_ARG
+    # |coordinate| / (eps ln 2) beyond 2^25: outside the exponent range
+    with pytest.raises(FinomError) as e:
+        finom_matvec(dev(x * 1e6), dev(y), 1e-3, dev(g), domain=1)
+    assert e.value.status == FINOM_E_ARG
 
 
 @pytest.mark.parametrize("precision", [0, 1])

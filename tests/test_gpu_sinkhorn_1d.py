@@ -153,6 +153,9 @@ def test_error_statuses():
     with pytest.raises(FinomError) as e:
         _solve(wl.Problem1D(p.x, p.y, p.u, p.v, 0.0, p.tol, 10))
     assert e.value.status == FINOM_E_ARG
+    with pytest.raises(FinomError) as e:
+        _solve(wl.Problem1D(p.x, p.y * 3e4, p.u, p.v, 1e-3, p.tol, 10))
+    assert e.value.status == FINOM_E_ARG
 
 
 def test_repeated_calls_are_deterministic():
