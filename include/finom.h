@@ -129,6 +129,94 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
                    int64_t itr_max, const finom_opts* opts, double* f_out,
                    double* g_out, finom_result* res, void* stream);
 
+/*
+ * One problem of a batch or a serving request. dim = 1: Algorithm 1 on
+ * x = x1 (n1 points, masses u) and y = x2 (n2 points, masses v); m1, m2, y1,
+ * y2 are ignored. dim = 2: Algorithm 2 on the grids x1 (n1) x y1 (m1) and
+ * x2 (n2) x y2 (m2) with column-major u, v as in sinkhorn_w1_2d. All arrays
+ * are device arrays owned by the caller; f_out / g_out may be NULL.
+ */
+typedef struct {
+    int32_t dim;
+    int32_t reserved;     /* 0 */
+    int64_t n1, m1, n2, m2;
+    const double *x1, *y1, *x2, *y2;
+    const double *u, *v;
+    double eps, tol;
+    int64_t itr_max;
+    double *f_out, *g_out;
+} finom_problem;
+
+/*
+ * Solves `count` independent problems (1D and 2D may be mixed) together: the
+ * lines of all live problems share each sweep launch, every problem keeps its
+ * own iteration counter, loop-head check and stop decision (the iteration of
+ * Algorithm 1 / Algorithm 2 is unchanged), and stopped problems retire from
+ * the launches. A problem's results equal those of sinkhorn_w1_1d /
+ * sinkhorn_w1_2d on it alone.
+ *   probs: HOST array of count descriptors; res: HOST array of count results
+ *   (res[i].status per problem). Problems that fail validation are skipped
+ *   (their status says why); the others are solved.
+ * Returns FINOM_OK if every problem converged, FINOM_NOT_CONVERGED if some hit
+ * their cap, else the first negative per-problem status (FINOM_E_ARG for a
+ * bad count or pointer, in which case nothing runs).
+ */
+int finom_batch(const finom_problem* probs, int64_t count, const finom_opts* opts,
+                finom_result* res, void* stream);
+
+/* Device bytes the library holds for one problem while it is being solved
+ * (the serving admission unit). Negative status for an invalid descriptor. */
+int64_t finom_footprint(const finom_problem* p, const finom_opts* opts);
+
+/*
+ * Serving loop. A server owns a device memory budget, a HIP stream and a host
+ * thread that admits submitted problems in arrival order while their
+ * footprints fit the budget, joins them to the running batch between rounds of
+ * a few iterations, and publishes each result when its problem stops.
+ * The caller keeps a problem's arrays alive and unmodified until its
+ * completion has been polled, and makes them ready (synchronised) before
+ * submitting. Calls on one server may come from any host thread.
+ */
+typedef struct finom_server finom_server;
+
+typedef struct {
+    int64_t ticket;
+    finom_result res;
+    double latency_ms;    /* submit -> result published */
+    double queue_ms;      /* submit -> joined the batch  */
+} finom_completion;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t live, queued, rounds;
+    double grid_pt_iters; /* sum over completed problems of grid points x iterations */
+    double busy_ms;       /* GPU time of the iteration rounds                         */
+    uint64_t hbm_used, hbm_budget;
+} finom_server_stats;
+
+/* opts: precision and graph_iters (iterations per round, default 8) apply. */
+int finom_server_create(uint64_t hbm_budget_bytes, const finom_opts* opts, finom_server** out);
+/* FINOM_E_ADMIT if the problem's footprint exceeds the whole budget,
+ * FINOM_E_ARG for an invalid descriptor (nothing queued in either case). */
+int finom_server_submit(finom_server* srv, const finom_problem* p, int64_t* ticket);
+/* Up to max completions into out (HOST); waits up to wait_ms for the first. */
+int finom_server_poll(finom_server* srv, finom_completion* out, int64_t max, int64_t* n_out,
+                      int32_t wait_ms);
+int finom_server_stats_get(finom_server* srv, finom_server_stats* st);
+/* Stops the thread after the live problems finish; pending results are dropped. */
+void finom_server_destroy(finom_server* srv);
+
+/*
+ * Tile-shape autotuner: times every tile shape on merged-line lengths of
+ * 2^9 .. 2^21 elements (batches that fill the GPU, update sweeps) and keeps the
+ * fastest per size class for all later calls in the process. With cache_path,
+ * results are read from that file if it exists and written to it otherwise.
+ * The environment variable FINOM_TILE_CFG (0..2) overrides every choice.
+ */
+int finom_autotune(int32_t precision, const char* cache_path, void* stream);
+/* The tile-shape index used for a line of `merged` = rows + columns elements. */
+int finom_tile_config(int32_t precision, int64_t merged);
+
 /* Human-readable text for a status code (static storage). */
 const char* finom_strerror(int status);
 

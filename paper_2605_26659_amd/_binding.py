@@ -48,6 +48,30 @@ class Result(C.Structure):
                 "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps)}
 
 
+class Problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("reserved", C.c_int32),
+                ("n1", C.c_int64), ("m1", C.c_int64), ("n2", C.c_int64), ("m2", C.c_int64),
+                ("x1", C.c_void_p), ("y1", C.c_void_p), ("x2", C.c_void_p), ("y2", C.c_void_p),
+                ("u", C.c_void_p), ("v", C.c_void_p),
+                ("eps", C.c_double), ("tol", C.c_double), ("itr_max", C.c_int64),
+                ("f_out", C.c_void_p), ("g_out", C.c_void_p)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("res", Result), ("latency_ms", C.c_double),
+                ("queue_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rejected", C.c_int64), ("live", C.c_int64), ("queued", C.c_int64),
+                ("rounds", C.c_int64), ("grid_pt_iters", C.c_double), ("busy_ms", C.c_double),
+                ("hbm_used", C.c_uint64), ("hbm_budget", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -84,6 +108,17 @@ def load(path: os.PathLike | None = None):
     if hasattr(L, "sinkhorn_w1_2d"):
         L.sinkhorn_w1_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _d, _d,
                                      _i64, C.POINTER(Opts), _vp, _vp, C.POINTER(Result), _vp]
+    L.finom_batch.argtypes = [C.POINTER(Problem), _i64, C.POINTER(Opts), C.POINTER(Result), _vp]
+    L.finom_footprint.argtypes = [C.POINTER(Problem), C.POINTER(Opts)]
+    L.finom_footprint.restype = _i64
+    L.finom_server_create.argtypes = [C.c_uint64, C.POINTER(Opts), C.POINTER(_vp)]
+    L.finom_server_submit.argtypes = [_vp, C.POINTER(Problem), C.POINTER(_i64)]
+    L.finom_server_poll.argtypes = [_vp, C.POINTER(Completion), _i64, C.POINTER(_i64), C.c_int32]
+    L.finom_server_stats_get.argtypes = [_vp, C.POINTER(ServerStats)]
+    L.finom_server_destroy.argtypes = [_vp]
+    L.finom_server_destroy.restype = None
+    L.finom_autotune.argtypes = [C.c_int32, C.c_char_p, _vp]
+    L.finom_tile_config.argtypes = [C.c_int32, _i64]
     if path is None:
         _lib = L
     return L
@@ -211,3 +246,151 @@ def finom_release():
 
 def finom_version() -> str:
     return load().finom_version().decode()
+
+
+# ----------------------------------------------------------------------------
+# batches and serving
+# ----------------------------------------------------------------------------
+
+def problem_1d(x, y, u, v, eps, tol, itr_max, f_out=None, g_out=None):
+    """Descriptor of a 1D problem (device tensors) for finom_batch / FinomServer."""
+    return {"dim": 1, "x1": x, "x2": y, "u": u, "v": v, "eps": eps, "tol": tol,
+            "itr_max": itr_max, "f_out": f_out, "g_out": g_out}
+
+
+def problem_2d(x1, y1, x2, y2, u, v, eps, tol, itr_max, f_out=None, g_out=None):
+    """Descriptor of a 2D problem; u, v and the outputs are flat column-major."""
+    return {"dim": 2, "x1": x1, "y1": y1, "x2": x2, "y2": y2, "u": u, "v": v, "eps": eps,
+            "tol": tol, "itr_max": itr_max, "f_out": f_out, "g_out": g_out}
+
+
+def _problem_struct(d):
+    P = Problem()
+    P.dim = int(d["dim"])
+    P.reserved = 0
+    P.n1 = d["x1"].numel()
+    P.n2 = d["x2"].numel()
+    P.x1 = _dev(d["x1"], "x1")
+    P.x2 = _dev(d["x2"], "x2")
+    if P.dim == 2:
+        P.m1 = d["y1"].numel()
+        P.m2 = d["y2"].numel()
+        P.y1 = _dev(d["y1"], "y1")
+        P.y2 = _dev(d["y2"], "y2")
+    else:
+        P.m1 = P.m2 = 1
+    P.u = _dev(d["u"], "u")
+    P.v = _dev(d["v"], "v")
+    P.eps = float(d["eps"])
+    P.tol = float(d["tol"])
+    P.itr_max = int(d["itr_max"])
+    P.f_out = _dev(d["f_out"], "f_out") if d.get("f_out") is not None else None
+    P.g_out = _dev(d["g_out"], "g_out") if d.get("g_out") is not None else None
+    return P
+
+
+def with_outputs(d):
+    """Adds freshly allocated f_out / g_out tensors to a descriptor."""
+    torch = _torch()
+    out = dict(d)
+    dev = d["x1"].device
+    if d["dim"] == 1:
+        na, nb = d["x1"].numel(), d["x2"].numel()
+    else:
+        na = d["x1"].numel() * d["y1"].numel()
+        nb = d["x2"].numel() * d["y2"].numel()
+    out["f_out"] = torch.empty(na, dtype=torch.float64, device=dev)
+    out["g_out"] = torch.empty(nb, dtype=torch.float64, device=dev)
+    return out
+
+
+def finom_footprint(d, *, precision=0) -> int:
+    return int(load().finom_footprint(C.byref(_problem_struct(d)), C.byref(_opts(precision))))
+
+
+def finom_batch(problems, *, precision=0, skip_checks=False, graph_iters=0, stream=None):
+    """Solves a list of descriptors together. Returns (status, [result dict]);
+    each result carries its own status. Raises only for runtime failures."""
+    n = len(problems)
+    arr = (Problem * max(n, 1))()
+    for i, d in enumerate(problems):
+        arr[i] = _problem_struct(d)
+    res = (Result * max(n, 1))()
+    st = load().finom_batch(arr, n, C.byref(_opts(precision, 0, skip_checks, graph_iters)), res,
+                            _stream_ptr(stream))
+    if st in (FINOM_E_HIP, FINOM_E_NOMEM):
+        raise FinomError(st, "finom_batch")
+    return st, [res[i].as_dict() for i in range(n)]
+
+
+def finom_autotune(precision=0, cache_path=None, stream=None):
+    st = load().finom_autotune(int(precision), cache_path.encode() if cache_path else None,
+                               _stream_ptr(stream))
+    _check(st, "finom_autotune")
+
+
+def finom_tile_config(precision, merged) -> int:
+    return int(load().finom_tile_config(int(precision), int(merged)))
+
+
+class FinomServer:
+    """Continuous-batching solver (one host thread and stream of its own).
+    Descriptors' tensors are kept referenced until their completion is polled."""
+
+    def __init__(self, hbm_budget_bytes, *, precision=0, graph_iters=0, skip_checks=False):
+        self._lib = load()
+        h = C.c_void_p()
+        st = self._lib.finom_server_create(int(hbm_budget_bytes),
+                                           C.byref(_opts(precision, 0, skip_checks, graph_iters)),
+                                           C.byref(h))
+        _check(st, "finom_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, d, sync=True) -> int:
+        """Queues a problem; returns its ticket. With sync, torch's current
+        stream is synchronised first so the inputs are complete."""
+        if sync:
+            _torch().cuda.current_stream().synchronize()
+        P = _problem_struct(d)
+        t = C.c_int64(0)
+        st = self._lib.finom_server_submit(self._h, C.byref(P), C.byref(t))
+        _check(st, "finom_server_submit")
+        self._keep[int(t.value)] = d
+        return int(t.value)
+
+    def poll(self, max_items=256, wait_ms=0):
+        buf = (Completion * max(1, max_items))()
+        n = C.c_int64(0)
+        st = self._lib.finom_server_poll(self._h, buf, int(max_items), C.byref(n), int(wait_ms))
+        _check(st, "finom_server_poll")
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            r = c.res.as_dict()
+            r.update(ticket=int(c.ticket), latency_ms=float(c.latency_ms),
+                     queue_ms=float(c.queue_ms), problem=self._keep.pop(int(c.ticket), None))
+            out.append(r)
+        return out
+
+    def stats(self):
+        s = ServerStats()
+        self._lib.finom_server_stats_get(self._h, C.byref(s))
+        return s.as_dict()
+
+    def close(self):
+        if self._h:
+            self._lib.finom_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -25,8 +25,8 @@ struct TileCfg {
     int block, ipt;
     int T() const { return block * ipt; }
 };
-constexpr int kNumCfg = 3;
-constexpr TileCfg kCfgs[kNumCfg] = {{256, 4}, {256, 8}, {512, 8}};
+constexpr int kNumCfg = 4;
+constexpr TileCfg kCfgs[kNumCfg] = {{256, 4}, {256, 8}, {512, 8}, {128, 4}};
 constexpr int kCostBlock = 256, kCostIpt = 2;
 
 struct HipError {
@@ -45,9 +45,14 @@ inline int cost_tile_size() { return kCostBlock * kCostIpt; }
 inline size_t ext_bytes(int precision) { return precision == 1 ? sizeof(Ext<float>) : sizeof(Ext<double>); }
 
 // Default tile shape for a 1D line of `merged` elements; the autotuner can
-// override it per size class.
+// override it per size class (class c holds lengths up to 2^(9 + c), the
+// last class everything longer).
 int default_cfg(int precision, long long merged);
 int tuned_cfg(int precision, long long merged);
+constexpr int kTuneClasses = 13;
+int tune_class(long long merged);
+void set_tuned_cfg(int precision, int cls, int cfg);
+int get_tuned_cfg(int precision, int cls);   // -1 when not tuned
 
 // ---------------------------------------------------------------------------
 // Workspace: per stream, a list of device blocks and pinned host blocks.

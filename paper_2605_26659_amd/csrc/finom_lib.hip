@@ -4,7 +4,9 @@
 // graphs, and the C ABI of include/finom.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
+#include <mutex>
 
 #include "../../include/finom.h"
 #include "finom_host.hpp"
@@ -307,12 +309,14 @@ static void dispatch(int precision, int inm, const Sweep& sw, ProbState* ps, dou
             case 0: FINOM_VARIANTS(float, 256, 4) break;
             case 1: FINOM_VARIANTS(float, 256, 8) break;
             case 2: FINOM_VARIANTS(float, 512, 8) break;
+            case 3: FINOM_VARIANTS(float, 128, 4) break;
         }
     } else {
         switch (sw.cfg) {
             case 0: FINOM_VARIANTS(double, 256, 4) break;
             case 1: FINOM_VARIANTS(double, 256, 8) break;
             case 2: FINOM_VARIANTS(double, 512, 8) break;
+            case 3: FINOM_VARIANTS(double, 128, 4) break;
         }
     }
     throw HipError{hipErrorInvalidValue};
@@ -331,6 +335,36 @@ void launch_aggregate(int precision, int inm, const Sweep& sw, ProbState* ps, hi
     dispatch(precision, inm, sw, ps, nullptr, nullptr, 0, true, s);
 }
 
+static std::atomic<int> g_tuned[2][kTuneClasses];
+static std::once_flag g_tuned_once;
+
+static void tuned_init()
+{
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < kTuneClasses; ++c) g_tuned[p][c].store(-1);
+}
+
+int tune_class(long long merged)
+{
+    int c = 0;
+    while (c < kTuneClasses - 1 && merged > (512LL << c)) ++c;
+    return c;
+}
+
+void set_tuned_cfg(int precision, int cls, int cfg)
+{
+    std::call_once(g_tuned_once, tuned_init);
+    if (precision < 0 || precision > 1 || cls < 0 || cls >= kTuneClasses) return;
+    g_tuned[precision][cls].store((cfg >= 0 && cfg < kNumCfg) ? cfg : -1);
+}
+
+int get_tuned_cfg(int precision, int cls)
+{
+    std::call_once(g_tuned_once, tuned_init);
+    if (precision < 0 || precision > 1 || cls < 0 || cls >= kTuneClasses) return -1;
+    return g_tuned[precision][cls].load();
+}
+
 int tuned_cfg(int precision, long long merged)
 {
     const char* e = getenv("FINOM_TILE_CFG");
@@ -338,6 +372,8 @@ int tuned_cfg(int precision, long long merged)
         const int c = atoi(e);
         if (c >= 0 && c < kNumCfg) return c;
     }
+    const int t = get_tuned_cfg(precision, tune_class(merged));
+    if (t >= 0) return t;
     return default_cfg(precision, merged);
 }
 

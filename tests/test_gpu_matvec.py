@@ -143,3 +143,20 @@ def test_full_size_graded_sampled_rows(eps, precision):
     # grows like sqrt(m) * 2^-53 per term magnitude, ~1e-12 here; the bound is
     # four times that.
     assert err <= (4e-12 if precision == 0 else TOL_F32), err
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_tile_shape_matches_oracle(cfg, precision, monkeypatch):
+    """Each tile shape (threads x columns per thread) on lines of one to many
+    tiles, with ties and n != m."""
+    from paper_2605_26659_amd import finom_matvec
+    monkeypatch.setenv("FINOM_TILE_CFG", str(cfg))
+    for seed, (n, m) in enumerate([(200, 150), (3000, 1700), (9000, 9000)]):
+        x, y = rand_meshes(40 + seed, n, m, ties=True)
+        g = np.random.default_rng(seed).normal(size=m) * 0.01
+        eps = 1e-2
+        out = host(finom_matvec(dev(x), dev(y), eps, dev(g), domain=1, precision=precision))
+        ref = clib.dense_logmatvec(x, y, g, eps)
+        tol = TOL_F64 if precision == 0 else TOL_F32
+        assert np.max(np.abs(out - ref)) / eps <= tol
