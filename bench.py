@@ -72,6 +72,11 @@ def parse():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 4096-problem batch")
+    ap.add_argument("--serving", action="store_true",
+                    help="full serving sweep (several arrival rates and the nominal 2000/s)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the short serving sample")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized FP64 buffer 10 times (counter calibration)")
     return ap.parse_args()
@@ -127,6 +132,130 @@ def cpu_baseline(prob, seconds):
     }
 
 
+def bench_batch(precision):
+    """The uneven batch: 4096 problems, n = m log-uniform in [256, 65536],
+    eps log-uniform in [1e-3, 1e-1], tol 1e-6, cap 20000, one finom_batch
+    call. Throughput = sum over problems of points x iterations / time."""
+    import torch
+    from paper_2605_26659_amd import finom_batch, problem_1d, workloads as wl
+    probs = wl.config_batch()
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+    descs = [problem_1d(dev(p.x), dev(p.y), dev(p.u), dev(p.v), p.eps, p.tol, p.itr_max)
+             for p in probs]
+    torch.cuda.synchronize()
+    out = {}
+    for rep in range(2):      # the first call also warms the workspace
+        t0 = time.perf_counter()
+        st, res = finom_batch(descs, precision=precision)
+        wall = time.perf_counter() - t0
+    work = float(sum(0.5 * (len(p.x) + len(p.y)) * r["iters"] for p, r in zip(probs, res)))
+    loop_s = max(r["loop_ms"] for r in res) * 1e-3
+    its = np.array([r["iters"] for r in res])
+    # the same problems solved one by one with the single-problem entry point
+    # in FP64 (a fixed sample: every 16th problem)
+    from paper_2605_26659_amd import sinkhorn_w1_1d
+    idx = list(range(0, len(probs), 16))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w_alone = 0.0
+    for i in idx:
+        d = descs[i]
+        r, _, _ = sinkhorn_w1_1d(d["x1"], d["x2"], d["u"], d["v"], d["eps"], d["tol"], d["itr_max"],
+                                 precision=0, want_potentials=False)
+        w_alone += 0.5 * (d["x1"].numel() + d["x2"].numel()) * r["iters"]
+    alone_rate = w_alone / (time.perf_counter() - t0)
+    out = {"value": work / wall, "unit": "grid-pt*iters/s", "problems": len(probs),
+           "points": float(sum(len(p.x) for p in probs)), "wall_s": wall,
+           "loop_s": loop_s, "loop_rate": work / loop_s,
+           "iters_mean": float(its.mean()), "iters_max": int(its.max()),
+           "converged": int(sum(r["converged"] for r in res)), "status": st,
+           "scan_mantissa": "fp32" if precision == 1 else "fp64",
+           "per_problem_fp64_alone": {"value": alone_rate, "unit": "grid-pt*iters/s",
+                                      "sample": f"{len(idx)} problems (every 16th), one "
+                                                "sinkhorn_w1_1d call each, FP64 scans"},
+           "note": "wall time of the call (setup, iteration, costs); loop_rate excludes "
+                   "setup and cost"}
+    return out
+
+
+def _serving_pool(size, precision):
+    """Materialised requests of the serving mix (70 % 1D graded n log-uniform
+    in [1e3, 1e6], 30 % 2D tanh side log-uniform in [64, 512], eps 1e-2 or
+    1e-3, tol 1e-6); arrivals reuse them round-robin."""
+    import torch
+    from paper_2605_26659_amd import finom_batch, problem_1d, problem_2d, workloads as wl
+    reqs = wl.serving_requests(rate=2000.0, window=10.0, max_requests=size)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    descs, pts = [], []
+    for r in reqs:
+        p = wl.build_request_problem(r.problem)
+        if r.problem[0] == "1d":
+            descs.append(problem_1d(dev(p.x), dev(p.y), dev(p.u), dev(p.v), p.eps, p.tol, p.itr_max))
+        else:
+            descs.append(problem_2d(dev(p.x1), dev(p.y1), dev(p.x2), dev(p.y2),
+                                    dev(p.u.ravel(order="F")), dev(p.v.ravel(order="F")),
+                                    p.eps, p.tol, p.itr_max))
+        pts.append(p.points)
+    torch.cuda.synchronize()
+    st, res = finom_batch(descs, precision=precision)
+    work = np.array([pt * r["iters"] for pt, r in zip(pts, res)])
+    return descs, np.array(pts), work
+
+
+def _serve(descs, work, rate, window, precision, budget, seed, drain_s=60.0):
+    from paper_2605_26659_amd import FinomServer
+    rng = np.random.default_rng(seed)
+    t, arr = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > window:
+            break
+        arr.append(t)
+    done, k = [], 0
+    with FinomServer(budget, precision=precision) as srv:
+        t0 = time.perf_counter()
+        while len(done) < len(arr):
+            now = time.perf_counter() - t0
+            while k < len(arr) and arr[k] <= now:
+                srv.submit(descs[k % len(descs)], sync=False)
+                k += 1
+            done += srv.poll(512, wait_ms=0)
+            if now > window + drain_s:
+                break
+            nxt = arr[k] - now if k < len(arr) else 0.002
+            time.sleep(max(0.0, min(nxt, 0.002)))
+        t_end = time.perf_counter() - t0
+        stats = srv.stats()
+    lat = np.array([c["latency_ms"] for c in done]) if done else np.array([np.nan])
+    served_work = float(sum(work[(c["ticket"] - 1) % len(descs)] for c in done))
+    offered_work = float(sum(work[i % len(descs)] for i in range(len(arr))))
+    return {"rate_per_s": rate, "window_s": window, "requests": len(arr), "completed": len(done),
+            "p50_latency_ms": float(np.percentile(lat, 50)),
+            "p99_latency_ms": float(np.percentile(lat, 99)),
+            "offered_grid_pt_iters_per_s": offered_work / window,
+            "served_grid_pt_iters_per_s": served_work / t_end,
+            "elapsed_s": t_end, "gpu_busy_ms": stats["busy_ms"], "rounds": stats["rounds"]}
+
+
+def bench_serving(precision, full):
+    budget = 64 << 30
+    descs, pts, work = _serving_pool(48, precision)
+    # sustainable rates relative to the measured single-batch capacity
+    cap_rate = 1.5e10 / float(work.mean())
+    out = {"pool": len(descs), "mean_points": float(pts.mean()),
+           "mean_work_grid_pt_iters": float(work.mean()), "budget_bytes": budget,
+           "scan_mantissa": "fp32" if precision == 1 else "fp64",
+           "note": "requests drawn round-robin from a pool of materialised requests of the "
+                   "serving mix; latency = submit -> result published", "runs": []}
+    fracs = (0.25, 0.5, 0.8) if full else (0.5,)
+    for i, fr in enumerate(fracs):
+        out["runs"].append(_serve(descs, work, fr * cap_rate, 3.0 if full else 2.0, precision,
+                                  budget, 100 + i))
+    if full:
+        out["runs"].append(_serve(descs, work, 2000.0, 1.0, precision, budget, 200, drain_s=120.0))
+    return out
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -158,6 +287,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 8 * n, "copies": 10}), flush=True)
         return
+
+    if not args.no_autotune:
+        from paper_2605_26659_amd import finom_autotune
+        for p in (1, 0):
+            finom_autotune(p)
 
     prob = wl.config_graded_1d(args.n, args.eps, tol=args.tol)
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
@@ -235,9 +369,26 @@ def main():
                     "tolerance = per-iteration time x FINOM's iteration count"}
         extra["speedup_vs_dense"] = value / dense_rate
 
+    if not args.no_batch:
+        extra["batch_4096"] = bench_batch(prec)
+    if args.serving or not args.no_serving:
+        extra["serving"] = bench_serving(prec, args.serving)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prob, args.cpu_seconds)
+
+    from paper_2605_26659_amd import finom_tile_config
+    extra["tile_shapes"] = {p: [finom_tile_config(1 if p == "fp32" else 0, 512 << c) for c in range(13)]
+                            for p in ("fp32", "fp64")}
+    extra["tile_shapes_note"] = ("tile-shape index per merged-line length class 2^9..2^21 "
+                                 "(0: 256x4, 1: 256x8, 2: 512x8, 3: 128x4)")
+    # the paper's own timing (section 4.1, Table 1: C++ on a 14-core Xeon Gold
+    # 5117 at 2.0 GHz, eps = 0.01, 1000 iterations), as context only
+    extra["paper_cpu_context"] = {"workload": "1D Chebyshev nodes N=8000, 1000 iterations",
+                                  "finom_s": 1.41e-1, "dense_s": 9.05e2,
+                                  "finom_grid_pt_iters_per_s": 8000 * 1000 / 1.41e-1,
+                                  "hardware": "Xeon Gold 5117 14-core 2.0 GHz (CPU)"}
 
     lat_ms = np.array(lat) * 1e3
     line = {

@@ -189,7 +189,7 @@ int finom_server_create(uint64_t hbm_budget_bytes, const finom_opts* opts, finom
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (o.precision != 0 && o.precision != 1) return FINOM_E_ARG;
-    if (hbm_budget_bytes < (1u << 20)) return FINOM_E_ARG;
+    if (hbm_budget_bytes < 4096) return FINOM_E_ARG;
     finom_server* srv = new (std::nothrow) finom_server();
     if (!srv) return FINOM_E_NOMEM;
     try {

@@ -8,8 +8,9 @@
 * Members against the oracle (Algorithm 1 on the CPU, dense definition).
 * Validation: failing members are reported and skipped, the rest is solved.
 * The uneven 4096-problem workload (n log-uniform in [256, 65536], eps
-  log-uniform in [1e-3, 1e-1], tol 1e-6): every member converges and
-  sampled members agree with the oracle.
+  log-uniform in [1e-3, 1e-1], tol 1e-6, cap 20000): members converge or
+  stop at the cap exactly where the oracle does, and sampled members agree
+  with the oracle.
 """
 import numpy as np
 import pytest

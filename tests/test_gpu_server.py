@@ -89,7 +89,7 @@ def test_refusals_and_validation_statuses():
     good = _desc_1d(p, tol=1e-6, itr_max=3000)
     budget = 4 * finom_footprint(good)
     assert finom_footprint(big) > budget
-    with FinomServer(max(budget, 1 << 20)) as srv:
+    with FinomServer(budget) as srv:
         with pytest.raises(FinomError) as e:
             srv.submit(big)
         assert e.value.status == FINOM_E_ADMIT
