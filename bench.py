@@ -40,7 +40,9 @@ TRAFFIC = {"sources_sha256": "9c9a5e7010b98db45a26a02cd4e3df9634052a077dc70048cb
            "fetch_kib": 23118.25, "write_kib": 8230.51,
            "fetch_scale": 262144 / 131084, "write_scale": 262144 / 262144, "n": 1 << 20}
 KERNEL_SOURCES = ("paper_2605_26659_amd/csrc/finom_kernels.hpp",
-                  "paper_2605_26659_amd/csrc/finom_device.hpp")
+                  "paper_2605_26659_amd/csrc/finom_device.hpp",
+                  "paper_2605_26659_amd/csrc/finom_fast.hpp",
+                  "paper_2605_26659_amd/csrc/finom_types.hpp")
 
 
 def kernel_sources_digest():
@@ -332,8 +334,8 @@ def main():
     achieved = per_sweep_bytes / (sweep_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.n),
-                "kernel": "k_sweep, both half-iteration variants (K^T phi with the fused "
-                          "marginal check, K psi), averaged over the loop's launches",
+                "kernel": "the loop's sweeps, both half-iteration variants (K^T phi with the "
+                          "fused marginal check, K psi), averaged over the loop's launches",
                 "avg_sweep_us": sweep_ms * 1e3,
                 "algorithmic_bytes_per_sweep": per_sweep_bytes}
 

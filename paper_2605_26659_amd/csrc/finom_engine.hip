@@ -38,6 +38,7 @@ struct ArrTask {
     const double* a;
     long long n;
     double* la;          // masses: log2 of each entry
+    Ext<float>* eout;    // meshes: 2^{c kappa} of each entry (optional)
     double* fill;        // optional: potential initialisation
     long long nfill;
     double fill_v;
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_arrays(const ArrTask* __restri
                 if (!(fabs(v) * t.kappa < kCoordLimit)) bad |= (v == v && fabs(v) != __builtin_inf()) ? 4 : 1;
                 if (k + 1 < t.n && v > t.a[k + 1]) bad |= 1;
             }
+            if (t.eout && fabs(v) * t.kappa < kCoordLimit) t.eout[k] = split_exp2(v * t.kappa);
         } else {
             if (!(v > 0.0) || v == __builtin_inf()) bad |= 2;
             t.la[k] = log2(v);
@@ -313,6 +315,10 @@ JobPlan plan_job(const JobDesc& d, int precision)
     p.o_G0 = take(8 * p.nb);
     p.o_G1 = take(8 * p.nb);
     if (d.dim == 2) p.o_S = take(8 * p.s_len);
+    if (d.dim == 1 && precision == 1) {
+        p.o_Ex = take(sizeof(Ext<float>) * p.na);
+        p.o_Ey = take(sizeof(Ext<float>) * p.nb);
+    }
     for (int a = 0; a < d.dim; ++a) {
         p.cfg[a] = tuned_cfg(precision, p.R[a] + p.C[a]);
         const int T = kCfgs[p.cfg[a]].T();
@@ -336,6 +342,8 @@ void Job::bind()
     G[0] = (double*)(mem + p.o_G0);
     G[1] = (double*)(mem + p.o_G1);
     S = d.dim == 2 ? (double*)(mem + p.o_S) : nullptr;
+    Ex = p.o_Ex ? (Ext<float>*)(mem + p.o_Ex) : nullptr;
+    Ey = p.o_Ey ? (Ext<float>*)(mem + p.o_Ey) : nullptr;
     const int Tc = cost_tile_size();
     for (int a = 0; a < d.dim; ++a) {
         const double* xr = a == 0 ? d.x1 : d.y1;
@@ -412,7 +420,8 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
         Job* j = jobs[i];
         const JobDesc& d = j->d;
         const double kappa = 1.0 / (d.eps * kLn2);
-        auto mesh = [&](const double* a, long long n) {
+        auto mesh = [&](const double* a, long long n, Ext<float>* eout) {
+            if (!checks && !eout) return;
             ArrTask t;
             memset(&t, 0, sizeof(t));
             t.a = a;
@@ -420,17 +429,17 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
             t.kind = 0;
             t.job = i;
             t.kappa = kappa;
-            t.checks = 1;
+            t.checks = checks ? 1 : 0;
+            t.eout = eout;
             at.push_back(t);
             at_n.push_back(n);
         };
-        if (checks) {
-            mesh(d.x1, d.n1);
-            mesh(d.x2, d.n2);
-            if (d.dim == 2) {
-                mesh(d.y1, d.m1);
-                mesh(d.y2, d.m2);
-            }
+        const bool want_fast = d.dim == 1 && j->Ex && fast_allowed();
+        mesh(d.x1, d.n1, want_fast ? j->Ex : nullptr);
+        mesh(d.x2, d.n2, want_fast ? j->Ey : nullptr);
+        if (d.dim == 2) {
+            mesh(d.y1, d.m1, nullptr);
+            mesh(d.y2, d.m2, nullptr);
         }
         auto mass = [&](const double* a, long long n, double* la, double* fill, int slot) {
             ArrTask t;
@@ -489,12 +498,54 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
     hipLaunchKernelGGL(k_setup_zeta, dim3(fz.back()), dim3(kBlock), 0, s_, d_pt, d_fz, 2 * npt);
     hipLaunchKernelGGL(k_setup_tiles, dim3(ft.back()), dim3(kBlock), 0, s_, d_pt, d_ft, npt);
     HIPCHK(hipGetLastError());
+    // fast-sweep eligibility of the 1D jobs (the static range bound of every tile)
+    std::vector<BoundTask> bt;
+    std::vector<long long> bt_n;
+    for (int i = 0; i < nj; ++i) {
+        Job* j = jobs[i];
+        if (!(j->d.dim == 1 && j->Ex && fast_allowed())) continue;
+        const double kappa = 1.0 / (j->d.eps * kLn2);
+        for (int dir = 0; dir < 2; ++dir) {
+            // dir 0: K psi, columns y with masses v; dir 1: K^T phi, columns x with masses u
+            const Part& pp = dir == 0 ? j->pk[0] : j->pkt[0];
+            BoundTask b;
+            memset(&b, 0, sizeof(b));
+            b.yc = pp.yc;
+            b.lmass = dir == 0 ? j->lv : j->lu;
+            b.trs = pp.trs;
+            b.R = pp.R;
+            b.C = pp.C;
+            b.kappa = kappa;
+            b.T = pp.T;
+            b.ntiles = pp.ntiles;
+            b.flag = i;
+            bt.push_back(b);
+            bt_n.push_back(pp.ntiles);
+        }
+    }
+    int* fflags = al.dev<int>(nj);
+    int* hfflags = al.host<int>(nj);
+    HIPCHK(hipMemsetAsync(fflags, 0, sizeof(int) * nj, s_));
+    if (!bt.empty()) {
+        std::vector<int> fb(bt.size() + 1, 0);
+        for (size_t q = 0; q < bt.size(); ++q) fb[q + 1] = fb[q] + (int)bt_n[q];
+        const BoundTask* d_bt = upload_vec(al, bt);
+        const int* d_fb = upload_vec(al, fb);
+        hipLaunchKernelGGL((k_tile_bounds<kBlock>), dim3(fb.back()), dim3(kBlock), 0, s_, d_bt, d_fb, (int)bt.size(),
+                           fflags);
+        HIPCHK(hipGetLastError());
+    }
     al.uploaded();
     for (Job* j : jobs) j->status = FINOM_OK;
-    if (!checks) return;
-    HIPCHK(hipMemcpyAsync(hflags, flags, sizeof(int) * nj, hipMemcpyDeviceToHost, s_));
-    HIPCHK(hipMemcpyAsync(hsums, sums, sizeof(double) * 2 * nj, hipMemcpyDeviceToHost, s_));
+    HIPCHK(hipMemcpyAsync(hfflags, fflags, sizeof(int) * nj, hipMemcpyDeviceToHost, s_));
+    if (checks) {
+        HIPCHK(hipMemcpyAsync(hflags, flags, sizeof(int) * nj, hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipMemcpyAsync(hsums, sums, sizeof(double) * 2 * nj, hipMemcpyDeviceToHost, s_));
+    }
     HIPCHK(hipStreamSynchronize(s_));
+    for (int i = 0; i < nj; ++i)
+        jobs[i]->fast = jobs[i]->d.dim == 1 && jobs[i]->Ex && fast_allowed() && hfflags[i] == 0;
+    if (!checks) return;
     for (int i = 0; i < nj; ++i) {
         const int f = hflags[i];
         const double su = hsums[2 * i], sv = hsums[2 * i + 1];
@@ -574,7 +625,8 @@ void Engine::rebuild()
     // split by single- / multi-tile lines: multi-tile lines run the tile
     // aggregate kernel first, which then takes their stop decision, so one
     // launch must not mix the two kinds. 1D stages pass aggregates through
-    // the update epilogue and need no split.
+    // the update epilogue; their split separates fast-sweep lines from the
+    // others.
     struct Group {
         int stage, cfg, split;
         Sweep* sw[2];
@@ -592,6 +644,7 @@ void Engine::rebuild()
             g.sw[b]->kind = 0;
             g.sw[b]->cfg = cfg;
             g.sw[b]->epi = kStageEpi[stage];
+            g.sw[b]->fast = (stage == S1_KT || stage == S1_K) && split == 1;
         }
         groups.push_back(g);
         gidx[key] = (int)groups.size() - 1;
@@ -605,7 +658,8 @@ void Engine::rebuild()
         const double eps = d.eps;
         if (d.dim == 1) {
             const long long n = d.n1, m = d.n2;
-            const int gt = group(S1_KT, j->p.cfg[0]), gk = group(S1_K, j->p.cfg[0]);
+            const int fs = j->fast ? 1 : 0;
+            const int gt = group(S1_KT, j->p.cfg[0], fs), gk = group(S1_K, j->p.cfg[0], fs);
             const int T = kCfgs[j->p.cfg[0]].T();
             for (int b = 0; b < 2; ++b) {
                 LineDesc a = make_line(d.x2, m, d.x1, n, j->pkt[0].zeta, j->pkt[0].trs, T, eps);
@@ -622,6 +676,12 @@ void Engine::rebuild()
                 c.a0 = j->lu;
                 c.prob = j->slot;
                 c.dec_part_off = -1;
+                if (j->fast) {
+                    a.er = j->Ey;
+                    a.ec = j->Ex;
+                    c.er = j->Ex;
+                    c.ec = j->Ey;
+                }
                 if (b == 0) {
                     chk[ji] = LineRange{gt, groups[gt].sw[0]->lines.size(), 1};
                     dcd[ji] = LineRange{gk, groups[gk].sw[0]->lines.size(), 1};
@@ -684,7 +744,7 @@ void Engine::rebuild()
     for (int gi : order) {
         Group& gt = groups[gi];
         if (gt.stage != S1_KT) continue;
-        Group& gk = groups[gidx[std::make_tuple((int)S1_K, gt.cfg, 0)]];
+        Group& gk = groups[gidx[std::make_tuple((int)S1_K, gt.cfg, gt.split)]];
         const int mt = gt.sw[0]->multi_tiles();
         if (mt == 0) continue;
         void* agg_kt = al.dev<char>((size_t)mt * 2 * eb);

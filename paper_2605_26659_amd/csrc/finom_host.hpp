@@ -11,6 +11,7 @@
 #include <new>
 #include <vector>
 
+#include "finom_fast.hpp"
 #include "finom_kernels.hpp"
 
 namespace finom {
@@ -166,6 +167,7 @@ struct Sweep {
     int cfg = 1;
     int epi = EPI_STORE_LOG2;
     bool agg_from_prev = false;
+    bool fast = false;                     // FP32 fast sweeps (lines carry er / ec)
     void* agg_next = nullptr;
     void* agg_buf = nullptr;               // preassigned aggregate buffer (optional)
     SweepDev dev;
@@ -264,6 +266,14 @@ void enqueue_fill(double* a, long long n, double v, hipStream_t s);
 void enqueue_scale(const double* a, double* b, long long n, double f, hipStream_t s);
 
 int map_exception();
+
+// Fast sweeps are used for eligible FP32 lines unless FINOM_FAST=0.
+bool fast_allowed();
+// Classifies the 1D pair (x: n, y: m) on partition pk (rows x) and its
+// transpose pkt for the fast sweeps; fills 2^{c kappa} for both meshes when
+// eligible. Synchronises the stream. Returns true when the pair is eligible.
+bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, const double* lu, const double* lv, double eps,
+                   Ext<float>** Ex, Ext<float>** Ey, hipStream_t s);
 
 constexpr double kCoordLimit = 33554432.0;   // 2^25: bound on |coordinate| / (eps ln 2)
 

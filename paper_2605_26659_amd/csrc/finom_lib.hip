@@ -274,6 +274,37 @@ static void launch_t(const Sweep& sw, ProbState* ps, double* partial, const doub
         case 6: launch_t<M, B, I, IN_LIN, EPI_STORE_LIN, false, false>(sw, ps, partial, dec, parity, ao, s); return;   \
     }
 
+template <int B, int I, int EPI, bool NA>
+static void launch_fast_t(const Sweep& sw, ProbState* ps, double* partial, const double* dec, int parity,
+                          bool agg_only, hipStream_t s)
+{
+    const SweepDev& d = sw.dev;
+    if (d.nwork == 0) return;
+    if (d.nwork_multi > 0 && (agg_only || !sw.agg_from_prev))
+        hipLaunchKernelGGL((k_tile_aggregate_fast<B, I>), dim3(d.nwork_multi), dim3(B), 0, s, d.work_multi, d.lines,
+                           ps, (Ext<float>*)d.agg);
+    if (!agg_only)
+        hipLaunchKernelGGL((k_sweep_fast<B, I, EPI, NA>), dim3(d.nwork), dim3(B), 0, s, d.work, d.lines, ps,
+                           (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next);
+    HIPCHK(hipGetLastError());
+}
+
+template <int B, int I>
+static void dispatch_fast(const Sweep& sw, ProbState* ps, double* partial, const double* dec, int parity, bool ao,
+                          hipStream_t s)
+{
+    const bool na = sw.agg_next != nullptr;
+    if (sw.epi == EPI_UPDATE) {
+        if (na) launch_fast_t<B, I, EPI_UPDATE, true>(sw, ps, partial, dec, parity, ao, s);
+        else launch_fast_t<B, I, EPI_UPDATE, false>(sw, ps, partial, dec, parity, ao, s);
+    } else if (sw.epi == EPI_UPDATE_CHECK) {
+        if (na) launch_fast_t<B, I, EPI_UPDATE_CHECK, true>(sw, ps, partial, dec, parity, ao, s);
+        else launch_fast_t<B, I, EPI_UPDATE_CHECK, false>(sw, ps, partial, dec, parity, ao, s);
+    } else {
+        throw HipError{hipErrorInvalidValue};
+    }
+}
+
 static int variant_of(int inm, int epi, bool next_agg)
 {
     if (inm == IN_NAT && epi == EPI_STORE_NAT) return 5;
@@ -301,6 +332,16 @@ static void dispatch(int precision, int inm, const Sweep& sw, ProbState* ps, dou
         else
             launch_t<double, kCostBlock, kCostIpt, IN_LOG2, EPI_STORE_LOG2, false, false>(sw, ps, partial, dec, parity, ao, s);
         return;
+    }
+    if (sw.fast) {
+        if (precision != 1 || inm != IN_LOG2) throw HipError{hipErrorInvalidValue};
+        switch (sw.cfg) {
+            case 0: dispatch_fast<256, 4>(sw, ps, partial, dec, parity, ao, s); return;
+            case 1: dispatch_fast<256, 8>(sw, ps, partial, dec, parity, ao, s); return;
+            case 2: dispatch_fast<512, 8>(sw, ps, partial, dec, parity, ao, s); return;
+            case 3: dispatch_fast<128, 4>(sw, ps, partial, dec, parity, ao, s); return;
+        }
+        throw HipError{hipErrorInvalidValue};
     }
     const int variant = variant_of(inm, sw.epi, sw.agg_next != nullptr);
     if (variant < 0) throw HipError{hipErrorInvalidValue};
@@ -465,6 +506,68 @@ void enqueue_fill(double* a, long long n, double v, hipStream_t s)
 void enqueue_scale(const double* a, double* b, long long n, double f, hipStream_t s)
 {
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, b, n, f);
+}
+
+// 2^{c kappa} per mesh point as (mantissa in [1, 2), exponent)
+__global__ void k_exp_coords(const double* __restrict__ c, long long n, double kappa, Ext<float>* __restrict__ E)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    E[i] = split_exp2(c[i] * kappa);
+}
+
+bool fast_allowed()
+{
+    const char* e = getenv("FINOM_FAST");
+    return !(e && e[0] == '0');
+}
+
+bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, const double* lu, const double* lv, double eps,
+                   Ext<float>** Ex, Ext<float>** Ey, hipStream_t s)
+{
+    *Ex = *Ey = nullptr;
+    const double kappa = 1.0 / (eps * kLn2);
+    BoundTask* ht = al.host<BoundTask>(2);
+    int* hfirst = al.host<int>(3);
+    int* hflag = al.host<int>(1);
+    memset(ht, 0, 2 * sizeof(BoundTask));
+    // K psi: columns y with masses v; K^T phi: columns x with masses u
+    ht[0].yc = pk.yc;
+    ht[0].lmass = lv;
+    ht[0].trs = pk.trs;
+    ht[0].R = pk.R;
+    ht[0].C = pk.C;
+    ht[0].kappa = kappa;
+    ht[0].T = pk.T;
+    ht[0].ntiles = pk.ntiles;
+    ht[1].yc = pkt.yc;
+    ht[1].lmass = lu;
+    ht[1].trs = pkt.trs;
+    ht[1].R = pkt.R;
+    ht[1].C = pkt.C;
+    ht[1].kappa = kappa;
+    ht[1].T = pkt.T;
+    ht[1].ntiles = pkt.ntiles;
+    hfirst[0] = 0;
+    hfirst[1] = pk.ntiles;
+    hfirst[2] = pk.ntiles + pkt.ntiles;
+    BoundTask* dt = al.dev<BoundTask>(2);
+    int* dfirst = al.dev<int>(3);
+    int* dflag = al.dev<int>(1);
+    HIPCHK(hipMemcpyAsync(dt, ht, 2 * sizeof(BoundTask), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dfirst, hfirst, 3 * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int), s));
+    hipLaunchKernelGGL((k_tile_bounds<kBlock>), dim3(hfirst[2]), dim3(kBlock), 0, s, dt, dfirst, 2, dflag);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hflag[0]) return false;
+    *Ex = al.dev<Ext<float>>(pk.R);
+    *Ey = al.dev<Ext<float>>(pk.C);
+    hipLaunchKernelGGL(k_exp_coords, dim3(blocks_for(pk.R)), dim3(kBlock), 0, s, pk.xr, pk.R, kappa, *Ex);
+    hipLaunchKernelGGL(k_exp_coords, dim3(blocks_for(pk.C)), dim3(kBlock), 0, s, pk.yc, pk.C, kappa, *Ey);
+    HIPCHK(hipGetLastError());
+    return true;
 }
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -751,6 +854,9 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         const Part pk = make_part(al, x, n, y, m, T, s);      // K psi:   rows x, columns y
         const Part pkt = make_part_transposed(al, pk, s);     // K^T phi: rows y, columns x
         const Part pc = make_part_like(al, pk, cost_tile_size(), s);
+        Ext<float>* Ex = nullptr;
+        Ext<float>* Ey = nullptr;
+        const bool fast = o.precision == 1 && fast_allowed() && setup_fast_1d(al, pk, pkt, lu, lv, eps, &Ex, &Ey, s);
 
         // state: phi = 1/n, psi = 1/m (log2 units)
         double* F = al.dev<double>(n);
@@ -776,7 +882,9 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             kt[b].agg_next = agg_k;
             LineDesc a = make_line(y, m, x, n, pkt.zeta, pkt.trs, T, eps);
             a.gin = F; a.out = G[1 - b]; a.a0 = lv; a.a1 = v; a.a2 = G[b];
+            a.er = Ey; a.ec = Ex;
             a.dec_part_off = -1;
+            kt[b].fast = kk[b].fast = fast;
             kt[b].lines.push_back(a);
             assign_parts(kt[b], 0);
             kk[b].epi = EPI_UPDATE;
@@ -786,6 +894,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             kk[b].agg_next = agg_kt;
             LineDesc c = make_line(x, n, y, m, pk.zeta, pk.trs, T, eps);
             c.gin = G[1 - b]; c.out = F; c.a0 = lu;
+            c.er = Ex; c.ec = Ey;
             kk[b].lines.push_back(c);
             set_decision(kk[b], 0, pkt.ntiles);
             upload_sweep(al, kt[b], eb);

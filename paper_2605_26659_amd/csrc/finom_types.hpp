@@ -18,6 +18,8 @@ struct LineDesc {
     const double* a0;      // epilogue operand, element i at a0[i * ostride]
     const double* a1;      // epilogue operand
     const double* a2;      // epilogue operand
+    const void* er;        // fast sweeps: 2^{xr_i kappa} per row (Ext<float>)
+    const void* ec;        // fast sweeps: 2^{yc_j kappa} per column (Ext<float>)
     long long R, C;
     long long gstride, ostride;
     double kappa;          // 1 / (eps ln 2)
