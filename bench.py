@@ -26,9 +26,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per grid point per iteration with FP64 state and
-# coordinates: K^T phi half reads f, x, y, v, g_old and writes g (16n + 32m);
-# K psi half reads g, y, x, u and writes f (24n + 16m).
-BYTES_KT = (16, 32)
+# coordinates: the K^T phi half reads f, x, y, log2 v and g_old and writes g
+# (16n + 24m; the check's weight v is 2^{log2 v}); the K psi half reads g,
+# y, x, log2 u and writes f (24n + 16m).
+BYTES_KT = (16, 24)
 BYTES_K = (24, 16)
 
 # HBM traffic of the two sweep kernels measured with rocprofv3 FETCH_SIZE and
@@ -36,8 +37,8 @@ BYTES_K = (24, 16)
 # each scaled by the counter's reading for a plain device copy of known size.
 # Valid only for the kernel sources whose digest is recorded beside them;
 # after any change to those sources the traffic is reported as null.
-TRAFFIC = {"sources_sha256": "9c9a5e7010b98db45a26a02cd4e3df9634052a077dc70048cbdf79fbbda754c5",
-           "fetch_kib": 23118.25, "write_kib": 8230.51,
+TRAFFIC = {"sources_sha256": "df8c12b9d2fec292f3c97345f1129789419172251e3eb7e63e78d97a38a865b7",
+           "fetch_kib": 20800.75, "write_kib": 8218.30,
            "fetch_scale": 262144 / 131084, "write_scale": 262144 / 262144, "n": 1 << 20}
 KERNEL_SOURCES = ("paper_2605_26659_amd/csrc/finom_kernels.hpp",
                   "paper_2605_26659_amd/csrc/finom_device.hpp",
@@ -79,6 +80,8 @@ def parse():
                     help="full serving sweep (several arrival rates and the nominal 2000/s)")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving sample")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2605_26659_amd", "tune_gfx950.txt"),
+                    help="tile-shape table: read if present, else tuned here and written")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized FP64 buffer 10 times (counter calibration)")
     return ap.parse_args()
@@ -293,7 +296,7 @@ def main():
     if not args.no_autotune:
         from paper_2605_26659_amd import finom_autotune
         for p in (1, 0):
-            finom_autotune(p)
+            finom_autotune(p, args.tune_cache or None)
 
     prob = wl.config_graded_1d(args.n, args.eps, tol=args.tol)
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")

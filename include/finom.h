@@ -224,6 +224,10 @@ const char* finom_strerror(int status);
  * with running calls. */
 void finom_release(void);
 
+/* Detail of the last FINOM_E_HIP / FINOM_E_NOMEM raised on the calling host
+ * thread (the HIP error string and code); empty if none. Static storage. */
+const char* finom_last_error(void);
+
 /* Library version string, e.g. "finom-gfx950 0.1". */
 const char* finom_version(void);
 

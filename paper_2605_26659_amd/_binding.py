@@ -29,7 +29,13 @@ FINOM_E_NUMERIC = -7
 class FinomError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__(f"{where}: {strerror(status)} (status {status})")
+        detail = ""
+        if status in (FINOM_E_HIP, FINOM_E_NOMEM):
+            try:
+                detail = load().finom_last_error().decode()
+            except Exception:
+                detail = ""
+        super().__init__(f"{where}: {strerror(status)} (status {status})" + (f": {detail}" if detail else ""))
 
 
 class Opts(C.Structure):
@@ -96,6 +102,13 @@ def load(path: os.PathLike | None = None):
     if not p.exists():
         raise RuntimeError(f"{p} is missing: build it with `python -m paper_2605_26659_amd.build` "
                            "(there is no CPU fallback)")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so the process holds one runtime (two runtimes in one process do not
+    # both see the device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(str(p))
     L.finom_matvec.argtypes = [_vp, _i64, _vp, _i64, _d, _vp, _vp, C.POINTER(Opts), _vp]
     L.dense_matvec.argtypes = L.finom_matvec.argtypes
@@ -104,6 +117,7 @@ def load(path: os.PathLike | None = None):
     L.finom_strerror.restype = C.c_char_p
     L.finom_strerror.argtypes = [C.c_int]
     L.finom_version.restype = C.c_char_p
+    L.finom_last_error.restype = C.c_char_p
     L.finom_release.restype = None
     if hasattr(L, "sinkhorn_w1_2d"):
         L.sinkhorn_w1_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _d, _d,

@@ -189,8 +189,73 @@ __device__ __forceinline__ void ref_add(RefAcc& a, Ext<float> v)
     a.s += ldexp_m(v.m, v.e - a.r);
 }
 
+// Wave-level total of per-lane (sum, exponent) pairs against the wave's
+// largest exponent; the result is valid in every lane.
+__device__ __forceinline__ Ext<float> wave_total_ref(RefAcc a)
+{
+    const int r = wave_max_i(a.r);
+    const float v = ldexp_m(a.s, a.r - r);
+    return Ext<float>{readlane_f(wave_incl_prefix_f(v), kWave - 1), r};
+}
+
+// Per-wave results of two totals go to LDS (slot wid of s_f / s_i and
+// NW + wid); after a barrier every thread combines them with block_total_read.
+template <int BLOCK>
+__device__ __forceinline__ void block_total2_write(RefAcc a, RefAcc b, float* s_f, int* s_i)
+{
+    constexpr int NW = BLOCK / kWave;
+    const Ext<float> wa = wave_total_ref(a), wb = wave_total_ref(b);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const int wid = threadIdx.x / kWave;
+        s_f[wid] = wa.m;
+        s_i[wid] = wa.e;
+        s_f[NW + wid] = wb.m;
+        s_i[NW + wid] = wb.e;
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ Ext<float> block_total_read(const float* s_f, const int* s_i)
+{
+    constexpr int NW = BLOCK / kWave;
+    int r = s_i[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) r = max(r, s_i[w]);
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += ldexp_m(s_f[w], s_i[w] - r);
+    return Ext<float>{v, r};
+}
+
 // ------------------------------------------------------------ fast sweep
 // Lines with unit strides (1D problems) whose tiles passed k_tile_bounds.
+// Thread t owns the slots k = t + q BLOCK (q < IPT) of the tile's elements
+// listed as [nc columns, nr rows]; column slots stage their terms in LDS, the
+// columns are scanned in fixed chunks of IPT per thread, and row slots read
+// the scans at their dividing index.
+
+struct FastGeom {
+    long long r0, c0;
+    int nr, nc;
+};
+
+// The tile's row and column ranges, clamped as in tile_geom (a corrupt
+// partition gives wrong values, never an access out of range), with at most
+// T elements in all.
+__device__ __forceinline__ FastGeom fast_geom(const LineDesc& L, int tile, int T, int ts0, int ts1)
+{
+    const long long m0 = (long long)tile * T;
+    long long m1 = m0 + T;
+    if (m1 > L.R + L.C) m1 = L.R + L.C;
+    const long long r0 = min(max((long long)ts0, 0LL), L.R);
+    long long r1 = min(max((long long)ts1, r0), L.R);
+    const long long c0 = min(max(m0 - r0, 0LL), L.C);
+    long long c1 = min(max(m1 - r1, c0), L.C);
+    if (c1 - c0 > T) c1 = c0 + T;
+    if ((r1 - r0) + (c1 - c0) > T) r1 = r0 + (T - (c1 - c0));
+    return FastGeom{r0, c0, (int)(r1 - r0), (int)(c1 - c0)};
+}
+
 template <int BLOCK, int IPT, int EPI, bool NEXT_AGG>
 __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict__ work,
                                                      const LineDesc* __restrict__ lines,
@@ -200,72 +265,102 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
                                                      const double* __restrict__ dec_partial, int parity,
                                                      Ext<float>* __restrict__ agg_next)
 {
+    static_assert(IPT % 4 == 0, "chunks are read as float4");
     constexpr int T = BLOCK * IPT;
     constexpr int NW = BLOCK / kWave;
     constexpr bool CHECK = (EPI == EPI_UPDATE_CHECK);
-    __shared__ float s_l[T + 1];
-    __shared__ float s_u[T + 1];
-    __shared__ float s_f[2 * NW];
-    __shared__ int s_i[2 * NW];
-    __shared__ double s_red[NW];
+    __shared__ __align__(16) float s_l[T + 4];
+    __shared__ __align__(16) float s_u[T + 4];
+    __shared__ float s_f[4 * NW];
+    __shared__ int s_i[4 * NW];
+    __shared__ double s_d[NW];
 
     const WorkItem w = work[blockIdx.x];
     const LineDesc L = lines[w.line];
     ProbState* P = ps + L.prob;
     if (P->done) return;
-    const TileGeom<double> tg = tile_geom(L, w.tile, T);
-    const int nc = (int)(tg.c1 - tg.c0);
-    const int nr = (int)(tg.r1 - tg.r0);
-    const int ncq = (nc + BLOCK - 1) / BLOCK;
-    const int nrq = (nr + BLOCK - 1) / BLOCK;
+    const FastGeom tg = fast_geom(L, w.tile, T, L.trs[w.tile], L.trs[w.tile + 1]);
+    const int nc = tg.nc;
+    const int nr = tg.nr;
     const bool decide = dec_partial && L.dec_part_off >= 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
     const double* __restrict__ gin = L.gin + tg.c0;
     const Ext<float>* __restrict__ EC = (const Ext<float>*)L.ec + tg.c0;
     const Ext<float>* __restrict__ ER = (const Ext<float>*)L.er + tg.r0;
     const int* __restrict__ ZT = L.zeta + tg.r0;
     const double* __restrict__ A0 = L.a0 + tg.r0;
+    const bool empty = nc + nr == 0;   // only with a corrupt partition
 
-    // ---- A. every load of the tile first (tail lanes re-read an in-range element)
-    double gq[IPT], a0q[IPT];
-    Ext<float> ecq[IPT], erq[IPT];
-    int zq[IPT];
+    // ---- A. every load of the tile first. Slot k < nc is column k, slot
+    // nc <= k < nc + nr is row k - nc; idle slots re-read an element in range.
+    Ext<float> Eq[IPT];
+    double Dq[IPT];
+    int Zq[IPT];
+    if (!empty) {
 #pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-        if (q >= ncq) break;
-        const int j = min((int)threadIdx.x + q * BLOCK, nc - 1);
-        gq[q] = gin[j];
-        ecq[q] = EC[j];
+        for (int q = 0; q < IPT; ++q) {
+            const int k = threadIdx.x + q * BLOCK;
+            const bool col = (k < nc) || nr == 0;
+            const int ic = min(k, nc - 1);
+            const int ir = min(k - nc, nr - 1);
+            Eq[q] = col ? EC[ic] : ER[ir];
+            Dq[q] = col ? gin[ic] : A0[ir];
+            Zq[q] = col ? 0 : ZT[ir];
+        }
     }
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-        if (q >= nrq) break;
-        const int i = min((int)threadIdx.x + q * BLOCK, nr - 1);
-        erq[q] = ER[i];
-        zq[q] = ZT[i];
-        a0q[q] = A0[i];
-    }
-    // reference exponents: the tile's first column terms
     double g0 = 0.0;
     Ext<float> E0 = ext_zero<float>();
     if (nc > 0) {
         g0 = gin[0];
         E0 = EC[0];
     }
-    Ext<float> cl = ext_zero<float>(), cu = ext_zero<float>();
+    RefAcc cl{0.f, kZeroExp}, cu{0.f, kZeroExp};
     if (L.ntiles > 1) {
+        Ext<float> al = ext_zero<float>(), au = ext_zero<float>();
         for (int t = threadIdx.x; t < L.ntiles; t += BLOCK) {
             const Ext<float>* a = agg + (long long)(L.agg_base + t) * 2;
-            if (t < w.tile) cl = ext_add(cl, a[0]);
-            else if (t > w.tile) cu = ext_add(cu, a[1]);
+            if (t < w.tile) al = ext_add(al, a[0]);
+            else if (t > w.tile) au = ext_add(au, a[1]);
         }
+        cl = RefAcc{al.m, al.e};
+        cu = RefAcc{au.m, au.e};
     }
     double dv = 0.0;
     if (decide)
         for (int k = threadIdx.x; k < L.dec_nparts; k += BLOCK) dv += dec_partial[L.dec_part_off + k];
 
-    // ---- B. stop decision of the loop head (uniform across the block)
+    // ---- C. column terms against the tile's first column, to LDS
+    int r0l = kZeroExp, r0u = kZeroExp;
+    if (nc > 0) {
+        const Ext<float> e0 = split_exp2(g0);
+        r0l = e0.e + E0.e;
+        r0u = e0.e - E0.e;
+    }
+    if (!empty) {
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            const int k = threadIdx.x + q * BLOCK;
+            if (k < nc) {
+                const Ext<float> eg = split_exp2(Dq[q]);
+                const Ext<float> E = Eq[q];
+                s_l[k] = ldexp_m(eg.m * E.m, eg.e + E.e - r0l);
+                s_u[k] = ldexp_m(eg.m * __builtin_amdgcn_rcpf(E.m), eg.e - E.e - r0u);
+            }
+        }
+    }
+    // carries and the stop decision share the next barrier
+    if (L.ntiles > 1) block_total2_write<BLOCK>(cl, cu, s_f + 2 * NW, s_i + 2 * NW);
     if (decide) {
-        const double err = block_sum_f64<BLOCK>(dv, s_red);
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) dv += __shfl_down(dv, d, kWave);
+        if (lane == 0) s_d[wid] = dv;
+    }
+    __syncthreads();
+    if (decide) {
+        double err = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) err += s_d[v];
         const long long l = P->cnt[parity];
         const bool stop = (l >= P->itr_max) || !(err > P->tol);
         if (L.writes_state && w.tile == 0 && threadIdx.x == 0) {
@@ -281,46 +376,56 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
         }
         if (stop) return;
     }
-
-    // ---- C. carries, references, column terms straight to LDS
-    Ext<float> CL = ext_zero<float>(), CU = ext_zero<float>();
-    if (L.ntiles > 1) block_total2_ref<BLOCK, 1>(&cl, &cu, CL, CU, s_i, s_f);
-    int rl = CL.e, ru = CU.e;
-    if (nc > 0) {
-        const Ext<float> e0 = split_exp2(g0);
-        rl = max(rl, e0.e + E0.e);
-        ru = max(ru, e0.e - E0.e);
+    if (empty) {
+        if (threadIdx.x == 0) {
+            if (CHECK) partial[L.part_base + w.tile] = 0.0;
+            if (NEXT_AGG && L.ntiles > 1) {
+                agg_next[(long long)(L.agg_base + w.tile) * 2 + 0] = ext_zero<float>();
+                agg_next[(long long)(L.agg_base + w.tile) * 2 + 1] = ext_zero<float>();
+            }
+        }
+        return;
     }
+    Ext<float> CL = ext_zero<float>(), CU = ext_zero<float>();
+    if (L.ntiles > 1) {
+        CL = block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW);
+        CU = block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW);
+    }
+    // row references: the larger of the first column's and the carry's exponent
+    const int rl = max(r0l, CL.e), ru = max(r0u, CU.e);
+    const float cl_rel = ldexp_m(CL.m, CL.e - rl), cu_rel = ldexp_m(CU.m, CU.e - ru);
+    const int shl = r0l - rl, shu = r0u - ru;   // <= 0: rescales the in-tile sums
+    double dqc[IPT];
+    if (CHECK) {
+        // old potential of each row for the marginal-error check, issued
+        // before the scan (the weight v = 2^{log2 v} comes from the row's a0)
 #pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-        if (q >= ncq) break;
-        const int k = threadIdx.x + q * BLOCK;
-        if (k < nc) {
-            const Ext<float> eg = split_exp2(gq[q]);
-            const Ext<float> E = ecq[q];
-            s_l[k] = ldexp_m(eg.m * E.m, eg.e + E.e - rl);
-            s_u[k] = ldexp_m(eg.m * __builtin_amdgcn_rcpf(E.m), eg.e - E.e - ru);
+        for (int q = 0; q < IPT; ++q) {
+            const int k = threadIdx.x + q * BLOCK;
+            dqc[q] = (k >= nc && k < nc + nr) ? L.a2[tg.r0 + (k - nc)] : 0.0;
         }
     }
-    const float cl_rel = ldexp_m(CL.m, CL.e - rl);
-    const float cu_rel = ldexp_m(CU.m, CU.e - ru);
-    __syncthreads();
 
-    // ---- D. blocked scan: thread owns columns [tid*ncq, tid*ncq + ncq)
+    // ---- D. scan in fixed chunks: thread t owns columns [t IPT, t IPT + IPT)
     {
         float vl[IPT], vu[IPT];
+        const int base = threadIdx.x * IPT;
+#pragma unroll
+        for (int q = 0; q < IPT; q += 4) {
+            const float4 a = *reinterpret_cast<const float4*>(s_l + base + q);
+            const float4 b = *reinterpret_cast<const float4*>(s_u + base + q);
+            vl[q] = a.x; vl[q + 1] = a.y; vl[q + 2] = a.z; vl[q + 3] = a.w;
+            vu[q] = b.x; vu[q + 1] = b.y; vu[q + 2] = b.z; vu[q + 3] = b.w;
+        }
         float sl = 0.f, su = 0.f;
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
-            if (q >= ncq) break;
-            const int idx = threadIdx.x * ncq + q;
-            vl[q] = (idx < nc) ? s_l[idx] : 0.f;
-            vu[q] = (idx < nc) ? s_u[idx] : 0.f;
+            const bool live = base + q < nc;
+            vl[q] = live ? vl[q] : 0.f;
+            vu[q] = live ? vu[q] : 0.f;
             sl += vl[q];
             su += vu[q];
         }
-        const int lane = threadIdx.x & (kWave - 1);
-        const int wid = threadIdx.x / kWave;
         const float il = wave_incl_prefix_f(sl);
         const float iu = wave_incl_suffix_f(su);
         if (lane == kWave - 1) s_f[wid] = il;
@@ -331,23 +436,28 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
         for (int v = wid + 1; v < NW; ++v) suf += s_f[NW + v];
         float run = pre + dpp_f<0x138>(il);    // wave_shr:1 -> exclusive prefix
         float runu = dpp_f<0x130>(iu) + suf;   // wave_shl:1 -> exclusive suffix
-        const float tot = pre + readlane_f(il, kWave - 1);
+        // in place: vl becomes the exclusive prefix, vu the inclusive suffix
 #pragma unroll
         for (int q = 0; q < IPT; ++q) {
-            if (q >= ncq) break;
-            const int idx = threadIdx.x * ncq + q;
-            if (idx < nc) s_l[idx] = run;
-            run += vl[q];
+            const float t = vl[q];
+            vl[q] = run;
+            run += t;
         }
 #pragma unroll
         for (int q = IPT - 1; q >= 0; --q) {
-            if (q >= ncq) continue;
-            const int idx = threadIdx.x * ncq + q;
             runu += vu[q];
-            if (idx < nc) s_u[idx] = runu;
+            vu[q] = runu;
         }
-        if (threadIdx.x == BLOCK - 1) s_l[nc] = tot;
-        if (threadIdx.x == 0) s_u[nc] = 0.f;
+        __syncthreads();   // every chunk is read before any is overwritten
+#pragma unroll
+        for (int q = 0; q < IPT; q += 4) {
+            *reinterpret_cast<float4*>(s_l + base + q) = make_float4(vl[q], vl[q + 1], vl[q + 2], vl[q + 3]);
+            *reinterpret_cast<float4*>(s_u + base + q) = make_float4(vu[q], vu[q + 1], vu[q + 2], vu[q + 3]);
+        }
+        if (threadIdx.x == BLOCK - 1) {
+            s_l[T] = run;      // z = nc = T: everything before
+            s_u[T] = 0.f;
+        }
         __syncthreads();
     }
 
@@ -357,25 +467,25 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     double* __restrict__ OUT = L.out + tg.r0;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        if (q >= nrq) break;
         const int k = threadIdx.x + q * BLOCK;
-        const bool live = k < nr;
-        int z = zq[q] - (int)tg.c0;
-        z = min(max(z, 0), nc);
-        const Ext<float> E = erq[q];
-        const float rE = __builtin_amdgcn_rcpf(E.m);
-        const float pm = cl_rel + s_l[z];
-        const float qm = s_u[z] + cu_rel;
-        const double val = ext_log2n(ext_add(Ext<float>{pm * rE, rl - E.e}, Ext<float>{qm * E.m, ru + E.e}));
-        const double pnew = a0q[q] - val;
-        if (CHECK && live) {
-            // |psi_old (K^T phi) - v| = v |2^{g_old + t - log2 v} - 1|, exponent in FP64
-            const long long o = tg.r0 + k;
-            const double d = (L.a2[o] - a0q[q]) + val;
-            red += (double)((float)L.a1[o] * fabsf(expm1f((float)(d * 0.69314718055994530942))));
-        }
-        if (live) {
-            OUT[k] = pnew;
+        if (k >= nc && k < nc + nr) {
+            int z = Zq[q] - (int)tg.c0;
+            z = min(max(z, 0), nc);
+            const Ext<float> E = Eq[q];
+            const float rE = __builtin_amdgcn_rcpf(E.m);
+            const float pm = cl_rel + ldexp_m(s_l[z], shl);
+            const float qm = ldexp_m(s_u[z], shu) + cu_rel;
+            const double val =
+                ext_log2n(ext_add(Ext<float>{pm * rE, rl - E.e}, Ext<float>{qm * E.m, ru + E.e}));
+            const double pnew = Dq[q] - val;
+            if (CHECK) {
+                // |psi_old (K^T phi) - v| = v |2^{g_old + t - log2 v} - 1|, exponent in FP64;
+                // the weight v = 2^{log2 v} from the row's operand
+                const double d = (dqc[q] - Dq[q]) + val;
+                const Ext<float> vv = split_exp2(Dq[q]);
+                red += (double)(ldexp_m(vv.m, vv.e) * fabsf(expm1f((float)(d * 0.69314718055994530942))));
+            }
+            OUT[k - nc] = pnew;
             if (NEXT_AGG) {
                 Ext<float> lo, up;
                 next_terms(pnew, E, rE, lo, up);
@@ -385,21 +495,32 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
         }
     }
     if (CHECK) {
-        const double b = block_sum_f64<BLOCK>(red, s_red);
-        if (threadIdx.x == 0) partial[L.part_base + w.tile] = b;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) red += __shfl_down(red, d, kWave);
+        if (lane == 0) s_d[wid] = red;
     }
-    if (NEXT_AGG && L.ntiles > 1) {
-        Ext<float> a1 = Ext<float>{n1.s, n1.r}, a2 = Ext<float>{n2.s, n2.r}, t1, t2;
-        block_total2_ref<BLOCK, 1>(&a1, &a2, t1, t2, s_i, s_f);
+    if (NEXT_AGG && L.ntiles > 1) block_total2_write<BLOCK>(n1, n2, s_f, s_i);
+    if (CHECK || (NEXT_AGG && L.ntiles > 1)) {
+        __syncthreads();
         if (threadIdx.x == 0) {
-            agg_next[(long long)(L.agg_base + w.tile) * 2 + 0] = t1;
-            agg_next[(long long)(L.agg_base + w.tile) * 2 + 1] = t2;
+            if (CHECK) {
+                double b = 0.0;
+#pragma unroll
+                for (int v = 0; v < NW; ++v) b += s_d[v];
+                partial[L.part_base + w.tile] = b;
+            }
+            if (NEXT_AGG && L.ntiles > 1) {
+                agg_next[(long long)(L.agg_base + w.tile) * 2 + 0] = block_total_read<BLOCK>(s_f, s_i);
+                agg_next[(long long)(L.agg_base + w.tile) * 2 + 1] = block_total_read<BLOCK>(s_f + NW, s_i + NW);
+            }
         }
     }
 }
 
 // Tile totals of a fast line's column terms (the carries of its first sweep),
-// computed exactly as the update epilogue computes them.
+// computed exactly as the update epilogue of the paired sweep computes them:
+// the paired sweep's rows are these columns, visited by the same threads in
+// the same order (its slots are [its nc = this nr columns..., its rows]).
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void k_tile_aggregate_fast(const WorkItem* __restrict__ work,
                                                               const LineDesc* __restrict__ lines,
@@ -413,27 +534,28 @@ __global__ __launch_bounds__(BLOCK) void k_tile_aggregate_fast(const WorkItem* _
     const WorkItem w = work[blockIdx.x];
     const LineDesc L = lines[w.line];
     if (ps[L.prob].done) return;
-    const TileGeom<double> tg = tile_geom(L, w.tile, T);
-    const int nc = (int)(tg.c1 - tg.c0);
+    const FastGeom tg = fast_geom(L, w.tile, T, L.trs[w.tile], L.trs[w.tile + 1]);
+    const int nc = tg.nc;
+    const int off = tg.nr;
     const Ext<float>* __restrict__ EC = (const Ext<float>*)L.ec + tg.c0;
     const double* __restrict__ gin = L.gin + tg.c0;
     RefAcc n1{0.f, kZeroExp}, n2{0.f, kZeroExp};
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        const int k = threadIdx.x + q * BLOCK;
-        if (k < nc) {
-            const Ext<float> E = EC[k];
+        const int j = (int)threadIdx.x + q * BLOCK - off;
+        if (j >= 0 && j < nc) {
+            const Ext<float> E = EC[j];
             Ext<float> lo, up;
-            next_terms(gin[k], E, __builtin_amdgcn_rcpf(E.m), lo, up);
+            next_terms(gin[j], E, __builtin_amdgcn_rcpf(E.m), lo, up);
             ref_add(n1, lo);
             ref_add(n2, up);
         }
     }
-    Ext<float> a1 = Ext<float>{n1.s, n1.r}, a2 = Ext<float>{n2.s, n2.r}, t1, t2;
-    block_total2_ref<BLOCK, 1>(&a1, &a2, t1, t2, s_i, s_f);
+    block_total2_write<BLOCK>(n1, n2, s_f, s_i);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        agg[(long long)(L.agg_base + w.tile) * 2 + 0] = t1;
-        agg[(long long)(L.agg_base + w.tile) * 2 + 1] = t2;
+        agg[(long long)(L.agg_base + w.tile) * 2 + 0] = block_total_read<BLOCK>(s_f, s_i);
+        agg[(long long)(L.agg_base + w.tile) * 2 + 1] = block_total_read<BLOCK>(s_f + NW, s_i + NW);
     }
 }
 

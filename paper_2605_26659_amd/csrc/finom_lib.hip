@@ -189,16 +189,21 @@ void arena_release_all()
     g_arenas.clear();
 }
 
+static thread_local char g_last_error[256] = "";
+
 int map_exception()
 {
     try {
         throw;
     } catch (const std::bad_alloc&) {
+        snprintf(g_last_error, sizeof(g_last_error), "allocation failed");
         return FINOM_E_NOMEM;
     } catch (const HipError& e) {
+        snprintf(g_last_error, sizeof(g_last_error), "%s (%d)", hipGetErrorString(e.e), (int)e.e);
         if (e.e == hipErrorOutOfMemory) return FINOM_E_NOMEM;
         return FINOM_E_HIP;
     } catch (...) {
+        snprintf(g_last_error, sizeof(g_last_error), "unexpected exception");
         return FINOM_E_HIP;
     }
 }
@@ -521,6 +526,7 @@ bool fast_allowed()
     const char* e = getenv("FINOM_FAST");
     return !(e && e[0] == '0');
 }
+
 
 bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, const double* lu, const double* lv, double eps,
                    Ext<float>** Ex, Ext<float>** Ey, hipStream_t s)
@@ -1107,6 +1113,8 @@ const char* finom_strerror(int status)
 
 void finom_release(void) { arena_release_all(); }
 
-const char* finom_version(void) { return "finom-gfx950 0.2"; }
+const char* finom_version(void) { return "finom-gfx950 0.3"; }
+
+const char* finom_last_error(void) { return g_last_error; }
 
 }  // extern "C"

@@ -114,16 +114,21 @@ double time_pair(Alloc& al, int precision, int cfg, long long n, long long count
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // best of three timings of 8 iterations each
     const int reps = 8;
-    HIPCHK(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) iteration(r & 1);
-    HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    float best = 0.f;
+    for (int trial = 0; trial < 3; ++trial) {
+        HIPCHK(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) iteration(r & 1);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (trial == 0 || ms < best) best = ms;
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    return ms * 1e-3 / reps;
+    return best * 1e-3 / reps;
 }
 
 bool read_cache(const char* path, int precision)
