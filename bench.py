@@ -26,10 +26,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per grid point per iteration with FP64 state and
-# coordinates: the K^T phi half reads f, x, y, log2 v and g_old and writes g
-# (16n + 24m; the check's weight v is 2^{log2 v}); the K psi half reads g,
-# y, x, log2 u and writes f (24n + 16m).
-BYTES_KT = (16, 24)
+# coordinates: the K^T phi half reads f, x, y, v (as log2 v) and g_old and
+# writes g (16n + 32m); the K psi half reads g, y, x, u (as log2 u) and
+# writes f (24n + 16m).
+BYTES_KT = (16, 32)
 BYTES_K = (24, 16)
 
 # HBM traffic of the two sweep kernels measured with rocprofv3 FETCH_SIZE and
