@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-problem batch")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the small 1D, eps = 1e-2 and 2D 1024^2 configurations")
     ap.add_argument("--serving", action="store_true",
                     help="full serving sweep (several arrival rates and the nominal 2000/s)")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving sample")
@@ -180,6 +182,50 @@ def bench_batch(precision):
                                                 "sinkhorn_w1_1d call each, FP64 scans"},
            "note": "wall time of the call (setup, iteration, costs); loop_rate excludes "
                    "setup and cost"}
+    return out
+
+
+def bench_other_configs(precision):
+    """The other single-problem configurations, one timed solve each after a
+    warm-up: the small 1D correctness case (FP64 scans, tol 1e-9, cap 2000),
+    the graded 1D workload at eps = 1e-2, and the 2D 1024 x 1024 tanh mesh
+    (eps = 5e-3, tol 1e-6)."""
+    import torch
+    from paper_2605_26659_amd import sinkhorn_w1_1d, sinkhorn_w1_2d, workloads as wl
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    out = {}
+
+    def run1d(p, prec):
+        x, y, u, v = dev(p.x), dev(p.y), dev(p.u), dev(p.v)
+        sinkhorn_w1_1d(x, y, u, v, p.eps, p.tol, p.itr_max, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, _, _ = sinkhorn_w1_1d(x, y, u, v, p.eps, p.tol, p.itr_max, precision=prec)
+        dt = time.perf_counter() - t0
+        return {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
+                "iters": r["iters"], "w1": r["w1"], "marginal_err": r["marginal_err"],
+                "converged": r["converged"], "scan_mantissa": "fp32" if prec == 1 else "fp64"}
+
+    p = wl.config_small_1d()
+    out["small_1d_n512"] = run1d(p, 0)
+    out["small_1d_n512"]["workload"] = "n=m=512 sorted U(0,1), masses U(0.1,1), eps=0.01, tol=1e-9, cap 2000"
+    p = wl.config_graded_1d(1 << 20, 1e-2)
+    out["graded_1d_eps1e-2"] = run1d(p, precision)
+    p = wl.config_tanh_2d(1024)
+    args2 = (dev(p.x1), dev(p.y1), dev(p.x2), dev(p.y2), dev(p.u.ravel(order="F")),
+             dev(p.v.ravel(order="F")), p.eps, p.tol, p.itr_max)
+    sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, _, _ = sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
+    dt = time.perf_counter() - t0
+    out["tanh_2d_1024"] = {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s",
+                           "solve_ms": dt * 1e3, "iters": r["iters"], "w1": r["w1"],
+                           "marginal_err": r["marginal_err"], "converged": r["converged"],
+                           "loop_ms": r["loop_ms"],
+                           "scan_mantissa": "fp32" if precision == 1 else "fp64",
+                           "workload": "1024 x 1024 tanh mesh (beta 2.5), 4-component 2D GMM masses, "
+                                       "eps=5e-3, tol=1e-6"}
     return out
 
 
@@ -374,6 +420,8 @@ def main():
                     "tolerance = per-iteration time x FINOM's iteration count"}
         extra["speedup_vs_dense"] = value / dense_rate
 
+    if not args.no_other:
+        extra.update(bench_other_configs(prec))
     if not args.no_batch:
         extra["batch_4096"] = bench_batch(prec)
     if args.serving or not args.no_serving:

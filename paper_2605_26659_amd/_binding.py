@@ -46,12 +46,12 @@ class Opts(C.Structure):
 class Result(C.Structure):
     _fields_ = [("w1", C.c_double), ("marginal_err", C.c_double), ("iters", C.c_int64),
                 ("converged", C.c_int32), ("status", C.c_int32), ("loop_ms", C.c_double),
-                ("sweeps", C.c_int64)]
+                ("sweeps", C.c_int64), ("fast", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {"w1": self.w1, "marginal_err": self.marginal_err, "iters": int(self.iters),
                 "converged": bool(self.converged), "status": int(self.status),
-                "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps)}
+                "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps), "fast": bool(self.fast)}
 
 
 class Problem(C.Structure):

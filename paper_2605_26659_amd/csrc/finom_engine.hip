@@ -920,6 +920,7 @@ std::vector<Job*> Engine::harvest()
         r.sweeps = j->d.dim == 1 ? 2 * st.iters + 1 : 4 * st.iters + 2;
         r.loop_ms = j->loop_ms;
         r.status = st.status ? FINOM_E_NUMERIC : (st.converged ? FINOM_OK : FINOM_NOT_CONVERGED);
+        r.fast = j->fast ? 1 : 0;
         free_slots_.push(j->slot);
         j->slot = -1;
     }

@@ -939,6 +939,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         finish_result(res, hps[0], hps[1].w1);
+        res->fast = fast ? 1 : 0;
         if (hps[0].status) return fail(FINOM_E_NUMERIC);
         return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
     } catch (...) {

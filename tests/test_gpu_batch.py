@@ -50,7 +50,7 @@ def _alone(d, precision):
 
 
 def _assert_same(r_mix, d, r_alone, f_alone, g_alone):
-    for k in ("iters", "converged", "status"):
+    for k in ("iters", "converged", "status", "fast"):
         assert r_mix[k] == r_alone[k], (k, r_mix[k], r_alone[k])
     assert r_mix["w1"] == r_alone["w1"]
     assert r_mix["marginal_err"] == r_alone["marginal_err"]
