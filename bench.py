@@ -435,7 +435,7 @@ def main():
     extra["tile_shapes"] = {p: [finom_tile_config(1 if p == "fp32" else 0, 512 << c) for c in range(13)]
                             for p in ("fp32", "fp64")}
     extra["tile_shapes_note"] = ("tile-shape index per merged-line length class 2^9..2^21 "
-                                 "(0: 256x4, 1: 256x8, 2: 512x8, 3: 128x4)")
+                                 "(0: 256x4, 1: 256x8, 2: 512x8, 3: 128x4, 4: 512x4)")
     # the paper's own timing (section 4.1, Table 1: C++ on a 14-core Xeon Gold
     # 5117 at 2.0 GHz, eps = 0.01, 1000 iterations), as context only
     extra["paper_cpu_context"] = {"workload": "1D Chebyshev nodes N=8000, 1000 iterations",

@@ -32,6 +32,25 @@ struct Ext {
 template <typename M>
 __device__ __forceinline__ Ext<M> ext_zero() { return Ext<M>{M(0), kZeroExp}; }
 
+// Pointers held in descriptors are generic (flat) pointers to the compiler,
+// which then emits flat loads and stores: those also count against the LDS
+// wait counter and may alias LDS, so every LDS access after a flat store waits
+// for that store to reach memory. All data the kernels touch through
+// descriptors lives in device global memory; marking those pointers global
+// gives global loads and stores, which the LDS traffic never waits on.
+// (The host pass of the compiler parses device functions as well; there the
+// qualifier has no meaning and the alias is a plain pointer.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = T*;
+#endif
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gbl(T* p) { return (gptr<T>)p; }
+
 __device__ __forceinline__ float ldexp_m(float m, int e) { return __builtin_amdgcn_ldexpf(m, e); }
 __device__ __forceinline__ double ldexp_m(double m, int e) { return __builtin_amdgcn_ldexp(m, e); }
 

@@ -38,7 +38,6 @@ struct ArrTask {
     const double* a;
     long long n;
     double* la;          // masses: log2 of each entry
-    Ext<float>* eout;    // meshes: 2^{c kappa} of each entry (optional)
     double* fill;        // optional: potential initialisation
     long long nfill;
     double fill_v;
@@ -69,7 +68,6 @@ __global__ __launch_bounds__(kBlock) void k_setup_arrays(const ArrTask* __restri
                 if (!(fabs(v) * t.kappa < kCoordLimit)) bad |= (v == v && fabs(v) != __builtin_inf()) ? 4 : 1;
                 if (k + 1 < t.n && v > t.a[k + 1]) bad |= 1;
             }
-            if (t.eout && fabs(v) * t.kappa < kCoordLimit) t.eout[k] = split_exp2(v * t.kappa);
         } else {
             if (!(v > 0.0) || v == __builtin_inf()) bad |= 2;
             t.la[k] = log2(v);
@@ -316,8 +314,8 @@ JobPlan plan_job(const JobDesc& d, int precision)
     p.o_G1 = take(8 * p.nb);
     if (d.dim == 2) p.o_S = take(8 * p.s_len);
     if (d.dim == 1 && precision == 1) {
-        p.o_Ex = take(sizeof(Ext<float>) * p.na);
-        p.o_Ey = take(sizeof(Ext<float>) * p.nb);
+        p.o_Bx = take(sizeof(Ext<float>) * p.na);
+        p.o_By = take(sizeof(Ext<float>) * p.nb);
     }
     for (int a = 0; a < d.dim; ++a) {
         p.cfg[a] = tuned_cfg(precision, p.R[a] + p.C[a]);
@@ -342,8 +340,8 @@ void Job::bind()
     G[0] = (double*)(mem + p.o_G0);
     G[1] = (double*)(mem + p.o_G1);
     S = d.dim == 2 ? (double*)(mem + p.o_S) : nullptr;
-    Ex = p.o_Ex ? (Ext<float>*)(mem + p.o_Ex) : nullptr;
-    Ey = p.o_Ey ? (Ext<float>*)(mem + p.o_Ey) : nullptr;
+    Bx = p.o_Bx ? (Ext<float>*)(mem + p.o_Bx) : nullptr;
+    By = p.o_By ? (Ext<float>*)(mem + p.o_By) : nullptr;
     const int Tc = cost_tile_size();
     for (int a = 0; a < d.dim; ++a) {
         const double* xr = a == 0 ? d.x1 : d.y1;
@@ -420,8 +418,8 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
         Job* j = jobs[i];
         const JobDesc& d = j->d;
         const double kappa = 1.0 / (d.eps * kLn2);
-        auto mesh = [&](const double* a, long long n, Ext<float>* eout) {
-            if (!checks && !eout) return;
+        auto mesh = [&](const double* a, long long n) {
+            if (!checks) return;
             ArrTask t;
             memset(&t, 0, sizeof(t));
             t.a = a;
@@ -430,16 +428,14 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
             t.job = i;
             t.kappa = kappa;
             t.checks = checks ? 1 : 0;
-            t.eout = eout;
             at.push_back(t);
             at_n.push_back(n);
         };
-        const bool want_fast = d.dim == 1 && j->Ex && fast_allowed();
-        mesh(d.x1, d.n1, want_fast ? j->Ex : nullptr);
-        mesh(d.x2, d.n2, want_fast ? j->Ey : nullptr);
+        mesh(d.x1, d.n1);
+        mesh(d.x2, d.n2);
         if (d.dim == 2) {
-            mesh(d.y1, d.m1, nullptr);
-            mesh(d.y2, d.m2, nullptr);
+            mesh(d.y1, d.m1);
+            mesh(d.y2, d.m2);
         }
         auto mass = [&](const double* a, long long n, double* la, double* fill, int slot) {
             ArrTask t;
@@ -503,7 +499,7 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
     std::vector<long long> bt_n;
     for (int i = 0; i < nj; ++i) {
         Job* j = jobs[i];
-        if (!(j->d.dim == 1 && j->Ex && fast_allowed())) continue;
+        if (!(j->d.dim == 1 && j->Bx && fast_allowed())) continue;
         const double kappa = 1.0 / (j->d.eps * kLn2);
         for (int dir = 0; dir < 2; ++dir) {
             // dir 0: K psi, columns y with masses v; dir 1: K^T phi, columns x with masses u
@@ -543,8 +539,34 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
         HIPCHK(hipMemcpyAsync(hsums, sums, sizeof(double) * 2 * nj, hipMemcpyDeviceToHost, s_));
     }
     HIPCHK(hipStreamSynchronize(s_));
-    for (int i = 0; i < nj; ++i)
-        jobs[i]->fast = jobs[i]->d.dim == 1 && jobs[i]->Ex && fast_allowed() && hfflags[i] == 0;
+    // fast jobs: B = 2^{2 c kappa}, the masses as Ext<float> over the log
+    // masses (the bound has read them), the state U = w 2^{-c kappa} over the
+    // log potentials
+    std::vector<FastStateTask> fst;
+    for (int i = 0; i < nj; ++i) {
+        Job* j = jobs[i];
+        j->fast = j->d.dim == 1 && j->Bx && fast_allowed() && hfflags[i] == 0;
+        if (!j->fast) continue;
+        const double kappa = 1.0 / (j->d.eps * kLn2);
+        FastStateTask t;
+        memset(&t, 0, sizeof(t));
+        t.mode = 0;
+        t.a = 0.0;
+        t.b = 2.0 * kappa;
+        t.out = j->Bx; t.in = j->d.x1; t.n = j->p.na; fst.push_back(t);
+        t.out = j->By; t.in = j->d.x2; t.n = j->p.nb; fst.push_back(t);
+        t.b = -kappa;
+        t.out = j->F; t.in = j->d.x1; t.n = j->p.na; t.a = -log2((double)j->p.na); fst.push_back(t);
+        t.out = j->G[0]; t.in = j->d.x2; t.n = j->p.nb; t.a = -log2((double)j->p.nb); fst.push_back(t);
+        t.mode = 1;
+        t.a = t.b = 0.0;
+        t.out = j->lu; t.in = j->d.u; t.n = j->p.na; fst.push_back(t);
+        t.out = j->lv; t.in = j->d.v; t.n = j->p.nb; fst.push_back(t);
+    }
+    if (!fst.empty()) {
+        enqueue_fast_state(al, fst, s_);
+        al.uploaded();
+    }
     if (!checks) return;
     for (int i = 0; i < nj; ++i) {
         const int f = hflags[i];
@@ -677,10 +699,10 @@ void Engine::rebuild()
                 c.prob = j->slot;
                 c.dec_part_off = -1;
                 if (j->fast) {
-                    a.er = j->Ey;
-                    a.ec = j->Ex;
-                    c.er = j->Ex;
-                    c.ec = j->Ey;
+                    a.er = j->By;
+                    a.ec = j->Bx;
+                    c.er = j->Bx;
+                    c.ec = j->By;
                 }
                 if (b == 0) {
                     chk[ji] = LineRange{gt, groups[gt].sw[0]->lines.size(), 1};
@@ -849,6 +871,19 @@ std::vector<Job*> Engine::harvest()
     std::vector<SegTask> segs;
     std::vector<ScaleTask> sc;
     std::vector<long long> sc_n;
+    // the fast sweeps' state back to log potentials, in place, before the costs
+    std::vector<FastStateTask> ft;
+    for (Job* j : fin) {
+        if (!j->fast) continue;
+        const double kappa = 1.0 / (j->d.eps * kLn2);
+        FastStateTask t;
+        memset(&t, 0, sizeof(t));
+        t.mode = 2;
+        t.b = kappa;
+        t.out = j->F; t.mesh = j->d.x1; t.n = j->p.na; ft.push_back(t);
+        t.out = j->G[hps_[j->slot].iters & 1]; t.mesh = j->d.x2; t.n = j->p.nb; ft.push_back(t);
+    }
+    enqueue_fast_state(al, ft, s_);
     int P = 0;
     for (Job* j : fin) {
         const JobDesc& d = j->d;

@@ -35,7 +35,7 @@ struct JobPlan {
     long long na = 0, nb = 0, s_len = 0;
     long long R[2] = {0, 0}, C[2] = {0, 0};
     int ntiles[2] = {0, 0}, ntiles_c[2] = {0, 0};
-    size_t o_lu = 0, o_lv = 0, o_F = 0, o_G0 = 0, o_G1 = 0, o_S = 0, o_Ex = 0, o_Ey = 0;
+    size_t o_lu = 0, o_lv = 0, o_F = 0, o_G0 = 0, o_G1 = 0, o_S = 0, o_Bx = 0, o_By = 0;
     size_t o_zeta[2] = {0, 0}, o_zeta_t[2] = {0, 0}, o_trs[2] = {0, 0}, o_trs_t[2] = {0, 0},
            o_trs_c[2] = {0, 0};
     size_t bytes = 0;
@@ -52,10 +52,12 @@ struct Job {
     long long tag = 0;       // caller's index or ticket
     double loop_ms = 0.0;    // GPU time of the rounds the job took part in
     finom_result res{};
-    // views into mem
+    // views into mem. Jobs on the fast sweeps keep, in the same buffers, the
+    // masses as Ext<float> in lu / lv and the state U = w 2^{-c kappa} in F / G
+    // until they are harvested.
     double *lu = nullptr, *lv = nullptr, *F = nullptr, *G[2] = {nullptr, nullptr}, *S = nullptr;
-    Ext<float>* Ex = nullptr;   // 1D: 2^{x kappa} and 2^{y kappa} for the fast sweeps
-    Ext<float>* Ey = nullptr;
+    Ext<float>* Bx = nullptr;   // 1D FP32: 2^{2 x kappa} and 2^{2 y kappa} for the fast sweeps
+    Ext<float>* By = nullptr;
     bool fast = false;          // runs on the fast sweeps
     Part pk[2], pkt[2], pc[2];   // per axis: K, K^T, cost partition of K
     void bind();

@@ -13,9 +13,17 @@
 // static (meshes, masses, eps), so lines are classified once at setup
 // (k_tile_bounds) and the two kinds run as different kernels.
 //
-// Rows and columns read 2^{c kappa} as a precomputed extended number per mesh
-// point (k_exp_coords), so a sweep forms one exponential per column
-// (2^{g_j}) and per updated row (2^{new potential}) instead of three.
+// State. A fast problem keeps its scaling vectors as extended numbers
+// instead of log potentials: per point c with scaling w (phi or psi) the
+// state is U = w 2^{-c kappa}; the masses are kept as A = u or v and the mesh
+// as B = 2^{2 c kappa}, all Ext<float> (8 bytes, as many as a log potential).
+// Then a column's two terms are w 2^{+c kappa} = U B and w 2^{-c kappa} = U,
+// and a row x with in-tile sums L (lower block) and R (upper block) has
+//   (K w)_x = 2^{-x kappa} (L + B_x R),
+// so the update w_x = A_x / (K w)_x is the state U_x = A_x / (L + B_x R):
+// one multiply-add, one reciprocal, no exponential or logarithm per element.
+// The marginal error of the check is |w_old (K w') - A| = |U_old W - A| with
+// W = L + B R. The log potentials are formed once, when the loop has ended.
 //
 // Tile totals for the next sweep's carries use a block-wide reference too;
 // terms more than 2^-126 below the tile's largest vanish, which changes a
@@ -156,23 +164,12 @@ __device__ __forceinline__ Ext<float> split_exp2(double s)
     return Ext<float>{__builtin_amdgcn_exp2f((float)(s - k)), (int)k};
 }
 
-// log2 of a positive extended value with the mantissa normalised to
-// [1/2, 1) first, so the FP32 logarithm works on a small argument
-__device__ __forceinline__ double ext_log2n(Ext<float> a)
+// Mantissa into [1/2, 1) (exact). Every stored state, mass and total is kept
+// normalised: the tile scans set their reference from exponents alone, which
+// is only within a factor 4 of the magnitude when mantissas are normalised.
+__device__ __forceinline__ Ext<float> ext_norm(Ext<float> a)
 {
-    if (!(a.m > 0.f)) return -__builtin_inf();
-    const float mm = __builtin_amdgcn_frexp_mantf(a.m);
-    const int me = __builtin_amdgcn_frexp_expf(a.m);
-    return (double)__builtin_amdgcn_logf(mm) + (double)(a.e + me);
-}
-
-// Terms of the next sweep's columns from a new potential p and the
-// column's 2^{c kappa} = E: lower 2^{p + c kappa}, upper 2^{p - c kappa}.
-__device__ __forceinline__ void next_terms(double p, Ext<float> E, float rcpE, Ext<float>& lo, Ext<float>& up)
-{
-    const Ext<float> ep = split_exp2(p);
-    lo = Ext<float>{ep.m * E.m, ep.e + E.e};
-    up = Ext<float>{ep.m * rcpE, ep.e - E.e};
+    return Ext<float>{__builtin_amdgcn_frexp_mantf(a.m), a.e + __builtin_amdgcn_frexp_expf(a.m)};
 }
 
 // Per-thread total of extended values against the exponent of the first
@@ -224,7 +221,7 @@ __device__ __forceinline__ Ext<float> block_total_read(const float* s_f, const i
     float v = 0.f;
 #pragma unroll
     for (int w = 0; w < NW; ++w) v += ldexp_m(s_f[w], s_i[w] - r);
-    return Ext<float>{v, r};
+    return ext_norm(Ext<float>{v, r});
 }
 
 // ------------------------------------------------------------ fast sweep
@@ -256,7 +253,325 @@ __device__ __forceinline__ FastGeom fast_geom(const LineDesc& L, int tile, int T
     return FastGeom{r0, c0, (int)(r1 - r0), (int)(c1 - c0)};
 }
 
+// The loaded operands of one tile: per slot B = 2^{2 c kappa} of its point
+// and V, the column's state or the row's mass; per row slot its dividing
+// index Z.
+template <int IPT>
+struct FastTileIn {
+    FastGeom tg;
+    Ext<float> B[IPT];
+    Ext<float> V[IPT];
+    int Z[IPT];
+    Ext<float> U0, B0;  // the first column's state and B
+};
+
+// Row offset of slot k, clamped into the tile's rows (idle slots and column
+// slots read row 0).
+__device__ __forceinline__ unsigned fast_row_index(int k, int nc, int nr)
+{
+    return (unsigned)min(max(k - nc, 0), max(nr - 1, 0));
+}
+
+// Every load of a tile. Offsets are 32-bit from tile bases clamped into the
+// arrays (lines have at least one row and one column, so index 0 of an
+// empty part is still in range). A wave whose 64 slots are all columns or
+// all rows takes a branch of its own with uniform bases; only the wave that
+// straddles the boundary selects a base per lane. Every branch issues the
+// same loads, so the compiler can still wait for one slot's data alone.
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void fast_tile_load(FastTileIn<IPT>& t, const LineDesc& L)
+{
+    const int nc = t.tg.nc, nr = t.tg.nr;
+    const long long cb = min(t.tg.c0, L.C - 1), rb = min(t.tg.r0, L.R - 1);
+    const gptr<const Ext<float>> UC = gbl((const Ext<float>*)L.gin) + cb;
+    const gptr<const Ext<float>> BC = gbl((const Ext<float>*)L.ec) + cb;
+    const gptr<const Ext<float>> BR = gbl((const Ext<float>*)L.er) + rb;
+    const gptr<const Ext<float>> AR = gbl((const Ext<float>*)L.a0) + rb;
+    const gptr<const int> ZR = gbl(L.zeta) + rb;
+    const unsigned ncm = (unsigned)max(nc - 1, 0);
+    t.U0 = UC[0];
+    t.B0 = BC[0];
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const int k = threadIdx.x + q * BLOCK;
+        const int kw = __builtin_amdgcn_readfirstlane(k);   // slot of the wave's lane 0
+        const unsigned ir = fast_row_index(k, nc, nr);
+        t.Z[q] = ZR[ir];
+        if (kw + kWave <= nc) {
+            t.B[q] = BC[(unsigned)k];
+            t.V[q] = UC[(unsigned)k];
+        } else if (kw >= nc) {
+            t.B[q] = BR[ir];
+            t.V[q] = AR[ir];
+        } else {
+            const bool col = k < nc;
+            const unsigned ic = min((unsigned)k, ncm);
+            t.B[q] = col ? BC[ic] : BR[ir];
+            t.V[q] = col ? UC[ic] : AR[ir];
+        }
+    }
+}
+
+// Old state of each row for the marginal-error check.
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void fast_tile_check_loads(const FastTileIn<IPT>& t, const LineDesc& L,
+                                                      Ext<float>* uold)
+{
+    const gptr<const Ext<float>> UO = gbl((const Ext<float>*)L.a2) + min(t.tg.r0, L.R - 1);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) uold[q] = UO[fast_row_index(threadIdx.x + q * BLOCK, t.tg.nc, t.tg.nr)];
+}
+
+// Column terms U B (lower block) and U (upper block) against the tile's
+// first column, to LDS.
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void fast_tile_columns(const FastTileIn<IPT>& t, float* s_l, float* s_u, int& r0l,
+                                                  int& r0u)
+{
+    const int nc = t.tg.nc;
+    r0l = kZeroExp;
+    r0u = kZeroExp;
+    if (nc > 0) {
+        r0l = t.U0.e + t.B0.e;
+        r0u = t.U0.e;
+    }
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const int k = threadIdx.x + q * BLOCK;
+        if (k < nc) {
+            const Ext<float> U = t.V[q], B = t.B[q];
+            s_l[k] = ldexp_m(U.m * B.m, U.e + B.e - r0l);
+            s_u[k] = ldexp_m(U.m, U.e - r0u);
+        }
+    }
+}
+
+// Exclusive prefix (s_l) and inclusive suffix (s_u) of the tile's columns in
+// place, thread t owning columns [t IPT, t IPT + IPT); the caller has passed a
+// barrier since the columns were written. s_f holds 2 * (BLOCK / 64) entries.
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void fast_tile_scan(float* s_l, float* s_u, int nc, float* s_f)
+{
+    constexpr int NW = BLOCK / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    float vl[IPT], vu[IPT];
+    const int base = threadIdx.x * IPT;
+#pragma unroll
+    for (int q = 0; q < IPT; q += 4) {
+        const float4 a = *reinterpret_cast<const float4*>(s_l + base + q);
+        const float4 b = *reinterpret_cast<const float4*>(s_u + base + q);
+        vl[q] = a.x; vl[q + 1] = a.y; vl[q + 2] = a.z; vl[q + 3] = a.w;
+        vu[q] = b.x; vu[q + 1] = b.y; vu[q + 2] = b.z; vu[q + 3] = b.w;
+    }
+    float sl = 0.f, su = 0.f;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const bool live = base + q < nc;
+        vl[q] = live ? vl[q] : 0.f;
+        vu[q] = live ? vu[q] : 0.f;
+        sl += vl[q];
+        su += vu[q];
+    }
+    const float il = wave_incl_prefix_f(sl);
+    const float iu = wave_incl_suffix_f(su);
+    if (lane == kWave - 1) s_f[wid] = il;
+    if (lane == 0) s_f[NW + wid] = iu;
+    __syncthreads();
+    float pre = 0.f, suf = 0.f;
+    for (int v = 0; v < wid; ++v) pre += s_f[v];
+    for (int v = wid + 1; v < NW; ++v) suf += s_f[NW + v];
+    float run = pre + dpp_f<0x138>(il);    // wave_shr:1 -> exclusive prefix
+    float runu = dpp_f<0x130>(iu) + suf;   // wave_shl:1 -> exclusive suffix
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const float t = vl[q];
+        vl[q] = run;
+        run += t;
+    }
+#pragma unroll
+    for (int q = IPT - 1; q >= 0; --q) {
+        runu += vu[q];
+        vu[q] = runu;
+    }
+    __syncthreads();   // every chunk is read before any is overwritten
+#pragma unroll
+    for (int q = 0; q < IPT; q += 4) {
+        *reinterpret_cast<float4*>(s_l + base + q) = make_float4(vl[q], vl[q + 1], vl[q + 2], vl[q + 3]);
+        *reinterpret_cast<float4*>(s_u + base + q) = make_float4(vu[q], vu[q + 1], vu[q + 2], vu[q + 3]);
+    }
+    if (threadIdx.x == BLOCK - 1) {
+        s_l[BLOCK * IPT] = run;      // z = nc = T: everything before
+        s_u[BLOCK * IPT] = 0.f;
+    }
+    __syncthreads();
+}
+
+// Rows of a scanned tile. With the carries, the row's sums are
+// L = (C_L + S_L[z]) and R = (S_U[z] + C_U), against the row references rl,
+// ru (the larger of the first column's and the carry's exponent); the new
+// state is U = A / (L + B R). New states go to un (stored by the caller after
+// the loop: a store inside it would make each later wait on the check loads
+// also wait for that store), the check term |U_old W - A| to red, the next
+// sweep's column terms U B and U to n1 / n2.
 template <int BLOCK, int IPT, int EPI, bool NEXT_AGG>
+__device__ __forceinline__ void fast_tile_rows(const FastTileIn<IPT>& t, const float* s_l, const float* s_u,
+                                               Ext<float> CL, Ext<float> CU, int r0l, int r0u,
+                                               const Ext<float>* uold, Ext<float>* un, double& red, RefAcc& n1,
+                                               RefAcc& n2)
+{
+    constexpr bool CHECK = (EPI == EPI_UPDATE_CHECK);
+    const int nc = t.tg.nc, nr = t.tg.nr;
+    const int rl = max(r0l, CL.e), ru = max(r0u, CU.e);
+    const float cl_rel = ldexp_m(CL.m, CL.e - rl), cu_rel = ldexp_m(CU.m, CU.e - ru);
+    const int shl = r0l - rl, shu = r0u - ru;   // <= 0: rescales the in-tile sums
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const int k = threadIdx.x + q * BLOCK;
+        un[q] = ext_zero<float>();
+        if (k >= nc && k < nc + nr) {
+            int z = t.Z[q] - (int)t.tg.c0;
+            z = min(max(z, 0), nc);
+            const Ext<float> B = t.B[q], A = t.V[q];
+            const float pm = cl_rel + ldexp_m(s_l[z], shl);
+            const float qm = ldexp_m(s_u[z], shu) + cu_rel;
+            const Ext<float> W = ext_add(Ext<float>{pm, rl}, Ext<float>{qm * B.m, ru + B.e});
+            const Ext<float> U = ext_norm(Ext<float>{A.m * __builtin_amdgcn_rcpf(W.m), A.e - W.e});
+            if (CHECK) {
+                // |U_old W - A| with one rounding: product and difference in one
+                // fused multiply-add, both operands scaled (exactly) to the larger
+                // of the two exponents so that neither can overflow
+                const Ext<float> O = uold[q];
+                const int ep = O.e + W.e;
+                const int re = max(ep, A.e);
+                const float d = __builtin_fmaf(ldexp_m(O.m, ep - re), W.m, -ldexp_m(A.m, A.e - re));
+                red += __builtin_amdgcn_ldexp((double)fabsf(d), re);
+            }
+            un[q] = U;
+            if (NEXT_AGG) {
+                ref_add(n1, Ext<float>{U.m * B.m, U.e + B.e});
+                ref_add(n2, U);
+            }
+        }
+    }
+}
+
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void fast_tile_store(const FastTileIn<IPT>& t, const LineDesc& L, const Ext<float>* un)
+{
+    const gptr<Ext<float>> OUT = gbl((Ext<float>*)L.out) + min(t.tg.r0, L.R - 1);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const int k = threadIdx.x + q * BLOCK;
+        if (k >= t.tg.nc && k < t.tg.nc + t.tg.nr) OUT[(unsigned)(k - t.tg.nc)] = un[q];
+    }
+}
+
+// Stop decision of the loop head from the block's sum of the checking
+// sweep's partials (every block sums them in the same order). Returns true
+// when the iteration stops.
+__device__ __forceinline__ bool fast_decide(const LineDesc& L, int tile, ProbState* P, double err, int parity)
+{
+    const long long l = P->cnt[parity];
+    const bool stop = (l >= P->itr_max) || !(err > P->tol);
+    if (L.writes_state && tile == 0 && threadIdx.x == 0) {
+        P->err = err;
+        if (!(err == err) || err == __builtin_inf()) P->status = 1;
+        if (stop) {
+            P->iters = l;
+            P->converged = (err <= P->tol) ? 1 : 0;
+            P->done = 1;
+        } else {
+            P->cnt[parity ^ 1] = l + 1;
+        }
+    }
+    return stop;
+}
+
+// Two fixed slots per thread of tile aggregates and decision partials
+// (loaded before the tiles, so that no wait sits between them); BIG adds
+// loops over the rest, which sit in that kernel variant only because a loop
+// with loads makes the compiler wait for every load issued before it.
+constexpr int kFastFix = 2;
+
+template <int BLOCK>
+__device__ __forceinline__ void fast_fixed_loads(const LineDesc& L, const Ext<float>* agg,
+                                                 const double* dec_partial, int np,
+                                                 Ext<float> (&af)[kFastFix][2], double (&df)[kFastFix])
+{
+    if (np > 0) {
+        const gptr<const double> DP = gbl(dec_partial) + L.dec_part_off;
+#pragma unroll
+        for (int f = 0; f < kFastFix; ++f) df[f] = DP[min((int)threadIdx.x + f * BLOCK, np - 1)];
+    }
+    const gptr<const Ext<float>> AG = gbl(agg) + (long long)L.agg_base * 2;
+#pragma unroll
+    for (int f = 0; f < kFastFix; ++f) {
+        const int t = min((int)threadIdx.x + f * BLOCK, L.ntiles - 1);
+        af[f][0] = AG[2 * t];
+        af[f][1] = AG[2 * t + 1];
+    }
+}
+
+template <int BLOCK, bool BIG>
+__device__ __forceinline__ double fast_decision_sum(const LineDesc& L, const double* dec_partial, int np,
+                                                    const double (&df)[kFastFix])
+{
+    double dv = 0.0;
+    if (np > 0) {
+#pragma unroll
+        for (int f = 0; f < kFastFix; ++f)
+            if ((int)threadIdx.x + f * BLOCK < np) dv += df[f];
+        if constexpr (BIG)
+            for (int k = threadIdx.x + kFastFix * BLOCK; k < np; k += BLOCK) dv += dec_partial[L.dec_part_off + k];
+    }
+    return dv;
+}
+
+// Per-thread carries of tile `tile`: lower terms of the tiles before it,
+// upper terms of the tiles after it.
+template <int BLOCK, bool BIG>
+__device__ __forceinline__ void fast_carries(const LineDesc& L, const Ext<float>* agg, int tile,
+                                             const Ext<float> (&af)[kFastFix][2], RefAcc& cl, RefAcc& cu)
+{
+    const int nt = L.ntiles;
+    Ext<float> al = ext_zero<float>(), au = ext_zero<float>();
+#pragma unroll
+    for (int f = 0; f < kFastFix; ++f) {
+        const int t = threadIdx.x + f * BLOCK;
+        if (t < nt && t < tile) al = ext_add(al, af[f][0]);
+        if (t < nt && t > tile) au = ext_add(au, af[f][1]);
+    }
+    if constexpr (BIG) {
+        for (int t = threadIdx.x + kFastFix * BLOCK; t < nt; t += BLOCK) {
+            const gptr<const Ext<float>> a = gbl(agg) + (long long)(L.agg_base + t) * 2;
+            if (t < tile) al = ext_add(al, a[0]);
+            else if (t > tile) au = ext_add(au, a[1]);
+        }
+    }
+    cl = RefAcc{al.m, al.e};
+    cu = RefAcc{au.m, au.e};
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void wave_sum_to(double v, double* s)
+{
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_down(v, d, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = v;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ double block_read_sum(const double* s)
+{
+    double b = 0.0;
+#pragma unroll
+    for (int v = 0; v < BLOCK / kWave; ++v) b += s[v];
+    return b;
+}
+
+// One tile per block.
+template <int BLOCK, int IPT, int EPI, bool NEXT_AGG, bool BIG>
 __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict__ work,
                                                      const LineDesc* __restrict__ lines,
                                                      ProbState* __restrict__ ps,
@@ -279,237 +594,55 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     const LineDesc L = lines[w.line];
     ProbState* P = ps + L.prob;
     if (P->done) return;
-    const FastGeom tg = fast_geom(L, w.tile, T, L.trs[w.tile], L.trs[w.tile + 1]);
-    const int nc = tg.nc;
-    const int nr = tg.nr;
+    const gptr<const int> TRS = gbl(L.trs);
     const bool decide = dec_partial && L.dec_part_off >= 0;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    const double* __restrict__ gin = L.gin + tg.c0;
-    const Ext<float>* __restrict__ EC = (const Ext<float>*)L.ec + tg.c0;
-    const Ext<float>* __restrict__ ER = (const Ext<float>*)L.er + tg.r0;
-    const int* __restrict__ ZT = L.zeta + tg.r0;
-    const double* __restrict__ A0 = L.a0 + tg.r0;
-    const bool empty = nc + nr == 0;   // only with a corrupt partition
+    const int np = decide ? L.dec_nparts : 0;
+    const bool multi = L.ntiles > 1;
 
-    // ---- A. every load of the tile first. Slot k < nc is column k, slot
-    // nc <= k < nc + nr is row k - nc; idle slots re-read an element in range.
-    Ext<float> Eq[IPT];
-    double Dq[IPT];
-    int Zq[IPT];
-    if (!empty) {
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-            const int k = threadIdx.x + q * BLOCK;
-            const bool col = (k < nc) || nr == 0;
-            const int ic = min(k, nc - 1);
-            const int ir = min(k - nc, nr - 1);
-            Eq[q] = col ? EC[ic] : ER[ir];
-            Dq[q] = col ? gin[ic] : A0[ir];
-            Zq[q] = col ? 0 : ZT[ir];
-        }
-    }
-    double g0 = 0.0;
-    Ext<float> E0 = ext_zero<float>();
-    if (nc > 0) {
-        g0 = gin[0];
-        E0 = EC[0];
-    }
+    // ---- loads, in the order they are consumed (the memory counter retires
+    // them in issue order)
+    Ext<float> af[kFastFix][2];
+    double df[kFastFix];
+    fast_fixed_loads<BLOCK>(L, agg, dec_partial, np, af, df);
+    FastTileIn<IPT> A;
+    A.tg = fast_geom(L, w.tile, T, TRS[w.tile], TRS[w.tile + 1]);
+    fast_tile_load<BLOCK, IPT>(A, L);
     RefAcc cl{0.f, kZeroExp}, cu{0.f, kZeroExp};
-    if (L.ntiles > 1) {
-        Ext<float> al = ext_zero<float>(), au = ext_zero<float>();
-        for (int t = threadIdx.x; t < L.ntiles; t += BLOCK) {
-            const Ext<float>* a = agg + (long long)(L.agg_base + t) * 2;
-            if (t < w.tile) al = ext_add(al, a[0]);
-            else if (t > w.tile) au = ext_add(au, a[1]);
-        }
-        cl = RefAcc{al.m, al.e};
-        cu = RefAcc{au.m, au.e};
-    }
-    double dv = 0.0;
-    if (decide)
-        for (int k = threadIdx.x; k < L.dec_nparts; k += BLOCK) dv += dec_partial[L.dec_part_off + k];
+    if (multi) fast_carries<BLOCK, BIG>(L, agg, w.tile, af, cl, cu);
+    const double dv = fast_decision_sum<BLOCK, BIG>(L, dec_partial, np, df);
 
-    // ---- C. column terms against the tile's first column, to LDS
-    int r0l = kZeroExp, r0u = kZeroExp;
-    if (nc > 0) {
-        const Ext<float> e0 = split_exp2(g0);
-        r0l = e0.e + E0.e;
-        r0u = e0.e - E0.e;
-    }
-    if (!empty) {
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-            const int k = threadIdx.x + q * BLOCK;
-            if (k < nc) {
-                const Ext<float> eg = split_exp2(Dq[q]);
-                const Ext<float> E = Eq[q];
-                s_l[k] = ldexp_m(eg.m * E.m, eg.e + E.e - r0l);
-                s_u[k] = ldexp_m(eg.m * __builtin_amdgcn_rcpf(E.m), eg.e - E.e - r0u);
-            }
-        }
-    }
-    // carries and the stop decision share the next barrier
-    if (L.ntiles > 1) block_total2_write<BLOCK>(cl, cu, s_f + 2 * NW, s_i + 2 * NW);
-    if (decide) {
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) dv += __shfl_down(dv, d, kWave);
-        if (lane == 0) s_d[wid] = dv;
-    }
+    // ---- columns; carries and the stop decision share the next barrier
+    int r0l, r0u;
+    fast_tile_columns<BLOCK, IPT>(A, s_l, s_u, r0l, r0u);
+    if (multi) block_total2_write<BLOCK>(cl, cu, s_f + 2 * NW, s_i + 2 * NW);
+    if (decide) wave_sum_to<BLOCK>(dv, s_d);
     __syncthreads();
-    if (decide) {
-        double err = 0.0;
-#pragma unroll
-        for (int v = 0; v < NW; ++v) err += s_d[v];
-        const long long l = P->cnt[parity];
-        const bool stop = (l >= P->itr_max) || !(err > P->tol);
-        if (L.writes_state && w.tile == 0 && threadIdx.x == 0) {
-            P->err = err;
-            if (!(err == err) || err == __builtin_inf()) P->status = 1;
-            if (stop) {
-                P->iters = l;
-                P->converged = (err <= P->tol) ? 1 : 0;
-                P->done = 1;
-            } else {
-                P->cnt[parity ^ 1] = l + 1;
-            }
-        }
-        if (stop) return;
-    }
-    if (empty) {
-        if (threadIdx.x == 0) {
-            if (CHECK) partial[L.part_base + w.tile] = 0.0;
-            if (NEXT_AGG && L.ntiles > 1) {
-                agg_next[(long long)(L.agg_base + w.tile) * 2 + 0] = ext_zero<float>();
-                agg_next[(long long)(L.agg_base + w.tile) * 2 + 1] = ext_zero<float>();
-            }
-        }
-        return;
-    }
+    if (decide && fast_decide(L, w.tile, P, block_read_sum<BLOCK>(s_d), parity)) return;
     Ext<float> CL = ext_zero<float>(), CU = ext_zero<float>();
-    if (L.ntiles > 1) {
+    if (multi) {
         CL = block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW);
         CU = block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW);
     }
-    // row references: the larger of the first column's and the carry's exponent
-    const int rl = max(r0l, CL.e), ru = max(r0u, CU.e);
-    const float cl_rel = ldexp_m(CL.m, CL.e - rl), cu_rel = ldexp_m(CU.m, CU.e - ru);
-    const int shl = r0l - rl, shu = r0u - ru;   // <= 0: rescales the in-tile sums
-    double dqc[IPT];
-    if (CHECK) {
-        // old potential of each row for the marginal-error check, issued
-        // before the scan (the weight v = 2^{log2 v} comes from the row's a0)
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-            const int k = threadIdx.x + q * BLOCK;
-            dqc[q] = (k >= nc && k < nc + nr) ? L.a2[tg.r0 + (k - nc)] : 0.0;
-        }
-    }
+    // the check operands are issued before the scan, which covers their latency
+    Ext<float> uold[IPT];
+    if (CHECK) fast_tile_check_loads<BLOCK, IPT>(A, L, uold);
 
-    // ---- D. scan in fixed chunks: thread t owns columns [t IPT, t IPT + IPT)
-    {
-        float vl[IPT], vu[IPT];
-        const int base = threadIdx.x * IPT;
-#pragma unroll
-        for (int q = 0; q < IPT; q += 4) {
-            const float4 a = *reinterpret_cast<const float4*>(s_l + base + q);
-            const float4 b = *reinterpret_cast<const float4*>(s_u + base + q);
-            vl[q] = a.x; vl[q + 1] = a.y; vl[q + 2] = a.z; vl[q + 3] = a.w;
-            vu[q] = b.x; vu[q + 1] = b.y; vu[q + 2] = b.z; vu[q + 3] = b.w;
-        }
-        float sl = 0.f, su = 0.f;
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-            const bool live = base + q < nc;
-            vl[q] = live ? vl[q] : 0.f;
-            vu[q] = live ? vu[q] : 0.f;
-            sl += vl[q];
-            su += vu[q];
-        }
-        const float il = wave_incl_prefix_f(sl);
-        const float iu = wave_incl_suffix_f(su);
-        if (lane == kWave - 1) s_f[wid] = il;
-        if (lane == 0) s_f[NW + wid] = iu;
-        __syncthreads();
-        float pre = 0.f, suf = 0.f;
-        for (int v = 0; v < wid; ++v) pre += s_f[v];
-        for (int v = wid + 1; v < NW; ++v) suf += s_f[NW + v];
-        float run = pre + dpp_f<0x138>(il);    // wave_shr:1 -> exclusive prefix
-        float runu = dpp_f<0x130>(iu) + suf;   // wave_shl:1 -> exclusive suffix
-        // in place: vl becomes the exclusive prefix, vu the inclusive suffix
-#pragma unroll
-        for (int q = 0; q < IPT; ++q) {
-            const float t = vl[q];
-            vl[q] = run;
-            run += t;
-        }
-#pragma unroll
-        for (int q = IPT - 1; q >= 0; --q) {
-            runu += vu[q];
-            vu[q] = runu;
-        }
-        __syncthreads();   // every chunk is read before any is overwritten
-#pragma unroll
-        for (int q = 0; q < IPT; q += 4) {
-            *reinterpret_cast<float4*>(s_l + base + q) = make_float4(vl[q], vl[q + 1], vl[q + 2], vl[q + 3]);
-            *reinterpret_cast<float4*>(s_u + base + q) = make_float4(vu[q], vu[q + 1], vu[q + 2], vu[q + 3]);
-        }
-        if (threadIdx.x == BLOCK - 1) {
-            s_l[T] = run;      // z = nc = T: everything before
-            s_u[T] = 0.f;
-        }
-        __syncthreads();
-    }
-
-    // ---- E. rows: p = (C_L + S_L[z]) 2^{rl - x kappa}, q = (S_U[z] + C_U) 2^{ru + x kappa}
+    // ---- scan, rows, stores
+    fast_tile_scan<BLOCK, IPT>(s_l, s_u, A.tg.nc, s_f);
     double red = 0.0;
     RefAcc n1{0.f, kZeroExp}, n2{0.f, kZeroExp};
-    double* __restrict__ OUT = L.out + tg.r0;
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-        const int k = threadIdx.x + q * BLOCK;
-        if (k >= nc && k < nc + nr) {
-            int z = Zq[q] - (int)tg.c0;
-            z = min(max(z, 0), nc);
-            const Ext<float> E = Eq[q];
-            const float rE = __builtin_amdgcn_rcpf(E.m);
-            const float pm = cl_rel + ldexp_m(s_l[z], shl);
-            const float qm = ldexp_m(s_u[z], shu) + cu_rel;
-            const double val =
-                ext_log2n(ext_add(Ext<float>{pm * rE, rl - E.e}, Ext<float>{qm * E.m, ru + E.e}));
-            const double pnew = Dq[q] - val;
-            if (CHECK) {
-                // |psi_old (K^T phi) - v| = v |2^{g_old + t - log2 v} - 1|, exponent in FP64;
-                // the weight v = 2^{log2 v} from the row's operand
-                const double d = (dqc[q] - Dq[q]) + val;
-                const Ext<float> vv = split_exp2(Dq[q]);
-                red += (double)(ldexp_m(vv.m, vv.e) * fabsf(expm1f((float)(d * 0.69314718055994530942))));
-            }
-            OUT[k - nc] = pnew;
-            if (NEXT_AGG) {
-                Ext<float> lo, up;
-                next_terms(pnew, E, rE, lo, up);
-                ref_add(n1, lo);
-                ref_add(n2, up);
-            }
-        }
-    }
-    if (CHECK) {
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) red += __shfl_down(red, d, kWave);
-        if (lane == 0) s_d[wid] = red;
-    }
-    if (NEXT_AGG && L.ntiles > 1) block_total2_write<BLOCK>(n1, n2, s_f, s_i);
-    if (CHECK || (NEXT_AGG && L.ntiles > 1)) {
+    Ext<float> un[IPT];
+    fast_tile_rows<BLOCK, IPT, EPI, NEXT_AGG>(A, s_l, s_u, CL, CU, r0l, r0u, uold, un, red, n1, n2);
+    fast_tile_store<BLOCK, IPT>(A, L, un);
+
+    // ---- epilogue: the tile's check partial and next-sweep aggregates
+    if (CHECK) wave_sum_to<BLOCK>(red, s_d);
+    if (NEXT_AGG && multi) block_total2_write<BLOCK>(n1, n2, s_f, s_i);
+    if (CHECK || (NEXT_AGG && multi)) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            if (CHECK) {
-                double b = 0.0;
-#pragma unroll
-                for (int v = 0; v < NW; ++v) b += s_d[v];
-                partial[L.part_base + w.tile] = b;
-            }
-            if (NEXT_AGG && L.ntiles > 1) {
+            if (CHECK) partial[L.part_base + w.tile] = block_read_sum<BLOCK>(s_d);
+            if (NEXT_AGG && multi) {
                 agg_next[(long long)(L.agg_base + w.tile) * 2 + 0] = block_total_read<BLOCK>(s_f, s_i);
                 agg_next[(long long)(L.agg_base + w.tile) * 2 + 1] = block_total_read<BLOCK>(s_f + NW, s_i + NW);
             }
@@ -534,21 +667,20 @@ __global__ __launch_bounds__(BLOCK) void k_tile_aggregate_fast(const WorkItem* _
     const WorkItem w = work[blockIdx.x];
     const LineDesc L = lines[w.line];
     if (ps[L.prob].done) return;
-    const FastGeom tg = fast_geom(L, w.tile, T, L.trs[w.tile], L.trs[w.tile + 1]);
+    const gptr<const int> TRS = gbl(L.trs);
+    const FastGeom tg = fast_geom(L, w.tile, T, TRS[w.tile], TRS[w.tile + 1]);
     const int nc = tg.nc;
     const int off = tg.nr;
-    const Ext<float>* __restrict__ EC = (const Ext<float>*)L.ec + tg.c0;
-    const double* __restrict__ gin = L.gin + tg.c0;
+    const gptr<const Ext<float>> BC = gbl((const Ext<float>*)L.ec) + tg.c0;
+    const gptr<const Ext<float>> UC = gbl((const Ext<float>*)L.gin) + tg.c0;
     RefAcc n1{0.f, kZeroExp}, n2{0.f, kZeroExp};
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int j = (int)threadIdx.x + q * BLOCK - off;
         if (j >= 0 && j < nc) {
-            const Ext<float> E = EC[j];
-            Ext<float> lo, up;
-            next_terms(gin[j], E, __builtin_amdgcn_rcpf(E.m), lo, up);
-            ref_add(n1, lo);
-            ref_add(n2, up);
+            const Ext<float> U = UC[j], B = BC[j];
+            ref_add(n1, Ext<float>{U.m * B.m, U.e + B.e});
+            ref_add(n2, U);
         }
     }
     block_total2_write<BLOCK>(n1, n2, s_f, s_i);
@@ -590,8 +722,10 @@ __global__ __launch_bounds__(BLOCK) void k_tile_bounds(const BoundTask* __restri
     const long long m0 = (long long)t * tk.T;
     long long m1 = m0 + tk.T;
     if (m1 > tk.R + tk.C) m1 = tk.R + tk.C;
-    const long long r0 = min(max((long long)tk.trs[t], 0LL), tk.R);
-    const long long r1 = min(max((long long)tk.trs[t + 1], r0), tk.R);
+    const gptr<const int> TRS = gbl(tk.trs);
+    const gptr<const double> LM = gbl(tk.lmass), YC = gbl(tk.yc);
+    const long long r0 = min(max((long long)TRS[t], 0LL), tk.R);
+    const long long r1 = min(max((long long)TRS[t + 1], r0), tk.R);
     // the tile's columns plus one neighbour on each side: the carries from
     // the other tiles then lie within the bound of the tile's own terms
     const long long c0 = max(min(max(m0 - r0, 0LL), tk.C) - 1, 0LL);
@@ -599,7 +733,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_bounds(const BoundTask* __restri
     if (c1 <= c0) return;
     double mx = -__builtin_inf(), mn = __builtin_inf();
     for (long long j = c0 + threadIdx.x; j < c1; j += BLOCK) {
-        const double v = tk.lmass[j];
+        const double v = LM[j];
         mx = fmax(mx, v);
         mn = fmin(mn, v);
     }
@@ -623,7 +757,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_bounds(const BoundTask* __restri
             a = fmax(a, s_red[v]);
             b = fmin(b, s_mn[v]);
         }
-        const double bound = (a - b) + 2.0 * tk.kappa * (tk.yc[c1 - 1] - tk.yc[c0]);
+        const double bound = (a - b) + 2.0 * tk.kappa * (YC[c1 - 1] - YC[c0]);
         if (!(bound <= kFastBound)) atomicOr(flags + tk.flag, 1);
     }
 }

@@ -19,15 +19,18 @@ namespace finom {
 constexpr int kBlock = 256;     // block size of the setup / utility kernels
 constexpr double kLn2 = 0.69314718055994530942;
 
-// Scan tile shapes: threads per block x columns per thread. T = block * ipt
-// merged elements per tile. The cost sweeps (FP64 moment sums, four LDS
-// arrays) always use kCostCfg.
+// Scan tile shapes: threads per block x elements per thread. T = block * ipt
+// merged elements per tile. The FP32 fast sweeps run every shape; the general
+// sweeps run a shape as the shape `general` of the same T (they are not
+// instantiated for 512 x 4). The cost sweeps (FP64 moment sums, four LDS
+// arrays) always use kCostBlock x kCostIpt.
 struct TileCfg {
     int block, ipt;
+    int general;
     int T() const { return block * ipt; }
 };
-constexpr int kNumCfg = 4;
-constexpr TileCfg kCfgs[kNumCfg] = {{256, 4}, {256, 8}, {512, 8}, {128, 4}};
+constexpr int kNumCfg = 5;
+constexpr TileCfg kCfgs[kNumCfg] = {{256, 4, 0}, {256, 8, 1}, {512, 8, 2}, {128, 4, 3}, {512, 4, 1}};
 constexpr int kCostBlock = 256, kCostIpt = 2;
 
 struct HipError {
@@ -150,6 +153,8 @@ struct Alloc {
 struct SweepDev {
     const WorkItem* work = nullptr;        // all tiles
     int nwork = 0;
+    int max_tiles = 0;                     // largest tile count of a line
+    int max_dec = 0;                       // largest number of decision partials of a line
     const WorkItem* work_multi = nullptr;  // tiles of lines with more than one tile
     int nwork_multi = 0;
     const LineDesc* lines = nullptr;
@@ -272,8 +277,26 @@ bool fast_allowed();
 // Classifies the 1D pair (x: n, y: m) on partition pk (rows x) and its
 // transpose pkt for the fast sweeps; fills 2^{c kappa} for both meshes when
 // eligible. Synchronises the stream. Returns true when the pair is eligible.
-bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, const double* lu, const double* lv, double eps,
-                   Ext<float>** Ex, Ext<float>** Ey, hipStream_t s);
+// Conversions for the fast sweeps' state, one thread per element:
+//   mode 0: out = 2^{a + b in_k} as Ext<float> (B = 2^{2 c kappa}, the initial state);
+//   mode 1: out = in_k as Ext<float> (masses);
+//   mode 2: out = log2(state_k) + b mesh_k as double, in place over the Ext<float> state.
+struct FastStateTask {
+    void* out;
+    const double* in;
+    const double* mesh;
+    long long n;
+    double a, b;
+    int mode;
+    int pad;
+};
+void enqueue_fast_state(Alloc& al, const std::vector<FastStateTask>& tasks, hipStream_t s);
+
+// Static range bound of every tile of both products of a 1D problem; when
+// it holds, B = 2^{2 c kappa} of both meshes into *Bx / *By and the masses u,
+// v as Ext<float> over the log masses lu, lv (which the bound has read).
+bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, double* lu, double* lv, const double* u,
+                   const double* v, double eps, Ext<float>** Bx, Ext<float>** By, hipStream_t s);
 
 constexpr double kCoordLimit = 33554432.0;   // 2^25: bound on |coordinate| / (eps ln 2)
 

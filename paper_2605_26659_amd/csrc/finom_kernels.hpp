@@ -45,8 +45,9 @@ __device__ __forceinline__ TileGeom<double> tile_geom(const LineDesc& L, int til
     const long long m0 = (long long)tile * T;
     long long m1 = m0 + T;
     if (m1 > L.R + L.C) m1 = L.R + L.C;
-    g.r0 = min(max((long long)L.trs[tile], 0LL), L.R);
-    g.r1 = min(max((long long)L.trs[tile + 1], g.r0), L.R);
+    const gptr<const int> TRS = gbl(L.trs);
+    g.r0 = min(max((long long)TRS[tile], 0LL), L.R);
+    g.r1 = min(max((long long)TRS[tile + 1], g.r0), L.R);
     g.c0 = min(max(m0 - g.r0, 0LL), L.C);
     g.c1 = min(max(m1 - g.r1, g.c0), L.C);
     if (g.r1 - g.r0 > T) g.r1 = g.r0 + T;
@@ -55,7 +56,7 @@ __device__ __forceinline__ TileGeom<double> tile_geom(const LineDesc& L, int til
 }
 
 template <int INM>
-__device__ __forceinline__ double load_in(const double* p, double scale)
+__device__ __forceinline__ double load_in(gptr<const double> p, double scale)
 {
     const double v = *p;
     if (INM == IN_LOG2) return v;
@@ -68,8 +69,8 @@ __device__ __forceinline__ double load_in(const double* p, double scale)
 template <typename M, int INM, bool MOMENT>
 __device__ __forceinline__ void column_terms(const LineDesc& L, long long j, Ext<M>* t)
 {
-    const double g = load_in<INM>(L.gin + j * L.gstride, L.in_scale);
-    const double y = L.yc[j] - L.shift;
+    const double g = load_in<INM>(gbl(L.gin) + j * L.gstride, L.in_scale);
+    const double y = gbl(L.yc)[j] - L.shift;
     t[0] = ext_exp2<M>(g + y * L.kappa);
     t[1] = ext_exp2<M>(g - y * L.kappa);
     if (MOMENT) {
@@ -199,16 +200,16 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
     for (int q = 0; q < IPT; ++q) {
         if (q >= ncq) break;
         const long long j = tg.c0 + min((int)threadIdx.x + q * BLOCK, nc - 1);
-        gq[q] = load_in<INM>(L.gin + j * L.gstride, L.in_scale);
-        yq[q] = L.yc[j];
+        gq[q] = load_in<INM>(gbl(L.gin) + j * L.gstride, L.in_scale);
+        yq[q] = gbl(L.yc)[j];
     }
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         if (q >= nrq) break;
         const long long i = tg.r0 + min((int)threadIdx.x + q * BLOCK, nr - 1);
-        xq[q] = L.xr[i];
-        zq[q] = L.zeta[i];
-        if (EPI == EPI_UPDATE || CHECK || EPI == EPI_COST) a0q[q] = L.a0[i * L.ostride];
+        xq[q] = gbl(L.xr)[i];
+        zq[q] = gbl(L.zeta)[i];
+        if (EPI == EPI_UPDATE || CHECK || EPI == EPI_COST) a0q[q] = gbl(L.a0)[i * L.ostride];
     }
     Ext<M> cr[NS];
 #pragma unroll
@@ -277,8 +278,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
         for (int q = 0; q < IPT; ++q) {
             if (q >= nrq) break;
             const long long o = (tg.r0 + min((int)threadIdx.x + q * BLOCK, nr - 1)) * L.ostride;
-            vq[q] = (M)L.a1[o];          // v: weight of the error term
-            dq[q] = L.a2[o] - a0q[q];    // log2 psi_old - log2 v
+            vq[q] = (M)gbl(L.a1)[o];          // v: weight of the error term
+            dq[q] = gbl(L.a2)[o] - a0q[q];    // log2 psi_old - log2 v
         }
     }
     __syncthreads();
@@ -322,6 +323,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
     }
 
     // ---- E. rows: each queries the column scan at its dividing index
+    const gptr<double> OUT = gbl(L.out);
     double red = 0.0;
     Ext<M> nl = ext_zero<M>(), nu = ext_zero<M>();
 #pragma unroll
@@ -357,14 +359,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
         const long long o = i * L.ostride;
         double pnew = 0.0;
         if (EPI == EPI_STORE_LOG2) {
-            if (live) L.out[o] = val;
+            if (live) OUT[o] = val;
         } else if (EPI == EPI_STORE_NAT) {
-            if (live) L.out[o] = val * L.out_scale;
+            if (live) OUT[o] = val * L.out_scale;
         } else if (EPI == EPI_STORE_LIN) {
-            if (live) L.out[o] = exp2(val);
+            if (live) OUT[o] = exp2(val);
         } else if (EPI == EPI_UPDATE) {
             pnew = a0q[q] - val;
-            if (live) L.out[o] = pnew;
+            if (live) OUT[o] = pnew;
         } else if (CHECK) {
             // marginal error of the pair checked at the loop head:
             // |psi_old (K^T phi) - v| = v |2^{g_old + t - log2 v} - 1|; the
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
             const double d = dq[q] + val;
             if (live) red += (double)(vq[q] * fabs(expm1((M)(d * 0.69314718055994530942))));
             pnew = a0q[q] - val;
-            if (live) L.out[o] = pnew;
+            if (live) OUT[o] = pnew;
         } else if (EPI == EPI_COST) {
             if (live) red += exp2(a0q[q] + val);
         }

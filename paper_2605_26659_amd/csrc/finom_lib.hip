@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_dense(const double* __restrict__ xr,
         __syncthreads();
         for (int k = threadIdx.x; k < nc; k += kBlock) {
             s_y[k] = yc[c0 + k];
-            s_g[k] = load_in<INM>(gin + c0 + k, in_scale);
+            s_g[k] = load_in<INM>(gbl(gin) + c0 + k, in_scale);
         }
         __syncthreads();
         for (int k = 0; k < nc; ++k)
@@ -236,6 +236,12 @@ void upload_sweep(Alloc& al, Sweep& sw, size_t ext_b)
     HIPCHK(hipMemcpyAsync(dw, hw, sizeof(WorkItem) * tt, hipMemcpyHostToDevice, al.s));
     if (mt > 0) HIPCHK(hipMemcpyAsync(dm, hm, sizeof(WorkItem) * mt, hipMemcpyHostToDevice, al.s));
     HIPCHK(hipMemcpyAsync(dl, hl, sizeof(LineDesc) * sw.lines.size(), hipMemcpyHostToDevice, al.s));
+    sw.dev.max_tiles = 0;
+    sw.dev.max_dec = 0;
+    for (auto& L : sw.lines) {
+        sw.dev.max_tiles = std::max(sw.dev.max_tiles, L.ntiles);
+        if (L.dec_part_off >= 0) sw.dev.max_dec = std::max(sw.dev.max_dec, L.dec_nparts);
+    }
     sw.dev.work = dw;
     sw.dev.nwork = tt;
     sw.dev.work_multi = dm;
@@ -288,9 +294,15 @@ static void launch_fast_t(const Sweep& sw, ProbState* ps, double* partial, const
     if (d.nwork_multi > 0 && (agg_only || !sw.agg_from_prev))
         hipLaunchKernelGGL((k_tile_aggregate_fast<B, I>), dim3(d.nwork_multi), dim3(B), 0, s, d.work_multi, d.lines,
                            ps, (Ext<float>*)d.agg);
-    if (!agg_only)
-        hipLaunchKernelGGL((k_sweep_fast<B, I, EPI, NA>), dim3(d.nwork), dim3(B), 0, s, d.work, d.lines, ps,
-                           (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next);
+    if (!agg_only) {
+        // two fixed slots per thread cover the carries and the decision
+        if (d.max_tiles > 2 * B || d.max_dec > 2 * B)
+            hipLaunchKernelGGL((k_sweep_fast<B, I, EPI, NA, true>), dim3(d.nwork), dim3(B), 0, s, d.work, d.lines,
+                               ps, (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next);
+        else
+            hipLaunchKernelGGL((k_sweep_fast<B, I, EPI, NA, false>), dim3(d.nwork), dim3(B), 0, s, d.work, d.lines,
+                               ps, (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next);
+    }
     HIPCHK(hipGetLastError());
 }
 
@@ -345,20 +357,23 @@ static void dispatch(int precision, int inm, const Sweep& sw, ProbState* ps, dou
             case 1: dispatch_fast<256, 8>(sw, ps, partial, dec, parity, ao, s); return;
             case 2: dispatch_fast<512, 8>(sw, ps, partial, dec, parity, ao, s); return;
             case 3: dispatch_fast<128, 4>(sw, ps, partial, dec, parity, ao, s); return;
+            case 4: dispatch_fast<512, 4>(sw, ps, partial, dec, parity, ao, s); return;
         }
         throw HipError{hipErrorInvalidValue};
     }
     const int variant = variant_of(inm, sw.epi, sw.agg_next != nullptr);
     if (variant < 0) throw HipError{hipErrorInvalidValue};
+    if (sw.cfg < 0 || sw.cfg >= kNumCfg) throw HipError{hipErrorInvalidValue};
+    const int gcfg = kCfgs[sw.cfg].general;
     if (precision == 1) {
-        switch (sw.cfg) {
+        switch (gcfg) {
             case 0: FINOM_VARIANTS(float, 256, 4) break;
             case 1: FINOM_VARIANTS(float, 256, 8) break;
             case 2: FINOM_VARIANTS(float, 512, 8) break;
             case 3: FINOM_VARIANTS(float, 128, 4) break;
         }
     } else {
-        switch (sw.cfg) {
+        switch (gcfg) {
             case 0: FINOM_VARIANTS(double, 256, 4) break;
             case 1: FINOM_VARIANTS(double, 256, 8) break;
             case 2: FINOM_VARIANTS(double, 512, 8) break;
@@ -513,12 +528,48 @@ void enqueue_scale(const double* a, double* b, long long n, double f, hipStream_
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, b, n, f);
 }
 
-// 2^{c kappa} per mesh point as (mantissa in [1, 2), exponent)
-__global__ void k_exp_coords(const double* __restrict__ c, long long n, double kappa, Ext<float>* __restrict__ E)
+__global__ __launch_bounds__(kBlock) void k_fast_state(const FastStateTask* __restrict__ tasks,
+                                                      const int* __restrict__ first, int ntasks)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    E[i] = split_exp2(c[i] * kappa);
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const FastStateTask t = tasks[lo];
+    const long long k = (long long)(blockIdx.x - first[lo]) * kBlock + threadIdx.x;
+    if (k >= t.n) return;
+    if (t.mode == 0) {
+        ((Ext<float>*)t.out)[k] = split_exp2(t.a + t.b * t.in[k]);
+    } else if (t.mode == 1) {
+        int e = 0;
+        const double fr = frexp(t.in[k], &e);
+        ((Ext<float>*)t.out)[k] = Ext<float>{(float)fr, e};
+    } else {
+        const Ext<float> u = ((const Ext<float>*)t.out)[k];
+        ((double*)t.out)[k] =
+            (u.m > 0.f) ? log2((double)u.m) + (double)u.e + t.b * t.mesh[k] : -__builtin_inf();
+    }
+}
+
+void enqueue_fast_state(Alloc& al, const std::vector<FastStateTask>& tasks, hipStream_t s)
+{
+    if (tasks.empty()) return;
+    const int nt = (int)tasks.size();
+    FastStateTask* ht = al.host<FastStateTask>(nt);
+    int* hf = al.host<int>(nt + 1);
+    hf[0] = 0;
+    for (int i = 0; i < nt; ++i) {
+        ht[i] = tasks[i];
+        hf[i + 1] = hf[i] + (int)blocks_for(tasks[i].n);
+    }
+    FastStateTask* dt = al.dev<FastStateTask>(nt);
+    int* df = al.dev<int>(nt + 1);
+    HIPCHK(hipMemcpyAsync(dt, ht, sizeof(FastStateTask) * nt, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(df, hf, sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
+    if (hf[nt] > 0) hipLaunchKernelGGL(k_fast_state, dim3(hf[nt]), dim3(kBlock), 0, s, dt, df, nt);
+    HIPCHK(hipGetLastError());
 }
 
 bool fast_allowed()
@@ -528,10 +579,10 @@ bool fast_allowed()
 }
 
 
-bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, const double* lu, const double* lv, double eps,
-                   Ext<float>** Ex, Ext<float>** Ey, hipStream_t s)
+bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, double* lu, double* lv, const double* u,
+                   const double* v, double eps, Ext<float>** Bx, Ext<float>** By, hipStream_t s)
 {
-    *Ex = *Ey = nullptr;
+    *Bx = *By = nullptr;
     const double kappa = 1.0 / (eps * kLn2);
     BoundTask* ht = al.host<BoundTask>(2);
     int* hfirst = al.host<int>(3);
@@ -568,11 +619,15 @@ bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, const double* lu,
     HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hflag[0]) return false;
-    *Ex = al.dev<Ext<float>>(pk.R);
-    *Ey = al.dev<Ext<float>>(pk.C);
-    hipLaunchKernelGGL(k_exp_coords, dim3(blocks_for(pk.R)), dim3(kBlock), 0, s, pk.xr, pk.R, kappa, *Ex);
-    hipLaunchKernelGGL(k_exp_coords, dim3(blocks_for(pk.C)), dim3(kBlock), 0, s, pk.yc, pk.C, kappa, *Ey);
-    HIPCHK(hipGetLastError());
+    *Bx = al.dev<Ext<float>>(pk.R);
+    *By = al.dev<Ext<float>>(pk.C);
+    std::vector<FastStateTask> ft(4);
+    memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
+    ft[0].out = *Bx; ft[0].in = pk.xr; ft[0].n = pk.R; ft[0].b = 2.0 * kappa; ft[0].mode = 0;
+    ft[1].out = *By; ft[1].in = pk.yc; ft[1].n = pk.C; ft[1].b = 2.0 * kappa; ft[1].mode = 0;
+    ft[2].out = lu; ft[2].in = u; ft[2].n = pk.R; ft[2].mode = 1;
+    ft[3].out = lv; ft[3].in = v; ft[3].n = pk.C; ft[3].mode = 1;
+    enqueue_fast_state(al, ft, s);
     return true;
 }
 
@@ -860,15 +915,26 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         const Part pk = make_part(al, x, n, y, m, T, s);      // K psi:   rows x, columns y
         const Part pkt = make_part_transposed(al, pk, s);     // K^T phi: rows y, columns x
         const Part pc = make_part_like(al, pk, cost_tile_size(), s);
-        Ext<float>* Ex = nullptr;
-        Ext<float>* Ey = nullptr;
-        const bool fast = o.precision == 1 && fast_allowed() && setup_fast_1d(al, pk, pkt, lu, lv, eps, &Ex, &Ey, s);
+        Ext<float>* Bx = nullptr;
+        Ext<float>* By = nullptr;
+        const bool fast =
+            o.precision == 1 && fast_allowed() && setup_fast_1d(al, pk, pkt, lu, lv, u, v, eps, &Bx, &By, s);
+        const double kappa = 1.0 / (eps * kLn2);
 
-        // state: phi = 1/n, psi = 1/m (log2 units)
+        // state: phi = 1/n, psi = 1/m, as log2 potentials, or for the fast
+        // sweeps as U = w 2^{-c kappa} in the same buffers
         double* F = al.dev<double>(n);
         double* G[2] = {al.dev<double>(m), al.dev<double>(m)};
-        enqueue_fill(F, n, -log2((double)n), s);
-        enqueue_fill(G[0], m, -log2((double)m), s);
+        if (fast) {
+            std::vector<FastStateTask> ft(2);
+            memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
+            ft[0].out = F; ft[0].in = x; ft[0].n = n; ft[0].a = -log2((double)n); ft[0].b = -kappa;
+            ft[1].out = G[0]; ft[1].in = y; ft[1].n = m; ft[1].a = -log2((double)m); ft[1].b = -kappa;
+            enqueue_fast_state(al, ft, s);
+        } else {
+            enqueue_fill(F, n, -log2((double)n), s);
+            enqueue_fill(G[0], m, -log2((double)m), s);
+        }
         ProbState* ps = al.dev<ProbState>(2);      // [0] iteration, [1] cost
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
@@ -888,7 +954,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             kt[b].agg_next = agg_k;
             LineDesc a = make_line(y, m, x, n, pkt.zeta, pkt.trs, T, eps);
             a.gin = F; a.out = G[1 - b]; a.a0 = lv; a.a1 = v; a.a2 = G[b];
-            a.er = Ey; a.ec = Ex;
+            a.er = By; a.ec = Bx;
             a.dec_part_off = -1;
             kt[b].fast = kk[b].fast = fast;
             kt[b].lines.push_back(a);
@@ -900,7 +966,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             kk[b].agg_next = agg_kt;
             LineDesc c = make_line(x, n, y, m, pk.zeta, pk.trs, T, eps);
             c.gin = G[1 - b]; c.out = F; c.a0 = lu;
-            c.er = Ex; c.ec = Ey;
+            c.er = Bx; c.ec = By;
             kk[b].lines.push_back(c);
             set_decision(kk[b], 0, pkt.ntiles);
             upload_sweep(al, kt[b], eb);
@@ -921,6 +987,13 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
 
         // returned pair (F, G[l % 2]); <C, Gamma> from the FP64 moment sums
         double* Gf = G[hps[0].iters & 1];
+        if (fast) {
+            std::vector<FastStateTask> ft(2);
+            memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
+            ft[0].out = F; ft[0].mesh = x; ft[0].n = n; ft[0].b = kappa; ft[0].mode = 2;
+            ft[1].out = Gf; ft[1].mesh = y; ft[1].n = m; ft[1].b = kappa; ft[1].mode = 2;
+            enqueue_fast_state(al, ft, s);
+        }
         Sweep kc;
         kc.kind = 2;
         kc.epi = EPI_COST;

@@ -33,7 +33,13 @@ __global__ void k_tune_fill(double* __restrict__ a, long long n, double v)
 
 constexpr long long kTuneTotal = 1LL << 22;
 
-// 2^{c kappa} for the fast sweeps
+__global__ void k_tune_fill_ext(Ext<float>* __restrict__ a, long long n, float m, int e)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) a[k] = Ext<float>{m, e};
+}
+
+// 2^{c kappa} (called with 2 kappa: B of the fast sweeps)
 __global__ void k_tune_exp(const double* __restrict__ c, long long n, double kappa, Ext<float>* __restrict__ E)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -188,7 +194,17 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
         A.EX = al.dev<Ext<float>>(cap_n);
         A.EY = al.dev<Ext<float>>(cap_n);
         A.ps = al.dev<ProbState>(1);
-        for (double* d : {A.F, A.G0, A.G1, A.LU, A.LV}) HIPCHK(hipMemsetAsync(d, 0, sizeof(double) * cap_n, s));
+        if (precision == 1) {
+            // the fast sweeps' state (U = 1) and masses (2^-21) as Ext<float>
+            for (double* d : {A.F, A.G0, A.G1})
+                hipLaunchKernelGGL(k_tune_fill_ext, dim3(blocks_for(cap_n)), dim3(kBlock), 0, s, (Ext<float>*)d,
+                                   cap_n, 1.0f, 0);
+            for (double* d : {A.LU, A.LV})
+                hipLaunchKernelGGL(k_tune_fill_ext, dim3(blocks_for(cap_n)), dim3(kBlock), 0, s, (Ext<float>*)d,
+                                   cap_n, 1.0f, -21);
+        } else {
+            for (double* d : {A.F, A.G0, A.G1, A.LU, A.LV}) HIPCHK(hipMemsetAsync(d, 0, sizeof(double) * cap_n, s));
+        }
         // V: weights of the error terms; never stop (tolerance below any error)
         hipLaunchKernelGGL(k_tune_fill, dim3(blocks_for(cap_n)), dim3(kBlock), 0, s, A.V, cap_n, 1.0 / (double)cap_n);
         ProbState* hst = al.host<ProbState>(1);
@@ -203,9 +219,9 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
             const long long count = std::max(1LL, kTuneTotal / L);
             hipLaunchKernelGGL(k_tune_meshes, dim3(blocks_for(count * n)), dim3(kBlock), 0, s, A.X, n, A.Y, n, count);
             hipLaunchKernelGGL(k_tune_exp, dim3(blocks_for(count * n)), dim3(kBlock), 0, s, A.X, count * n,
-                               1.0 / kLn2, A.EX);
+                               2.0 / kLn2, A.EX);
             hipLaunchKernelGGL(k_tune_exp, dim3(blocks_for(count * n)), dim3(kBlock), 0, s, A.Y, count * n,
-                               1.0 / kLn2, A.EY);
+                               2.0 / kLn2, A.EY);
             HIPCHK(hipGetLastError());
             double tbest = 0.0;
             best[c] = 0;

@@ -80,3 +80,16 @@ def test_fast_and_general_converge_to_the_same_plan(monkeypatch):
     assert abs(r1["w1"] - r0["w1"]) <= 1e-6 * r0["w1"]
     assert abs(r1["iters"] - r0["iters"]) <= max(3, 0.01 * r0["iters"])
     assert np.max(np.abs(f1 - f0)) / p.eps <= 1e-4
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+def test_every_tile_shape_on_the_fast_path(cfg, monkeypatch):
+    """Every tile shape against the oracle, on lines of 80000 and 600002
+    elements: the second has more tiles than two per thread of a block for
+    256 x 4 and 128 x 4 (the kernel variant with remainder loops over the
+    carries and the decision partials)."""
+    monkeypatch.setenv("FINOM_TILE_CFG", str(cfg))
+    for n in (40000, 300001):
+        p = wl.config_graded_1d(n, 1e-2)
+        res = _against_oracle(p, 24)
+        assert res["fast"]
