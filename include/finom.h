@@ -70,8 +70,11 @@ typedef struct {
     double loop_ms;       /* GPU time of the iteration loop (HIP events on `stream`),
                              excluding setup and the final cost reduction             */
     int64_t sweeps;       /* half-iteration products executed in the loop: 2 l + 1     */
-    int32_t fast;         /* 1 when the loop ran the FP32 fast sweeps (every tile inside
-                             the FP32 exponent range; 1D, precision 1)                  */
+    int32_t fast;         /* 1D, precision 1, every tile inside the FP32 exponent range:
+                             1 when the loop ran the FP32 fast sweeps, 2 when it ran them
+                             in the resident solver (one cooperative launch holding the
+                             state on chip; sinkhorn_w1_1d when the tiles fit the GPU);
+                             0 otherwise                                                  */
     int32_t reserved;
 } finom_result;
 

@@ -51,7 +51,7 @@ class Result(C.Structure):
     def as_dict(self):
         return {"w1": self.w1, "marginal_err": self.marginal_err, "iters": int(self.iters),
                 "converged": bool(self.converged), "status": int(self.status),
-                "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps), "fast": bool(self.fast)}
+                "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps), "fast": int(self.fast)}
 
 
 class Problem(C.Structure):

@@ -10,6 +10,7 @@
 
 #include "../../include/finom.h"
 #include "finom_host.hpp"
+#include "finom_resident.hpp"
 
 namespace finom {
 
@@ -860,6 +861,106 @@ int dense_matvec(const double* x_rows, int64_t n, const double* y_cols, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Resident-state solver (one cooperative launch per solve)
+// ---------------------------------------------------------------------------
+constexpr int kResBlock = 512, kResIpt = 8, kResWaves = 4;
+constexpr int kResT = kResBlock * kResIpt;
+
+static bool resident_allowed()
+{
+    const char* e = getenv("FINOM_RESIDENT");
+    return !(e && e[0] == '0');
+}
+
+// Blocks of the resident kernel that can be resident at once on the current
+// device (0 when the device cannot launch it cooperatively).
+static int resident_capacity()
+{
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resident_1d<kResBlock, kResIpt, kResWaves>, kResBlock, 0) !=
+        hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+// A 1D problem of n + m points whose tiles of kResT all fit on the device at
+// once (two fixed carry slots per thread bound the tile count as well).
+static bool resident_fits(long long n, long long m)
+{
+    if (!resident_allowed()) return false;
+    const long long nt = (n + m + kResT - 1) / kResT;
+    if (nt < 2 || nt > kResBlock) return false;   // one record per thread
+    static int cap = -1;
+    static std::mutex mu;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cap < 0) cap = resident_capacity();
+    }
+    return nt <= cap;
+}
+
+// Runs the whole loop; the final phi is left in UF and the returned psi in UG
+// (both as the fast state).
+static int run_resident(Alloc& al, const Part& pk, const Part& pkt, Ext<float>* UF, Ext<float>* UG,
+                        const Ext<float>* Ax, const Ext<float>* Ay, const Ext<float>* Bx, const Ext<float>* By,
+                        ProbState* ps, ProbState* hps, hipStream_t s, finom_result* res)
+{
+    ResidentArgs a;
+    memset(&a, 0, sizeof(a));
+    a.UF = UF;
+    a.UG = UG;
+    a.Ax = Ax;
+    a.Ay = Ay;
+    a.Bx = Bx;
+    a.By = By;
+    a.zx = pk.zeta;
+    a.zy = pkt.zeta;
+    a.trs = pk.trs;
+    a.n = pk.R;
+    a.m = pk.C;
+    a.ntiles = pk.ntiles;
+    a.rec = al.dev<unsigned long long>(5 * (size_t)pk.ntiles);
+    const int groups = (pk.ntiles + kResidentGroup - 1) / kResidentGroup;
+    const size_t ncnt = (size_t)kResidentLine * (groups + 2);
+    a.counter = (unsigned*)al.dev<int>(ncnt);
+    a.fail = (int*)a.counter + kResidentLine * (groups + 1);
+    a.ps = ps;
+    a.spin_limit = kResidentSpin;
+    if (const char* e = getenv("FINOM_RESIDENT_SPIN")) a.spin_limit = (unsigned)strtoul(e, nullptr, 10);
+    HIPCHK(hipMemsetAsync(a.counter, 0, ncnt * sizeof(int), s));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int st = FINOM_OK;
+    try {
+        HIPCHK(hipEventCreate(&ev0));
+        HIPCHK(hipEventCreate(&ev1));
+        HIPCHK(hipEventRecord(ev0, s));
+        void* args[] = {&a};
+        HIPCHK(hipLaunchCooperativeKernel((const void*)k_resident_1d<kResBlock, kResIpt, kResWaves>, dim3(pk.ntiles),
+                                          dim3(kResBlock), args, 0, s));
+        HIPCHK(hipEventRecord(ev1, s));
+        int* hfail = al.host<int>(1);
+        HIPCHK(hipMemcpyAsync(hfail, a.fail, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hps, ps, sizeof(ProbState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+        res->loop_ms = ms;
+        if (*hfail) {
+            st = FINOM_E_HIP;
+            snprintf(g_last_error, sizeof(g_last_error), "resident solver: a grid wait exceeded its bound");
+        }
+    } catch (...) {
+        st = map_exception();
+    }
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
 // Algorithm 1
 // ---------------------------------------------------------------------------
 int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const double* u,
@@ -882,7 +983,9 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
     hipStream_t s = (hipStream_t)stream;
     try {
         Alloc al(stream);
-        const int cfg = tuned_cfg(o.precision, n + m);
+        // the resident solver runs tiles of 512 x 8
+        const bool try_resident = o.precision == 1 && fast_allowed() && resident_fits(n, m);
+        const int cfg = try_resident ? 2 : tuned_cfg(o.precision, n + m);
         const int T = kCfgs[cfg].T();
         const size_t eb = ext_bytes(o.precision);
 
@@ -938,6 +1041,13 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         ProbState* ps = al.dev<ProbState>(2);      // [0] iteration, [1] cost
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
+        const bool resident = try_resident && fast && T == kResT;
+        if (resident) {
+            al.uploaded();
+            const int st = run_resident(al, pk, pkt, (Ext<float>*)F, (Ext<float>*)G[0], (const Ext<float>*)lu,
+                                        (const Ext<float>*)lv, Bx, By, ps, hps, s, res);
+            if (st != FINOM_OK) return fail(st);
+        }
         const int nparts = std::max(pkt.ntiles, pc.ntiles);
         double* partial = al.dev<double>(nparts);
         // tile aggregates: each product's epilogue writes the other's
@@ -946,7 +1056,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         void* agg_kt = multi ? (void*)al.dev<char>((size_t)pk.ntiles * 2 * eb) : nullptr;
 
         Sweep kt[2], kk[2];
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < 2 && !resident; ++b) {
             kt[b].epi = EPI_UPDATE_CHECK;
             kt[b].cfg = cfg;
             kt[b].agg_from_prev = multi;
@@ -972,21 +1082,24 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             upload_sweep(al, kt[b], eb);
             upload_sweep(al, kk[b], eb);
         }
-        al.uploaded();
-        // aggregates of the initial phi for the first K^T phi
-        launch_aggregate(o.precision, IN_LOG2, kt[0], ps, s);
+        if (!resident) {
+            al.uploaded();
+            // aggregates of the initial phi for the first K^T phi
+            launch_aggregate(o.precision, IN_LOG2, kt[0], ps, s);
 
-        LoopSpec lp;
-        for (int b = 0; b < 2; ++b) {
-            lp.seq[b] = {&kt[b], &kk[b]};
-            lp.decides[b] = {false, true};
+            LoopSpec lp;
+            for (int b = 0; b < 2; ++b) {
+                lp.seq[b] = {&kt[b], &kk[b]};
+                lp.decides[b] = {false, true};
+            }
+            const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((n + m) / 2);
+            const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
+            if (st != FINOM_OK) return fail(st);
         }
-        const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((n + m) / 2);
-        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
-        if (st != FINOM_OK) return fail(st);
 
-        // returned pair (F, G[l % 2]); <C, Gamma> from the FP64 moment sums
-        double* Gf = G[hps[0].iters & 1];
+        // returned pair (F, G[l % 2]) (the resident solver leaves it in
+        // (F, G[0])); <C, Gamma> from the FP64 moment sums
+        double* Gf = resident ? G[0] : G[hps[0].iters & 1];
         if (fast) {
             std::vector<FastStateTask> ft(2);
             memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
@@ -1012,7 +1125,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         finish_result(res, hps[0], hps[1].w1);
-        res->fast = fast ? 1 : 0;
+        res->fast = fast ? (resident ? 2 : 1) : 0;
         if (hps[0].status) return fail(FINOM_E_NUMERIC);
         return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
     } catch (...) {

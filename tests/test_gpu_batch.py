@@ -38,11 +38,25 @@ def _desc_2d(p, tol=None, itr_max=None):
                                    p.itr_max if itr_max is None else itr_max))
 
 
-def _alone(d, precision):
+def _alone(d, precision, resident=False):
+    """The member solved by a single call. Batches run the streaming sweeps,
+    so by default the single call does too (FINOM_RESIDENT=0): then the
+    results agree bit for bit. With resident=True a 1D FP32 call may take the
+    resident solver, whose results agree to rounding."""
+    import os
     from paper_2605_26659_amd import sinkhorn_w1_1d, sinkhorn_w1_2d
     if d["dim"] == 1:
-        res, f, g = sinkhorn_w1_1d(d["x1"], d["x2"], d["u"], d["v"], d["eps"], d["tol"],
-                                   d["itr_max"], precision=precision)
+        old = os.environ.get("FINOM_RESIDENT")
+        if not resident:
+            os.environ["FINOM_RESIDENT"] = "0"
+        try:
+            res, f, g = sinkhorn_w1_1d(d["x1"], d["x2"], d["u"], d["v"], d["eps"], d["tol"],
+                                       d["itr_max"], precision=precision)
+        finally:
+            if old is None:
+                os.environ.pop("FINOM_RESIDENT", None)
+            else:
+                os.environ["FINOM_RESIDENT"] = old
     else:
         res, f, g = sinkhorn_w1_2d(d["x1"], d["y1"], d["x2"], d["y2"], d["u"], d["v"], d["eps"],
                                    d["tol"], d["itr_max"], precision=precision)

@@ -46,7 +46,7 @@ def test_graded_lines_match_oracle_on_either_path(n, eps, fast):
     2 kappa span ~ 193 binary orders > the bound, so the general sweeps run."""
     p = wl.config_graded_1d(n, eps)
     res = _against_oracle(p, 40)
-    assert res["fast"] == fast
+    assert bool(res["fast"]) == fast
 
 
 def test_dominant_carries():
@@ -72,10 +72,11 @@ def test_ineligible_line_runs_general_sweeps():
 
 def test_fast_and_general_converge_to_the_same_plan(monkeypatch):
     p = wl.config_graded_1d(1 << 16, 1e-2)
+    monkeypatch.setenv("FINOM_RESIDENT", "0")
     r1, f1, g1 = _solve(p, tol=1e-6, itr_max=20000)
     monkeypatch.setenv("FINOM_FAST", "0")
     r0, f0, g0 = _solve(p, tol=1e-6, itr_max=20000)
-    assert r1["fast"] and not r0["fast"]
+    assert r1["fast"] == 1 and not r0["fast"]
     assert r1["converged"] and r0["converged"]
     assert abs(r1["w1"] - r0["w1"]) <= 1e-6 * r0["w1"]
     assert abs(r1["iters"] - r0["iters"]) <= max(3, 0.01 * r0["iters"])
@@ -89,6 +90,7 @@ def test_every_tile_shape_on_the_fast_path(cfg, monkeypatch):
     256 x 4 and 128 x 4 (the kernel variant with remainder loops over the
     carries and the decision partials)."""
     monkeypatch.setenv("FINOM_TILE_CFG", str(cfg))
+    monkeypatch.setenv("FINOM_RESIDENT", "0")
     for n in (40000, 300001):
         p = wl.config_graded_1d(n, 1e-2)
         res = _against_oracle(p, 24)
