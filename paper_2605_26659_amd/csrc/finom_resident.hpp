@@ -179,12 +179,12 @@ __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l,
 // The rows of a sweep (slots [r_first, r_first + nrow), dividing index Z as a
 // column index of this tile) once the carries are known: replaces the rows'
 // states and leaves the next sweep's tile totals (and for CHECK the tile's
-// partial error) in the block's LDS slots. CHECK also writes the rows' old
-// states to `old_out` (the pair the loop head returns when it stops).
+// partial error) in the block's LDS slots. CHECK also keeps the rows' old
+// states in `old` (the pair the loop head returns when it stops).
 template <int BLOCK, int IPT, bool CHECK>
 __device__ __forceinline__ void resident_rows(const ResidentIn& in, int ncol, int r_first, int nrow, int r0l,
                                               int r0u, Ext<float>* U, const Ext<float>* s_a, const Ext<float>* B,
-                                              const int* Z, Ext<float>* old_out, const float* s_l,
+                                              const unsigned short* s_z, Ext<float>* old, const float* s_l,
                                               const float* s_u, float* s_f, int* s_i, double* s_d)
 {
     constexpr int NW = BLOCK / kWave;
@@ -204,7 +204,7 @@ __device__ __forceinline__ void resident_rows(const ResidentIn& in, int ncol, in
     for (int q = 0; q < IPT; ++q) {
         const int k = tid + q * BLOCK - r_first;
         if (k >= 0 && k < nrow) {
-            const int z = Z[q];
+            const int z = s_z[tid + q * BLOCK];
             const Ext<float> Aq = s_a[tid + q * BLOCK];
             const float pm = cl_rel + ldexp_m(s_l[z], shl);
             const float qm = ldexp_m(s_u[z], shu) + cu_rel;
@@ -215,7 +215,7 @@ __device__ __forceinline__ void resident_rows(const ResidentIn& in, int ncol, in
                 const int re = max(ep, Aq.e);
                 const float d = __builtin_fmaf(ldexp_m(U[q].m, ep - re), W.m, -ldexp_m(Aq.m, Aq.e - re));
                 red += __builtin_amdgcn_ldexp((double)fabsf(d), re);
-                old_out[k] = U[q];
+                old[q] = U[q];
             }
             U[q] = Un;
             ref_add(n1, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
@@ -240,7 +240,8 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
     __shared__ float s_f[6 * NW];
     __shared__ int s_i[6 * NW];
     __shared__ double s_d[NW];
-    __shared__ Ext<float> s_a[T];   // the slots' masses
+    __shared__ Ext<float> s_a[T];           // the slots' masses
+    __shared__ unsigned short s_z[T];       // the slots' dividing indices (as rows), within the tile
 
     const int tile = blockIdx.x;
     const int nt = a.ntiles;
@@ -258,10 +259,10 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
     const int nc = (int)(c1 - c0);
     const int nr = (int)min(r1 - r0, (long long)(T - nc));
 
-    // per slot: state, mass (LDS), B and, as a row, its dividing index as a
-    // column index of this tile (y rows over the tile's x, x rows over its y)
+    // per slot: state and B in registers; mass and, as a row, its dividing
+    // index as a column index of this tile (y rows over the tile's x, x rows
+    // over its y; at most T, so 16 bits) in LDS
     Ext<float> U[IPT], B[IPT];
-    int Z[IPT];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int k = threadIdx.x + q * BLOCK;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         s_a[k] = isy ? a.Ay[jy] : a.Ax[jx];
         B[q] = isy ? a.By[jy] : a.Bx[jx];
         const long long z = isy ? (long long)a.zy[jy] - r0 : (long long)a.zx[jx] - c0;
-        Z[q] = (int)min(max(z, 0LL), (long long)(isy ? nr : nc));
+        s_z[k] = (unsigned short)min(max(z, 0LL), (long long)(isy ? nr : nc));
     }
 
     // The loop. Each sweep: its columns and their scan (local, done while the
@@ -309,6 +310,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
     double err = 0.0;
     bool ok = true;
     ResidentIn in;
+    Ext<float> uold[IPT];   // the y points' states the loop head checks
     for (;;) {
         // ---- K^T phi with the marginal check: columns x, rows y
         resident_columns<BLOCK, IPT>(nc, nr, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
@@ -316,8 +318,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         ok = resident_wait(a, gen, &s_flag);
         if (!ok) break;
         resident_read<false>(a, rec_x, nullptr, in);
-        resident_rows<BLOCK, IPT, true>(in, nr, 0, nc, rxl, rxu, U, s_a, B, Z, a.UG + c0, s_l, s_u, s_f, s_i,
-                                        s_d);
+        resident_rows<BLOCK, IPT, true>(in, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
         ++gen;
@@ -340,9 +341,17 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         wave_sum_to<BLOCK>(in.part, s_d);
         __syncthreads();
         err = block_read_sum<BLOCK>(s_d);
-        if (l >= itr_max || !(err > tol)) break;
+        if (l >= itr_max || !(err > tol)) {
+            // the returned psi: the states the loop head checked
+#pragma unroll
+            for (int q = 0; q < IPT; ++q) {
+                const int k = threadIdx.x + q * BLOCK;
+                if (k < nc) a.UG[c0 + k] = uold[q];
+            }
+            break;
+        }
         // ---- K psi: rows x
-        resident_rows<BLOCK, IPT, false>(in, nc, nc, nr, ryl, ryu, U, s_a, B, Z, nullptr, s_l, s_u, s_f, s_i,
+        resident_rows<BLOCK, IPT, false>(in, nc, nc, nr, ryl, ryu, U, s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i,
                                          s_d);
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
@@ -354,8 +363,8 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         __syncthreads();   // the LDS scans of K psi are read
         ++l;
     }
-    // the returned pair: the current phi, and the psi the loop head checked
-    // (written to UG by the checking sweep)
+    // the returned pair: the current phi (and the psi the loop head checked,
+    // written above)
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int k = threadIdx.x + q * BLOCK;
