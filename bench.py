@@ -32,34 +32,51 @@ HBM_PEAK_GBS = 8000.0
 BYTES_KT = (16, 32)
 BYTES_K = (24, 16)
 
-# HBM traffic of the two sweep kernels measured with rocprofv3 FETCH_SIZE and
-# WRITE_SIZE at n = m = 2^20 (KiB per dispatch, mean of the two variants),
-# each scaled by the counter's reading for a plain device copy of known size.
-# Valid only for the kernel sources whose digest is recorded beside them;
-# after any change to those sources the traffic is reported as null.
-TRAFFIC = {"sources_sha256": "df8c12b9d2fec292f3c97345f1129789419172251e3eb7e63e78d97a38a865b7",
-           "fetch_kib": 20800.75, "write_kib": 8218.30,
-           "fetch_scale": 262144 / 131084, "write_scale": 262144 / 262144, "n": 1 << 20}
-KERNEL_SOURCES = ("paper_2605_26659_amd/csrc/finom_kernels.hpp",
-                  "paper_2605_26659_amd/csrc/finom_device.hpp",
-                  "paper_2605_26659_amd/csrc/finom_fast.hpp",
-                  "paper_2605_26659_amd/csrc/finom_types.hpp")
+# The resident solver (one cooperative launch per solve, state on chip) is
+# bound by arithmetic and latency, not by HBM. Its algorithmic work is counted
+# in lane operations per grid point per iteration: every FP32 / FP64 add,
+# multiply, fused multiply-add, ldexp, reciprocal, frexp and conversion
+# counts once, integer exponent arithmetic does not. An x point costs 3 as a
+# column, 4 in the column scan and 17 as a row; a y point the same plus 6 for
+# the marginal check: 54 per (x, y) pair, i.e. per grid point.
+OPS_PER_PT_ITER = 54
+# One lane operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz (packed FP32 instructions are not used).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# HBM traffic measured with rocprofv3 FETCH_SIZE and WRITE_SIZE at
+# n = m = 2^20 (KiB per dispatch), each scaled by the counter's reading for a
+# plain device copy of known size: for the resident kernel per launch (one
+# solve at eps = 1e-3, tol 1e-6), for the streaming sweeps per sweep (mean of
+# the two variants). Valid only for the kernel sources whose digest is
+# recorded beside them; after any change to those sources the traffic is null.
+FETCH_SCALE = 262144 / 131084
+WRITE_SCALE = 262144 / 262144
+TRAFFIC_RESIDENT = {"sources_sha256": "1af82088474e7046f488032be36600e20eee483f526b240972a3db22ac521b0c",
+                    "fetch_kib": 308332.0, "write_kib": 422607.0, "n": 1 << 20}
+TRAFFIC_STREAM = {"sources_sha256": "cdedeb22e36a32830477ce4c70afdf9dc1a95834a628ae1f32b2934952ca0711",
+                  "fetch_kib": (22823.5 + 18713.6) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
+RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
+                    "paper_2605_26659_amd/csrc/finom_fast.hpp",
+                    "paper_2605_26659_amd/csrc/finom_kernels.hpp",
+                    "paper_2605_26659_amd/csrc/finom_device.hpp",
+                    "paper_2605_26659_amd/csrc/finom_types.hpp")
+STREAM_SOURCES = RESIDENT_SOURCES[1:]
 
 
-def kernel_sources_digest():
+def sources_digest(paths):
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in paths:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(n):
-    t = TRAFFIC
-    if t["sources_sha256"] is None or n != t["n"] or kernel_sources_digest() != t["sources_sha256"]:
+def measured_traffic(t, paths, n):
+    if t["sources_sha256"] is None or n != t["n"] or sources_digest(paths) != t["sources_sha256"]:
         return None
-    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+    return 1024.0 * (t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE)
 
 
 def parse():
@@ -187,9 +204,9 @@ def bench_batch(precision):
 
 def bench_other_configs(precision):
     """The other single-problem configurations, one timed solve each after a
-    warm-up: the small 1D correctness case (FP64 scans, tol 1e-9, cap 2000),
-    the graded 1D workload at eps = 1e-2, and the 2D 1024 x 1024 tanh mesh
-    (eps = 5e-3, tol 1e-6)."""
+    warm-up: the headline workload on the streaming sweeps, the small 1D
+    correctness case (FP64 scans, tol 1e-9, cap 2000), the graded 1D workload
+    at eps = 1e-2, and the 2D 1024 x 1024 tanh mesh (eps = 5e-3, tol 1e-6)."""
     import torch
     from paper_2605_26659_amd import sinkhorn_w1_1d, sinkhorn_w1_2d, workloads as wl
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
@@ -204,8 +221,31 @@ def bench_other_configs(precision):
         dt = time.perf_counter() - t0
         return {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
                 "iters": r["iters"], "w1": r["w1"], "marginal_err": r["marginal_err"],
-                "converged": r["converged"], "scan_mantissa": "fp32" if prec == 1 else "fp64"}
+                "converged": r["converged"], "scan_mantissa": "fp32" if prec == 1 else "fp64",
+                "resident": r["fast"] == 2, "loop_ms": r["loop_ms"]}
 
+    # the headline workload on the streaming sweeps (the path taken by
+    # problems too large for the resident solver, and by batches)
+    if precision == 1:
+        old = os.environ.get("FINOM_RESIDENT")
+        os.environ["FINOM_RESIDENT"] = "0"
+        try:
+            p = wl.config_graded_1d(1 << 20, 1e-3)
+            r = run1d(p, 1)
+        finally:
+            if old is None:
+                os.environ.pop("FINOM_RESIDENT", None)
+            else:
+                os.environ["FINOM_RESIDENT"] = old
+        n = len(p.x)
+        per_sweep = ((BYTES_KT[0] + BYTES_K[0]) * n + (BYTES_KT[1] + BYTES_K[1]) * n) / 2.0
+        sweep_s = r.pop("loop_ms") * 1e-3 / (2 * r["iters"] + 1)
+        gbs = per_sweep / sweep_s / 1e9
+        r["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(TRAFFIC_STREAM, STREAM_SOURCES, n),
+                         "avg_sweep_us": sweep_s * 1e6, "algorithmic_bytes_per_sweep": per_sweep}
+        out["graded_1d_streaming"] = r
     p = wl.config_small_1d()
     out["small_1d_n512"] = run1d(p, 0)
     out["small_1d_n512"]["workload"] = "n=m=512 sorted U(0,1), masses U(0.1,1), eps=0.01, tol=1e-9, cap 2000"
@@ -374,19 +414,36 @@ def main():
     total = time.perf_counter() - t_start
     value = pts * sum(its) / total
 
-    # dominant kernels: the half-iteration sweeps; average launch duration from
-    # the loop's HIP events divided by the sweeps executed
     n, m = len(prob.x), len(prob.y)
     bytes_iter = (BYTES_KT[0] + BYTES_K[0]) * n + (BYTES_KT[1] + BYTES_K[1]) * m
     per_sweep_bytes = bytes_iter / 2.0
     sweep_ms = sum(loops) / max(1, sum(sweeps))
-    achieved = per_sweep_bytes / (sweep_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.n),
-                "kernel": "the loop's sweeps, both half-iteration variants (K^T phi with the "
-                          "fused marginal check, K psi), averaged over the loop's launches",
-                "avg_sweep_us": sweep_ms * 1e3,
-                "algorithmic_bytes_per_sweep": per_sweep_bytes}
+    if last["fast"] == 2:
+        # dominant kernel: the resident solver, one launch per solve, timed by
+        # HIP events around the launch on its stream
+        launch_ms = sum(loops) / len(loops)
+        ops = OPS_PER_PT_ITER * pts * sum(its) / len(its)
+        achieved = ops / (launch_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                    "frac": achieved / ALU_PEAK_TOPS,
+                    "traffic": measured_traffic(TRAFFIC_RESIDENT, RESIDENT_SOURCES, args.n),
+                    "kernel": "k_resident_1d: the whole loop in one cooperative launch",
+                    "avg_launch_ms": launch_ms, "avg_sweep_us": sweep_ms * 1e3,
+                    "ops_per_grid_pt_iter": OPS_PER_PT_ITER,
+                    "unit_note": "lane operations (each add, multiply, fma, ldexp, reciprocal counts once) "
+                                 "against 256 CUs x 64 lanes x 2.4 GHz",
+                    "streaming_equivalent_GBs": per_sweep_bytes / (sweep_ms * 1e-3) / 1e9}
+    else:
+        # dominant kernels: the half-iteration sweeps; average launch duration
+        # from the loop's HIP events divided by the sweeps executed
+        achieved = per_sweep_bytes / (sweep_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": measured_traffic(TRAFFIC_STREAM, STREAM_SOURCES, args.n),
+                    "kernel": "the loop's sweeps, both half-iteration variants (K^T phi with the "
+                              "fused marginal check, K psi), averaged over the loop's launches",
+                    "avg_sweep_us": sweep_ms * 1e3,
+                    "algorithmic_bytes_per_sweep": per_sweep_bytes}
 
     extra = {}
     if not args.no_fp64_compare:
