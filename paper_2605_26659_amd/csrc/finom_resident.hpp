@@ -36,42 +36,68 @@ struct ResidentArgs {
     long long n, m;
     int ntiles;               // at most the block size
     int pad;
-    unsigned long long* rec;  // records: [ntiles][2] x totals, [ntiles][2] y totals, [ntiles] partial errors
-    unsigned* counter;        // barrier counters (top, then one per group of blocks), zero at launch
+    unsigned long long* rec;  // tagged records: [ntiles][2] x totals, [ntiles][2] y totals, [ntiles] partial errors; zero at launch
+    unsigned* counter;        // arrival counters [copy][group], 256 bytes apart; zero at launch
     int* fail;                // set when a wait exceeds its bound
     unsigned spin_limit;      // polls before a wait gives up
+    int group;                // blocks per arrival group (ntiles / group <= 64)
+    int copies;               // copies of the arrival counters (<= 64)
     ProbState* ps;
 };
 
 // ---- exchange between blocks
-// After each sweep every block publishes its tile's totals (and, for the
-// checking sweep, its partial error) into one of three record buffers and
-// counts itself in at a grid barrier; after the barrier every block reads all
-// records of the buffer. Records are written with agent-scope exchanges whose
-// completion the writer waits for before it arrives, and read with
-// agent-scope atomic loads: both complete at the device's coherence point,
-// so no cache maintenance is needed (a release / acquire pair would write
-// back and invalidate the L2 of every XCD once per block). The barrier
-// counts in two levels (a counter per group of blocks, the last block of a
-// group counts the group in at the top counter) to spread the atomic traffic;
-// every block polls the top counter. A buffer is written again only after a
-// later barrier, which every block reaches only after it has read the buffer.
+// After each sweep a block publishes its tile's totals (and, for the checking
+// sweep, its partial error) into one of three record buffers and counts
+// itself in at a grid barrier; after the barrier every block reads the
+// records of the buffer. Records are written with agent-scope atomic stores
+// and read with agent-scope atomic loads, both of which complete at the
+// device's coherence point, so no cache maintenance is needed (a release /
+// acquire pair would write back and invalidate the L2 of every XCD once per
+// block). Neither the records nor the arrival wait for completion: each
+// record carries a one-bit tag, and a reader that finds the previous write
+// of a record reads it again.
+//
+// Tags. The k-th write of a record carries tag k & 1. A reader waiting for
+// write k can only find write k - 1 or write k there: write k + 1 comes after
+// its writer has passed a barrier that this reader's own arrival, made after
+// this read, completes. A zeroed buffer holds tag 0, as if written 0 times.
+// The tag is the sign bit of the word: a total (an Ext<float> whose mantissa
+// is 0 or in [1/2, 1)) keeps its mantissa's bits in the high half and its
+// exponent in the low half; a partial error is a non-negative double. Both
+// are restored exactly.
+//
+// Arrival. Blocks form groups of a.group; a group has one arrival counter in
+// each of a.copies copies, and an arriving block adds 1 to its group's
+// counter in every copy (one lane per copy, no return value). A block waits
+// by polling the counters of all groups in one copy (blockIdx % a.copies),
+// one lane per group: the copies spread the
+// polls, the groups spread the additions. Barrier gen is complete when every
+// group's counter holds gen times the group's size; a counter cannot count a
+// later barrier's arrival before every block has arrived at this one.
 constexpr unsigned kResidentSpin = 1u << 22;   // default bound of a wait, in polls (~seconds)
-constexpr int kResidentGroup = 16;             // blocks per first-level counter
+constexpr int kResidentGroup = 16;             // blocks per group (at least ntiles / 64)
+constexpr int kResidentCopies = 8;             // copies of the arrival counters
 constexpr int kResidentLine = 64;              // counters 256 bytes apart
 
-__device__ __forceinline__ unsigned long long u64_of(Ext<float> v)
+__device__ __forceinline__ unsigned long long rec_of(Ext<float> v, unsigned tag)
 {
-    unsigned long long r;
-    __builtin_memcpy(&r, &v, sizeof(r));
-    return r;
+    const unsigned hi = (__float_as_uint(v.m) & 0x7FFFFFFFu) | (tag << 31);
+    return ((unsigned long long)hi << 32) | (unsigned)v.e;
 }
 
-__device__ __forceinline__ Ext<float> ext_of(unsigned long long w)
+__device__ __forceinline__ Ext<float> ext_of_rec(unsigned long long w)
 {
-    Ext<float> r;
-    __builtin_memcpy(&r, &w, sizeof(r));
-    return r;
+    return Ext<float>{__uint_as_float((unsigned)(w >> 32) & 0x7FFFFFFFu), (int)(unsigned)w};
+}
+
+__device__ __forceinline__ unsigned long long rec_of(double v, unsigned tag)
+{
+    return ((unsigned long long)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull) | ((unsigned long long)tag << 63);
+}
+
+__device__ __forceinline__ double double_of_rec(unsigned long long w)
+{
+    return __longlong_as_double((long long)(w & 0x7FFFFFFFFFFFFFFFull));
 }
 
 __device__ __forceinline__ unsigned long long rec_load(const unsigned long long* p)
@@ -79,48 +105,78 @@ __device__ __forceinline__ unsigned long long rec_load(const unsigned long long*
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread 0 of a block: writes n words and waits until the writes have
-// completed at the coherence point.
-__device__ __forceinline__ void resident_publish(unsigned long long* p0, unsigned long long v0,
-                                                 unsigned long long* p1, unsigned long long v1,
-                                                 unsigned long long* p2, unsigned long long v2)
+__device__ __forceinline__ void resident_fail(const ResidentArgs& a, int* s_flag)
 {
-    unsigned long long w = __hip_atomic_exchange(p0, v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    w ^= __hip_atomic_exchange(p1, v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (p2) w ^= __hip_atomic_exchange(p2, v2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    asm volatile("s_waitcnt vmcnt(0)" : : "v"((unsigned)w) : "memory");
+    __hip_atomic_store(a.fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = 0;
 }
 
-// The grid barrier in two halves, so that a block can do its local work
-// between them. Thread 0 arrives after its publication has completed; every
-// block arrives and waits the same number of times. resident_wait returns
-// false when the wait exceeded its bound or another block reported that;
-// then every later wait returns false at once.
-__device__ __forceinline__ void resident_arrive(const ResidentArgs& a, unsigned gen)
+// Reads a record until it carries the expected tag (bounded: on failure the
+// block's flag is cleared, and its next wait ends it).
+__device__ __forceinline__ unsigned long long rec_read(const ResidentArgs& a, const unsigned long long* p,
+                                                       unsigned tag, int* s_flag)
 {
-    const unsigned nb = gridDim.x;
-    const unsigned g = blockIdx.x / kResidentGroup;
-    const unsigned gsz = min((unsigned)kResidentGroup, nb - g * kResidentGroup);
-    unsigned* grp = a.counter + kResidentLine * (1 + g);
-    const unsigned old = __hip_atomic_fetch_add(grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == gen * gsz - 1) __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long w = rec_load(p);
+    unsigned polls = 0;
+    while ((unsigned)(w >> 63) != tag) {
+        if (++polls > a.spin_limit) {
+            resident_fail(a, s_flag);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        w = rec_load(p);
+    }
+    return w;
 }
 
+// Wave 0 of a block, with wave-uniform arguments: writes the block's records
+// (lane i writes word i, n words) and counts the block in at its group's
+// counter in every copy. Nothing waits for these writes.
+__device__ __forceinline__ void resident_signal(const ResidentArgs& a, int n, unsigned long long* p0,
+                                                unsigned long long w0, unsigned long long* p1, unsigned long long w1,
+                                                unsigned long long* p2, unsigned long long w2)
+{
+    const int lane = threadIdx.x;
+    if (lane < n) {
+        unsigned long long* p = lane == 0 ? p0 : lane == 1 ? p1 : p2;
+        const unsigned long long w = lane == 0 ? w0 : lane == 1 ? w1 : w2;
+        __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane < a.copies) {
+        const unsigned gs = (unsigned)a.group;
+        const unsigned G = (gridDim.x + gs - 1) / gs;
+        __hip_atomic_fetch_add(a.counter + kResidentLine * (lane * G + blockIdx.x / gs), 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The wait for barrier gen (the arrival is resident_signal; a block's own
+// work runs between the two). Every block arrives and waits the same number
+// of times. Returns false when a wait of this block failed (its bound, or
+// another block's failure seen through the fail flag, checked every 64
+// polls); a block that has failed arrives no more, so every other block's
+// wait then fails too.
 __device__ __forceinline__ bool resident_wait(const ResidentArgs& a, unsigned gen, int* s_flag)
 {
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned G = (gridDim.x + kResidentGroup - 1) / kResidentGroup;
+    if (threadIdx.x < kWave) {
+        const unsigned nb = gridDim.x, gs = (unsigned)a.group;
+        const unsigned G = (nb + gs - 1) / gs;
+        const unsigned h = min((unsigned)threadIdx.x, G - 1);
+        const unsigned need = gen * min(gs, nb - h * gs);
+        const unsigned* c = a.counter + kResidentLine * ((blockIdx.x % (unsigned)a.copies) * G + h);
+        int ok = __builtin_amdgcn_readfirstlane(*s_flag);
         unsigned polls = 0;
-        while (__hip_atomic_load(a.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gen * G) {
-            if (__hip_atomic_load(a.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || ++polls > a.spin_limit) {
-                __hip_atomic_store(a.fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (ok) {
+            const unsigned v = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__builtin_amdgcn_ballot_w64((int)(v - need) < 0) == 0) break;
+            ++polls;
+            if (polls > a.spin_limit ||
+                ((polls & 63) == 0 && __hip_atomic_load(a.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
                 ok = 0;
-                break;
-            }
+            ok = __builtin_amdgcn_readfirstlane(ok);
             __builtin_amdgcn_s_sleep(1);
         }
-        *s_flag = ok;
+        if (!ok && threadIdx.x == 0) resident_fail(a, s_flag);
     }
     __syncthreads();
     return *s_flag != 0;
@@ -136,18 +192,19 @@ struct ResidentIn {
 
 template <bool PART>
 __device__ __forceinline__ void resident_read(const ResidentArgs& a, const unsigned long long* tot,
-                                              const unsigned long long* part, ResidentIn& in)
+                                              const unsigned long long* part, unsigned tag, int* s_flag,
+                                              ResidentIn& in)
 {
     const int t = threadIdx.x, tile = blockIdx.x, nt = a.ntiles;
     in.cl = in.cu = ext_zero<float>();
     in.part = 0.0;
     if (t < nt) {
-        if (t < tile) in.cl = ext_of(rec_load(tot + 2 * t));
-        if (t > tile) in.cu = ext_of(rec_load(tot + 2 * t + 1));
-        if (PART) {
-            const unsigned long long w = rec_load(part + t);
-            __builtin_memcpy(&in.part, &w, sizeof(w));
+        if (t != tile) {
+            const Ext<float> v = ext_of_rec(rec_read(a, tot + 2 * t + (t > tile ? 1 : 0), tag, s_flag));
+            if (t < tile) in.cl = v;
+            else in.cu = v;
         }
+        if (PART) in.part = double_of_rec(rec_read(a, part + t, tag, s_flag));
     }
 }
 
@@ -280,6 +337,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
     // other blocks finish the previous sweep), the wait for the previous
     // sweep's records, the carries, the rows, publication and arrival.
     __shared__ int s_flag;
+    if (threadIdx.x == 0) s_flag = 1;
     unsigned gen = 0;
     // the first sweep's column totals (x points) from the initial state
     Ext<float> own_l, own_u;
@@ -298,10 +356,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
         ++gen;
-        if (threadIdx.x == 0) {
-            resident_publish(rec_x + 2 * tile, u64_of(own_l), rec_x + 2 * tile + 1, u64_of(own_u), nullptr, 0);
-            resident_arrive(a, gen);
-        }
+        if (threadIdx.x < kWave)
+            resident_signal(a, 2, rec_x + 2 * tile, rec_of(own_l, 1u), rec_x + 2 * tile + 1, rec_of(own_u, 1u),
+                            nullptr, 0);
     }
 
     const long long itr_max = a.ps->itr_max;
@@ -315,20 +372,19 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         // ---- K^T phi with the marginal check: columns x, rows y
         resident_columns<BLOCK, IPT>(nc, nr, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
         const int rxl = own_l.e, rxu = own_u.e;
+        // records of this iteration's sweeps: write l + 1 of their buffers
+        const unsigned tag = (unsigned)((l + 1) & 1);
         ok = resident_wait(a, gen, &s_flag);
         if (!ok) break;
-        resident_read<false>(a, rec_x, nullptr, in);
+        resident_read<false>(a, rec_x, nullptr, tag, &s_flag, in);
         resident_rows<BLOCK, IPT, true>(in, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
         ++gen;
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < kWave) {
             const double pe = block_read_sum<BLOCK>(s_d);
-            unsigned long long pb;
-            __builtin_memcpy(&pb, &pe, sizeof(pb));
-            resident_publish(rec_y + 2 * tile, u64_of(own_l), rec_y + 2 * tile + 1, u64_of(own_u), rec_p + tile,
-                             pb);
-            resident_arrive(a, gen);
+            resident_signal(a, 3, rec_y + 2 * tile, rec_of(own_l, tag), rec_y + 2 * tile + 1, rec_of(own_u, tag),
+                            rec_p + tile, rec_of(pe, tag));
         }
         // ---- K psi: its columns (y) while the others finish, then the loop
         // head (every block sums the partials in the same order)
@@ -337,7 +393,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         const int ryl = own_l.e, ryu = own_u.e;
         ok = resident_wait(a, gen, &s_flag);
         if (!ok) break;
-        resident_read<true>(a, rec_y, rec_p, in);
+        resident_read<true>(a, rec_y, rec_p, tag, &s_flag, in);
         wave_sum_to<BLOCK>(in.part, s_d);
         __syncthreads();
         err = block_read_sum<BLOCK>(s_d);
@@ -356,10 +412,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
         ++gen;
-        if (threadIdx.x == 0) {
-            resident_publish(rec_x + 2 * tile, u64_of(own_l), rec_x + 2 * tile + 1, u64_of(own_u), nullptr, 0);
-            resident_arrive(a, gen);
-        }
+        if (threadIdx.x < kWave)
+            resident_signal(a, 2, rec_x + 2 * tile, rec_of(own_l, tag ^ 1u), rec_x + 2 * tile + 1,
+                            rec_of(own_u, tag ^ 1u), nullptr, 0);
         __syncthreads();   // the LDS scans of K psi are read
         ++l;
     }
