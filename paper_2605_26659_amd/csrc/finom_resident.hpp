@@ -239,7 +239,7 @@ __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l,
 // partial error) in the block's LDS slots. CHECK also keeps the rows' old
 // states in `old` (the pair the loop head returns when it stops).
 template <int BLOCK, int IPT, bool CHECK>
-__device__ __forceinline__ void resident_rows(const ResidentIn& in, int ncol, int r_first, int nrow, int r0l,
+__device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<float> CU, int ncol, int r_first, int nrow, int r0l,
                                               int r0u, Ext<float>* U, const Ext<float>* s_a, const Ext<float>* B,
                                               const unsigned short* s_z, Ext<float>* old, const float* s_l,
                                               const float* s_u, float* s_f, int* s_i, double* s_d)
@@ -248,10 +248,6 @@ __device__ __forceinline__ void resident_rows(const ResidentIn& in, int ncol, in
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     asm volatile("" : "+s"(ncol), "+s"(r_first), "+s"(nrow));
-    block_total2_write<BLOCK>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, s_f + 2 * NW, s_i + 2 * NW);
-    __syncthreads();
-    const Ext<float> CL = block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW);
-    const Ext<float> CU = block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW);
     const int rl = max(r0l, CL.e), ru = max(r0u, CU.e);
     const float cl_rel = ldexp_m(CL.m, CL.e - rl), cu_rel = ldexp_m(CU.m, CU.e - ru);
     const int shl = r0l - rl, shu = r0u - ru;
@@ -377,7 +373,11 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         ok = resident_wait(a, gen, &s_flag);
         if (!ok) break;
         resident_read<false>(a, rec_x, nullptr, tag, &s_flag, in);
-        resident_rows<BLOCK, IPT, true>(in, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
+        block_total2_write<BLOCK>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, s_f + 2 * NW, s_i + 2 * NW);
+        __syncthreads();
+        resident_rows<BLOCK, IPT, true>(block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW),
+                                        block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW), nr, 0, nc, rxl, rxu, U,
+                                        s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
         ++gen;
@@ -394,6 +394,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         ok = resident_wait(a, gen, &s_flag);
         if (!ok) break;
         resident_read<true>(a, rec_y, rec_p, tag, &s_flag, in);
+        block_total2_write<BLOCK>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, s_f + 2 * NW, s_i + 2 * NW);
         wave_sum_to<BLOCK>(in.part, s_d);
         __syncthreads();
         err = block_read_sum<BLOCK>(s_d);
@@ -407,8 +408,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
             break;
         }
         // ---- K psi: rows x
-        resident_rows<BLOCK, IPT, false>(in, nc, nc, nr, ryl, ryu, U, s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i,
-                                         s_d);
+        resident_rows<BLOCK, IPT, false>(block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW),
+                                         block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW), nc, nc, nr, ryl, ryu, U,
+                                         s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i, s_d);
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
         ++gen;
