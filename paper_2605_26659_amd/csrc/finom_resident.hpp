@@ -208,6 +208,74 @@ __device__ __forceinline__ void resident_read(const ResidentArgs& a, const unsig
     }
 }
 
+// ---- block totals
+// The per-wave parts of a block's two extended totals (each against the
+// wave's largest exponent) and, with D, of a double sum, as one interleaved
+// sequence of DPP steps so that the independent reductions fill each other's
+// wait states; lane 0 of each wave leaves them in LDS for block_total_read /
+// block_read_sum after a barrier. The order of every sum is fixed.
+template <int C, int R>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<C, R>(0, (int)(b & 0xffffffffLL));
+    const int hi = dpp_i<C, R>(0, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int C, int R, bool D>
+__device__ __forceinline__ void tot_step1(int& ra, int& rb, double& d)
+{
+    ra = max(ra, dpp_i<C, R>(kZeroExp, ra));
+    rb = max(rb, dpp_i<C, R>(kZeroExp, rb));
+    if (D) d += dpp_d<C, R>(d);
+}
+
+template <int C, int R>
+__device__ __forceinline__ void tot_step2(float& sa, float& sb)
+{
+    sa += dpp_f<C, R>(sa);
+    sb += dpp_f<C, R>(sb);
+}
+
+template <int BLOCK, bool D>
+__device__ __forceinline__ void block_totals_write(RefAcc a, RefAcc b, double d, float* s_f, int* s_i, double* s_d)
+{
+    constexpr int NW = BLOCK / kWave;
+    int ra = a.r, rb = b.r;
+    tot_step1<0x111, 0xF, D>(ra, rb, d);   // row_shr:1
+    tot_step1<0x112, 0xF, D>(ra, rb, d);   // row_shr:2
+    tot_step1<0x114, 0xF, D>(ra, rb, d);   // row_shr:4
+    tot_step1<0x118, 0xF, D>(ra, rb, d);   // row_shr:8
+    tot_step1<0x142, 0xA, D>(ra, rb, d);   // row_bcast:15
+    tot_step1<0x143, 0xC, D>(ra, rb, d);   // row_bcast:31
+    ra = __builtin_amdgcn_readlane(ra, kWave - 1);
+    rb = __builtin_amdgcn_readlane(rb, kWave - 1);
+    float sa = ldexp_m(a.s, a.r - ra), sb = ldexp_m(b.s, b.r - rb);
+    tot_step2<0x111, 0xF>(sa, sb);
+    tot_step2<0x112, 0xF>(sa, sb);
+    tot_step2<0x114, 0xF>(sa, sb);
+    tot_step2<0x118, 0xF>(sa, sb);
+    tot_step2<0x142, 0xA>(sa, sb);
+    tot_step2<0x143, 0xC>(sa, sb);
+    sa = readlane_f(sa, kWave - 1);
+    sb = readlane_f(sb, kWave - 1);
+    if (D) {
+        const long long db = __double_as_longlong(d);
+        const int lo = __builtin_amdgcn_readlane((int)(db & 0xffffffffLL), kWave - 1);
+        const int hi = __builtin_amdgcn_readlane((int)(db >> 32), kWave - 1);
+        d = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const int wid = threadIdx.x / kWave;
+        s_f[wid] = sa;
+        s_i[wid] = ra;
+        s_f[NW + wid] = sb;
+        s_i[NW + wid] = rb;
+        if (D) s_d[wid] = d;
+    }
+}
+
 // The local half of a sweep: the column terms (slots [c_first, c_first +
 // ncol), column index k - c_first) against the tile's own totals, to LDS, and
 // their in-tile scan. Needs nothing from other blocks.
@@ -253,14 +321,22 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
     const int shl = r0l - rl, shu = r0u - ru;
     double red = 0.0;
     RefAcc n1{0.f, kZeroExp}, n2{0.f, kZeroExp};
+    // every slot's scan values first (unconditional: each slot's dividing
+    // index is within the scans), so that no row waits on its own LDS reads
+    float sl[IPT], su[IPT];
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const int z = s_z[tid + q * BLOCK];
+        sl[q] = s_l[z];
+        su[q] = s_u[z];
+    }
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int k = tid + q * BLOCK - r_first;
         if (k >= 0 && k < nrow) {
-            const int z = s_z[tid + q * BLOCK];
             const Ext<float> Aq = s_a[tid + q * BLOCK];
-            const float pm = cl_rel + ldexp_m(s_l[z], shl);
-            const float qm = ldexp_m(s_u[z], shu) + cu_rel;
+            const float pm = cl_rel + ldexp_m(sl[q], shl);
+            const float qm = ldexp_m(su[q], shu) + cu_rel;
             const Ext<float> W = ext_add(Ext<float>{pm, rl}, Ext<float>{qm * B[q].m, ru + B[q].e});
             const Ext<float> Un = ext_norm(Ext<float>{Aq.m * __builtin_amdgcn_rcpf(W.m), Aq.e - W.e});
             if (CHECK) {
@@ -275,8 +351,7 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
             ref_add(n2, Un);
         }
     }
-    if (CHECK) wave_sum_to<BLOCK>(red, s_d);
-    block_total2_write<BLOCK>(n1, n2, s_f + 4 * NW, s_i + 4 * NW);
+    block_totals_write<BLOCK, CHECK>(n1, n2, red, s_f + 4 * NW, s_i + 4 * NW, s_d);
     __syncthreads();
 }
 
@@ -370,10 +445,12 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         const int rxl = own_l.e, rxu = own_u.e;
         // records of this iteration's sweeps: write l + 1 of their buffers
         const unsigned tag = (unsigned)((l + 1) & 1);
+        __builtin_amdgcn_s_setprio(2);
         ok = resident_wait(a, gen, &s_flag);
         if (!ok) break;
         resident_read<false>(a, rec_x, nullptr, tag, &s_flag, in);
-        block_total2_write<BLOCK>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, s_f + 2 * NW, s_i + 2 * NW);
+        block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.0, s_f + 2 * NW,
+                                         s_i + 2 * NW, s_d);
         __syncthreads();
         resident_rows<BLOCK, IPT, true>(block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW),
                                         block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW), nr, 0, nc, rxl, rxu, U,
@@ -386,16 +463,18 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
             resident_signal(a, 3, rec_y + 2 * tile, rec_of(own_l, tag), rec_y + 2 * tile + 1, rec_of(own_u, tag),
                             rec_p + tile, rec_of(pe, tag));
         }
+        __builtin_amdgcn_s_setprio(0);
         // ---- K psi: its columns (y) while the others finish, then the loop
         // head (every block sums the partials in the same order)
         __syncthreads();   // s_d and the LDS scans of the checking sweep are read
         resident_columns<BLOCK, IPT>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
         const int ryl = own_l.e, ryu = own_u.e;
+        __builtin_amdgcn_s_setprio(2);
         ok = resident_wait(a, gen, &s_flag);
         if (!ok) break;
         resident_read<true>(a, rec_y, rec_p, tag, &s_flag, in);
-        block_total2_write<BLOCK>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, s_f + 2 * NW, s_i + 2 * NW);
-        wave_sum_to<BLOCK>(in.part, s_d);
+        block_totals_write<BLOCK, true>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, in.part, s_f + 2 * NW,
+                                        s_i + 2 * NW, s_d);
         __syncthreads();
         err = block_read_sum<BLOCK>(s_d);
         if (l >= itr_max || !(err > tol)) {
@@ -417,6 +496,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         if (threadIdx.x < kWave)
             resident_signal(a, 2, rec_x + 2 * tile, rec_of(own_l, tag ^ 1u), rec_x + 2 * tile + 1,
                             rec_of(own_u, tag ^ 1u), nullptr, 0);
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();   // the LDS scans of K psi are read
         ++l;
     }
