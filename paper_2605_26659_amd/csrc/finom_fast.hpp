@@ -378,9 +378,15 @@ __device__ __forceinline__ void fast_tile_scan(float* s_l, float* s_u, int nc, f
     if (lane == kWave - 1) s_f[wid] = il;
     if (lane == 0) s_f[NW + wid] = iu;
     __syncthreads();
+    // the other waves' totals, read at once (adding the zeros of the other
+    // side leaves the sums exact)
     float pre = 0.f, suf = 0.f;
-    for (int v = 0; v < wid; ++v) pre += s_f[v];
-    for (int v = wid + 1; v < NW; ++v) suf += s_f[NW + v];
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+        const float f = s_f[v], g = s_f[NW + v];
+        pre += v < wid ? f : 0.f;
+        suf += v > wid ? g : 0.f;
+    }
     float run = pre + dpp_f<0x138>(il);    // wave_shr:1 -> exclusive prefix
     float runu = dpp_f<0x130>(iu) + suf;   // wave_shl:1 -> exclusive suffix
 #pragma unroll
@@ -394,7 +400,8 @@ __device__ __forceinline__ void fast_tile_scan(float* s_l, float* s_u, int nc, f
         runu += vu[q];
         vu[q] = runu;
     }
-    __syncthreads();   // every chunk is read before any is overwritten
+    // every chunk was read before the barrier above, so the chunks can be
+    // overwritten in place
 #pragma unroll
     for (int q = 0; q < IPT; q += 4) {
         *reinterpret_cast<float4*>(s_l + base + q) = make_float4(vl[q], vl[q + 1], vl[q + 2], vl[q + 3]);
