@@ -276,6 +276,42 @@ __device__ __forceinline__ void block_totals_write(RefAcc a, RefAcc b, double d,
     }
 }
 
+// The block's totals from the per-wave parts that block_totals_write left in
+// LDS: lane w of every wave reads wave w's parts, and the waves' parts are
+// combined across lanes (largest exponent, then the sum in a fixed order), so
+// every thread gets the same results.
+template <int BLOCK, bool D>
+__device__ __forceinline__ void block_totals_read(const float* s_f, const int* s_i, const double* s_d, Ext<float>& ta,
+                                                  Ext<float>& tb, double& td)
+{
+    constexpr int NW = BLOCK / kWave;
+    static_assert(NW == 8, "three DPP steps combine eight waves");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = lane & (NW - 1);
+    const bool mine = lane < NW;
+    const float fa = s_f[w], fb = s_f[NW + w];
+    const int ea = mine ? s_i[w] : kZeroExp, eb = mine ? s_i[NW + w] : kZeroExp;
+    double d = D && mine ? s_d[w] : 0.0;
+    int ra = ea, rb = eb;
+    tot_step1<0x111, 0xF, D>(ra, rb, d);   // row_shr:1
+    tot_step1<0x112, 0xF, D>(ra, rb, d);   // row_shr:2
+    tot_step1<0x114, 0xF, D>(ra, rb, d);   // row_shr:4
+    ra = __builtin_amdgcn_readlane(ra, NW - 1);
+    rb = __builtin_amdgcn_readlane(rb, NW - 1);
+    float sa = mine ? ldexp_m(fa, ea - ra) : 0.f, sb = mine ? ldexp_m(fb, eb - rb) : 0.f;
+    tot_step2<0x111, 0xF>(sa, sb);
+    tot_step2<0x112, 0xF>(sa, sb);
+    tot_step2<0x114, 0xF>(sa, sb);
+    ta = ext_norm(Ext<float>{readlane_f(sa, NW - 1), ra});
+    tb = ext_norm(Ext<float>{readlane_f(sb, NW - 1), rb});
+    if (D) {
+        const long long db = __double_as_longlong(d);
+        const int lo = __builtin_amdgcn_readlane((int)(db & 0xffffffffLL), NW - 1);
+        const int hi = __builtin_amdgcn_readlane((int)(db >> 32), NW - 1);
+        td = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    }
+}
+
 // The local half of a sweep: the column terms (slots [c_first, c_first +
 // ncol), column index k - c_first) against the tile's own totals, to LDS, and
 // their in-tile scan. Needs nothing from other blocks.
@@ -452,14 +488,13 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.0, s_f + 2 * NW,
                                          s_i + 2 * NW, s_d);
         __syncthreads();
-        resident_rows<BLOCK, IPT, true>(block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW),
-                                        block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW), nr, 0, nc, rxl, rxu, U,
-                                        s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
-        own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
-        own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
+        Ext<float> CL, CU;
+        double pe;
+        block_totals_read<BLOCK, false>(s_f + 2 * NW, s_i + 2 * NW, s_d, CL, CU, pe);
+        resident_rows<BLOCK, IPT, true>(CL, CU, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
+        block_totals_read<BLOCK, true>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
         ++gen;
         if (threadIdx.x < kWave) {
-            const double pe = block_read_sum<BLOCK>(s_d);
             resident_signal(a, 3, rec_y + 2 * tile, rec_of(own_l, tag), rec_y + 2 * tile + 1, rec_of(own_u, tag),
                             rec_p + tile, rec_of(pe, tag));
         }
@@ -476,7 +511,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         block_totals_write<BLOCK, true>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, in.part, s_f + 2 * NW,
                                         s_i + 2 * NW, s_d);
         __syncthreads();
-        err = block_read_sum<BLOCK>(s_d);
+        block_totals_read<BLOCK, true>(s_f + 2 * NW, s_i + 2 * NW, s_d, CL, CU, err);
         if (l >= itr_max || !(err > tol)) {
             // the returned psi: the states the loop head checked
 #pragma unroll
@@ -487,11 +522,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
             break;
         }
         // ---- K psi: rows x
-        resident_rows<BLOCK, IPT, false>(block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW),
-                                         block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW), nc, nc, nr, ryl, ryu, U,
-                                         s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i, s_d);
-        own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
-        own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
+        resident_rows<BLOCK, IPT, false>(CL, CU, nc, nc, nr, ryl, ryu, U, s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i,
+                                         s_d);
+        block_totals_read<BLOCK, false>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
         ++gen;
         if (threadIdx.x < kWave)
             resident_signal(a, 2, rec_x + 2 * tile, rec_of(own_l, tag ^ 1u), rec_x + 2 * tile + 1,
