@@ -923,19 +923,13 @@ static int run_resident(Alloc& al, const Part& pk, const Part& pkt, Ext<float>* 
     a.m = pk.C;
     a.ntiles = pk.ntiles;
     a.rec = al.dev<unsigned long long>(5 * (size_t)pk.ntiles);
-    a.group = std::max(kResidentGroup, (pk.ntiles + kWave - 1) / kWave);   // one polling lane per group
-    a.copies = kResidentCopies;
-    const int groups = (pk.ntiles + a.group - 1) / a.group;
-    // arrival counters [copy][group], then the fail flag; records and
-    // counters start at zero (tag 0, no arrivals)
-    const size_t ncnt = (size_t)kResidentLine * ((size_t)a.copies * groups + 1);
-    a.counter = (unsigned*)al.dev<int>(ncnt);
-    a.fail = (int*)a.counter + (size_t)kResidentLine * a.copies * groups;
+    a.fail = al.dev<int>(1);
+    // records start at zero (tag 0: written 0 times)
     HIPCHK(hipMemsetAsync(a.rec, 0, 5 * (size_t)pk.ntiles * sizeof(unsigned long long), s));
+    HIPCHK(hipMemsetAsync(a.fail, 0, sizeof(int), s));
     a.ps = ps;
     a.spin_limit = kResidentSpin;
     if (const char* e = getenv("FINOM_RESIDENT_SPIN")) a.spin_limit = (unsigned)strtoul(e, nullptr, 10);
-    HIPCHK(hipMemsetAsync(a.counter, 0, ncnt * sizeof(int), s));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int st = FINOM_OK;
     try {

@@ -8,10 +8,10 @@
 // and its dividing index. One cooperative launch then runs Algorithm 1's
 // loop; per sweep the only data that leaves the block are the tile's totals
 // of the next sweep's column terms (two extended numbers) and, for the
-// checking sweep, its partial marginal error. Blocks exchange them through a
-// grid barrier (an agent-scope counter). Every block reads all totals and
-// partials in the same order, so all blocks compute the same carries and take
-// the same stop decision, and every block runs the same number of barriers.
+// checking sweep, its partial marginal error. Blocks exchange them as tagged
+// records (below). Every block reads the partials of all tiles and sums them
+// in the same order, so all blocks take the same stop decision and run the
+// same number of sweeps.
 //
 // A block's slots k = t + q BLOCK (thread t, q < IPT) cover the tile's
 // elements as [its nc y points, its nr x points]. In the checking sweep
@@ -37,47 +37,33 @@ struct ResidentArgs {
     int ntiles;               // at most the block size
     int pad;
     unsigned long long* rec;  // tagged records: [ntiles][2] x totals, [ntiles][2] y totals, [ntiles] partial errors; zero at launch
-    unsigned* counter;        // arrival counters [copy][group], 256 bytes apart; zero at launch
     int* fail;                // set when a wait exceeds its bound
     unsigned spin_limit;      // polls before a wait gives up
-    int group;                // blocks per arrival group (ntiles / group <= 64)
-    int copies;               // copies of the arrival counters (<= 64)
+    int pad2;
     ProbState* ps;
 };
 
 // ---- exchange between blocks
 // After each sweep a block publishes its tile's totals (and, for the checking
-// sweep, its partial error) into one of three record buffers and counts
-// itself in at a grid barrier; after the barrier every block reads the
-// records of the buffer. Records are written with agent-scope atomic stores
-// and read with agent-scope atomic loads, both of which complete at the
-// device's coherence point, so no cache maintenance is needed (a release /
-// acquire pair would write back and invalidate the L2 of every XCD once per
-// block). Neither the records nor the arrival wait for completion: each
-// record carries a one-bit tag, and a reader that finds the previous write
-// of a record reads it again.
+// sweep, its partial error) into one of three record buffers; in the next
+// sweep every block reads the records it needs from that buffer, each thread
+// one record, until they carry the expected tag. The records are the whole
+// synchronisation: there is no barrier counter. They are written with
+// agent-scope atomic stores and read with agent-scope atomic loads, both of
+// which complete at the device's coherence point, so no cache maintenance is
+// needed (a release / acquire pair would write back and invalidate the L2 of
+// every XCD once per block), and the writer does not wait for its stores.
 //
 // Tags. The k-th write of a record carries tag k & 1. A reader waiting for
-// write k can only find write k - 1 or write k there: write k + 1 comes after
-// its writer has passed a barrier that this reader's own arrival, made after
-// this read, completes. A zeroed buffer holds tag 0, as if written 0 times.
-// The tag is the sign bit of the word: a total (an Ext<float> whose mantissa
-// is 0 or in [1/2, 1)) keeps its mantissa's bits in the high half and its
-// exponent in the low half; a partial error is a non-negative double. Both
-// are restored exactly.
-//
-// Arrival. Blocks form groups of a.group; a group has one arrival counter in
-// each of a.copies copies, and an arriving block adds 1 to its group's
-// counter in every copy (one lane per copy, no return value). A block waits
-// by polling the counters of all groups in one copy (blockIdx % a.copies),
-// one lane per group: the copies spread the
-// polls, the groups spread the additions. Barrier gen is complete when every
-// group's counter holds gen times the group's size; a counter cannot count a
-// later barrier's arrival before every block has arrived at this one.
+// write k can only find write k - 1 or write k there: its writer makes write
+// k + 1 only after reading this reader's record in the other buffer, which
+// this reader writes after this read; and having once read write k - 1, the
+// reader cannot see an older write. A zeroed buffer holds tag 0, as if
+// written 0 times. The tag is the sign bit of the word: a total (an
+// Ext<float> whose mantissa is 0 or in [1/2, 1)) keeps its mantissa's bits in
+// the high half and its exponent in the low half; a partial error is a
+// non-negative double. Both are restored exactly.
 constexpr unsigned kResidentSpin = 1u << 22;   // default bound of a wait, in polls (~seconds)
-constexpr int kResidentGroup = 16;             // blocks per group (at least ntiles / 64)
-constexpr int kResidentCopies = 8;             // copies of the arrival counters
-constexpr int kResidentLine = 64;              // counters 256 bytes apart
 
 __device__ __forceinline__ unsigned long long rec_of(Ext<float> v, unsigned tag)
 {
@@ -111,15 +97,20 @@ __device__ __forceinline__ void resident_fail(const ResidentArgs& a, int* s_flag
     *s_flag = 0;
 }
 
-// Reads a record until it carries the expected tag (bounded: on failure the
-// block's flag is cleared, and its next wait ends it).
+// Reads a record until it carries the expected tag. The wait is bounded: it
+// fails after a.spin_limit polls, or when another block's failure shows in
+// the fail flag (checked every 64 polls); a failure clears the block's flag,
+// so the block leaves its loop and publishes no more, and every block waiting
+// for it fails in turn.
 __device__ __forceinline__ unsigned long long rec_read(const ResidentArgs& a, const unsigned long long* p,
                                                        unsigned tag, int* s_flag)
 {
     unsigned long long w = rec_load(p);
     unsigned polls = 0;
     while ((unsigned)(w >> 63) != tag) {
-        if (++polls > a.spin_limit) {
+        ++polls;
+        if (polls > a.spin_limit ||
+            ((polls & 63) == 0 && __hip_atomic_load(a.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
             resident_fail(a, s_flag);
             break;
         }
@@ -130,11 +121,10 @@ __device__ __forceinline__ unsigned long long rec_read(const ResidentArgs& a, co
 }
 
 // Wave 0 of a block, with wave-uniform arguments: writes the block's records
-// (lane i writes word i, n words) and counts the block in at its group's
-// counter in every copy. Nothing waits for these writes.
-__device__ __forceinline__ void resident_signal(const ResidentArgs& a, int n, unsigned long long* p0,
-                                                unsigned long long w0, unsigned long long* p1, unsigned long long w1,
-                                                unsigned long long* p2, unsigned long long w2)
+// (lane i writes word i, n words). Nothing waits for these writes.
+__device__ __forceinline__ void resident_publish(int n, unsigned long long* p0, unsigned long long w0,
+                                                 unsigned long long* p1, unsigned long long w1,
+                                                 unsigned long long* p2, unsigned long long w2)
 {
     const int lane = threadIdx.x;
     if (lane < n) {
@@ -142,44 +132,6 @@ __device__ __forceinline__ void resident_signal(const ResidentArgs& a, int n, un
         const unsigned long long w = lane == 0 ? w0 : lane == 1 ? w1 : w2;
         __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (lane < a.copies) {
-        const unsigned gs = (unsigned)a.group;
-        const unsigned G = (gridDim.x + gs - 1) / gs;
-        __hip_atomic_fetch_add(a.counter + kResidentLine * (lane * G + blockIdx.x / gs), 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// The wait for barrier gen (the arrival is resident_signal; a block's own
-// work runs between the two). Every block arrives and waits the same number
-// of times. Returns false when a wait of this block failed (its bound, or
-// another block's failure seen through the fail flag, checked every 64
-// polls); a block that has failed arrives no more, so every other block's
-// wait then fails too.
-__device__ __forceinline__ bool resident_wait(const ResidentArgs& a, unsigned gen, int* s_flag)
-{
-    if (threadIdx.x < kWave) {
-        const unsigned nb = gridDim.x, gs = (unsigned)a.group;
-        const unsigned G = (nb + gs - 1) / gs;
-        const unsigned h = min((unsigned)threadIdx.x, G - 1);
-        const unsigned need = gen * min(gs, nb - h * gs);
-        const unsigned* c = a.counter + kResidentLine * ((blockIdx.x % (unsigned)a.copies) * G + h);
-        int ok = __builtin_amdgcn_readfirstlane(*s_flag);
-        unsigned polls = 0;
-        while (ok) {
-            const unsigned v = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__builtin_amdgcn_ballot_w64((int)(v - need) < 0) == 0) break;
-            ++polls;
-            if (polls > a.spin_limit ||
-                ((polls & 63) == 0 && __hip_atomic_load(a.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-                ok = 0;
-            ok = __builtin_amdgcn_readfirstlane(ok);
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (!ok && threadIdx.x == 0) resident_fail(a, s_flag);
-    }
-    __syncthreads();
-    return *s_flag != 0;
 }
 
 // A block's share of the carries from one buffer of records: thread t holds
@@ -441,11 +393,13 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
     }
 
     // The loop. Each sweep: its columns and their scan (local, done while the
-    // other blocks finish the previous sweep), the wait for the previous
-    // sweep's records, the carries, the rows, publication and arrival.
-    __shared__ int s_flag;
+    // other blocks finish the previous sweep), the previous sweep's records
+    // and the carries, the rows, publication. Two blocks share a CU, and the
+    // SIMDs favour the older block's waves: a block raises its waves' issue
+    // priority from its records to its publication, so that a block on the
+    // critical path is not held back by its neighbour's column work.
+    __shared__ int s_flag;   // 0 once a wait of this block has failed
     if (threadIdx.x == 0) s_flag = 1;
-    unsigned gen = 0;
     // the first sweep's column totals (x points) from the initial state
     Ext<float> own_l, own_u;
     {
@@ -462,10 +416,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         __syncthreads();
         own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
         own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
-        ++gen;
         if (threadIdx.x < kWave)
-            resident_signal(a, 2, rec_x + 2 * tile, rec_of(own_l, 1u), rec_x + 2 * tile + 1, rec_of(own_u, 1u),
-                            nullptr, 0);
+            resident_publish(2, rec_x + 2 * tile, rec_of(own_l, 1u), rec_x + 2 * tile + 1, rec_of(own_u, 1u),
+                             nullptr, 0);
     }
 
     const long long itr_max = a.ps->itr_max;
@@ -482,21 +435,20 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         // records of this iteration's sweeps: write l + 1 of their buffers
         const unsigned tag = (unsigned)((l + 1) & 1);
         __builtin_amdgcn_s_setprio(2);
-        ok = resident_wait(a, gen, &s_flag);
-        if (!ok) break;
         resident_read<false>(a, rec_x, nullptr, tag, &s_flag, in);
         block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.0, s_f + 2 * NW,
                                          s_i + 2 * NW, s_d);
         __syncthreads();
+        ok = s_flag != 0;
+        if (!ok) break;
         Ext<float> CL, CU;
         double pe;
         block_totals_read<BLOCK, false>(s_f + 2 * NW, s_i + 2 * NW, s_d, CL, CU, pe);
         resident_rows<BLOCK, IPT, true>(CL, CU, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
         block_totals_read<BLOCK, true>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
-        ++gen;
         if (threadIdx.x < kWave) {
-            resident_signal(a, 3, rec_y + 2 * tile, rec_of(own_l, tag), rec_y + 2 * tile + 1, rec_of(own_u, tag),
-                            rec_p + tile, rec_of(pe, tag));
+            resident_publish(3, rec_y + 2 * tile, rec_of(own_l, tag), rec_y + 2 * tile + 1, rec_of(own_u, tag),
+                             rec_p + tile, rec_of(pe, tag));
         }
         __builtin_amdgcn_s_setprio(0);
         // ---- K psi: its columns (y) while the others finish, then the loop
@@ -505,12 +457,12 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         resident_columns<BLOCK, IPT>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
         const int ryl = own_l.e, ryu = own_u.e;
         __builtin_amdgcn_s_setprio(2);
-        ok = resident_wait(a, gen, &s_flag);
-        if (!ok) break;
         resident_read<true>(a, rec_y, rec_p, tag, &s_flag, in);
         block_totals_write<BLOCK, true>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, in.part, s_f + 2 * NW,
                                         s_i + 2 * NW, s_d);
         __syncthreads();
+        ok = s_flag != 0;
+        if (!ok) break;
         block_totals_read<BLOCK, true>(s_f + 2 * NW, s_i + 2 * NW, s_d, CL, CU, err);
         if (l >= itr_max || !(err > tol)) {
             // the returned psi: the states the loop head checked
@@ -525,10 +477,9 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         resident_rows<BLOCK, IPT, false>(CL, CU, nc, nc, nr, ryl, ryu, U, s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i,
                                          s_d);
         block_totals_read<BLOCK, false>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
-        ++gen;
         if (threadIdx.x < kWave)
-            resident_signal(a, 2, rec_x + 2 * tile, rec_of(own_l, tag ^ 1u), rec_x + 2 * tile + 1,
-                            rec_of(own_u, tag ^ 1u), nullptr, 0);
+            resident_publish(2, rec_x + 2 * tile, rec_of(own_l, tag ^ 1u), rec_x + 2 * tile + 1,
+                             rec_of(own_u, tag ^ 1u), nullptr, 0);
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();   // the LDS scans of K psi are read
         ++l;
