@@ -312,17 +312,19 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
     // every slot's scan values first (unconditional: each slot's dividing
     // index is within the scans), so that no row waits on its own LDS reads
     float sl[IPT], su[IPT];
+    Ext<float> A[IPT];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int z = s_z[tid + q * BLOCK];
         sl[q] = s_l[z];
         su[q] = s_u[z];
+        A[q] = s_a[tid + q * BLOCK];
     }
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int k = tid + q * BLOCK - r_first;
         if (k >= 0 && k < nrow) {
-            const Ext<float> Aq = s_a[tid + q * BLOCK];
+            const Ext<float> Aq = A[q];
             const float pm = cl_rel + ldexp_m(sl[q], shl);
             const float qm = ldexp_m(su[q], shu) + cu_rel;
             const Ext<float> W = ext_add(Ext<float>{pm, rl}, Ext<float>{qm * B[q].m, ru + B[q].e});
@@ -452,8 +454,10 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         }
         __builtin_amdgcn_s_setprio(0);
         // ---- K psi: its columns (y) while the others finish, then the loop
-        // head (every block sums the partials in the same order)
-        __syncthreads();   // s_d and the LDS scans of the checking sweep are read
+        // head (every block sums the partials in the same order). No barrier
+        // is needed before the columns: the scans were last read before the
+        // rows' barrier, and the LDS read since then is written again only
+        // after the column phase's barriers.
         resident_columns<BLOCK, IPT>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
         const int ryl = own_l.e, ryu = own_u.e;
         __builtin_amdgcn_s_setprio(2);
@@ -481,7 +485,6 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
             resident_publish(2, rec_x + 2 * tile, rec_of(own_l, tag ^ 1u), rec_x + 2 * tile + 1,
                              rec_of(own_u, tag ^ 1u), nullptr, 0);
         __builtin_amdgcn_s_setprio(0);
-        __syncthreads();   // the LDS scans of K psi are read
         ++l;
     }
     // the returned pair: the current phi (and the psi the loop head checked,
