@@ -52,8 +52,8 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # recorded beside them; after any change to those sources the traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
-TRAFFIC_RESIDENT = {"sources_sha256": "26c9dd2b0c06a34023d7a8c1da57de23137a07579a00e90f99e4eefbc950fab5",
-                    "fetch_kib": 454997.0, "write_kib": 1013930.0, "n": 1 << 20}
+TRAFFIC_RESIDENT = {"sources_sha256": "97aab2370c68f72a46c0512cc79f078838ff46622f1500597b8978221fe36bc8",
+                    "fetch_kib": 421493.0, "write_kib": 213368.0, "n": 1 << 20}
 TRAFFIC_STREAM = {"sources_sha256": "cdedeb22e36a32830477ce4c70afdf9dc1a95834a628ae1f32b2934952ca0711",
                   "fetch_kib": (22823.5 + 18713.6) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
