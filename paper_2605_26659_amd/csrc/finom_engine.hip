@@ -16,6 +16,7 @@
 #include <tuple>
 
 #include "finom_engine.hpp"
+#include "finom_resident.hpp"
 
 namespace finom {
 
@@ -374,8 +375,9 @@ Engine::Engine(int precision, hipStream_t stream, int capacity, bool use_graphs)
         throw std::bad_alloc();
     }
     memset(hps_, 0, sizeof(ProbState) * (cap_ + 1));
-    // the cost sweeps' state (never done)
-    HIPCHK(hipMemsetAsync(ps_ + cap_, 0, sizeof(ProbState), s_));
+    // every state not done (a job's state is set when it starts), and the
+    // cost sweeps' state (never done)
+    HIPCHK(hipMemsetAsync(ps_, 0, sizeof(ProbState) * (cap_ + 1), s_));
     for (int i = 0; i < cap_; ++i) free_slots_.push(i);
     HIPCHK(hipStreamCreateWithFlags(&cs_, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&ev0_));
@@ -389,6 +391,7 @@ Engine::~Engine()
     arena_free(&ar_setup_);
     arena_free(&ar_loop_);
     arena_free(&ar_cost_);
+    arena_free(&ar_res_);
     if (ev0_) hipEventDestroy(ev0_);
     if (ev1_) hipEventDestroy(ev1_);
     if (cs_) hipStreamDestroy(cs_);
@@ -577,6 +580,108 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
         else if (!(fabs(su - sv) <= 1e-12 * std::max(fabs(su), fabs(sv)))) st = FINOM_E_MASS;
         else if (f & 4) st = FINOM_E_ARG;
         jobs[i]->status = st;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// resident batch
+// ---------------------------------------------------------------------------
+int resident_batch_capacity()
+{
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resident_batch<kResidentBlock, kResidentIpt, kResidentWaves>, kResidentBlock,
+                                                     0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+void Engine::solve_resident()
+{
+    if (precision_ != 1 || !fast_allowed() || !resident_allowed()) return;
+    std::vector<Job*> rj;
+    for (Job* j : pending_init_)
+        if (j->d.dim == 1 && j->fast && resident_fits(j->p.na, j->p.nb, j->pk[0].T)) rj.push_back(j);
+    if (rj.empty()) return;
+    // larger problems first: the tiles are handed out in this order
+    std::stable_sort(rj.begin(), rj.end(), [](const Job* a, const Job* b) { return a->pk[0].ntiles > b->pk[0].ntiles; });
+    std::vector<Job*> rest;
+    for (Job* j : pending_init_)
+        if (std::find(rj.begin(), rj.end(), j) == rj.end()) rest.push_back(j);
+    pending_init_.swap(rest);
+
+    Alloc al(&ar_res_, s_);
+    std::vector<StateInit> ini;
+    std::vector<int> first(1, 0);
+    for (Job* j : rj) {
+        ini.push_back(StateInit{j->slot, 0, j->d.itr_max, j->d.tol});
+        first.push_back(first.back() + j->pk[0].ntiles);
+    }
+    const int total = first.back();
+    unsigned long long* rec = al.dev<unsigned long long>(5 * (size_t)total);
+    int* flags = al.dev<int>(2);   // fail, tile counter
+    unsigned spin = kResidentSpin;
+    if (const char* e = getenv("FINOM_RESIDENT_SPIN")) spin = (unsigned)strtoul(e, nullptr, 10);
+    std::vector<ResidentArgs> args(rj.size());
+    for (size_t i = 0; i < rj.size(); ++i) {
+        const Job* j = rj[i];
+        ResidentArgs& a = args[i];
+        memset(&a, 0, sizeof(a));
+        a.UF = (Ext<float>*)j->F;
+        a.UG = (Ext<float>*)j->G[0];
+        a.Ax = (const Ext<float>*)j->lu;
+        a.Ay = (const Ext<float>*)j->lv;
+        a.Bx = j->Bx;
+        a.By = j->By;
+        a.zx = j->pk[0].zeta;
+        a.zy = j->pkt[0].zeta;
+        a.trs = j->pk[0].trs;
+        a.n = j->p.na;
+        a.m = j->p.nb;
+        a.ntiles = j->pk[0].ntiles;
+        a.T = j->pk[0].T;
+        a.rec = rec + 5 * (size_t)first[i];
+        a.fail = flags;
+        a.spin_limit = spin;
+        a.ps = ps_ + j->slot;
+    }
+    const StateInit* d_ini = upload_vec(al, ini);
+    const ResidentArgs* d_args = upload_vec(al, args);
+    const int* d_first = upload_vec(al, first);
+    al.uploaded();
+    hipLaunchKernelGGL(k_init_states, dim3(blocks_for((long long)ini.size())), dim3(kBlock), 0, s_, d_ini,
+                       (int)ini.size(), ps_);
+    HIPCHK(hipGetLastError());
+    // records start at zero (tag 0: written 0 times)
+    HIPCHK(hipMemsetAsync(rec, 0, 5 * (size_t)total * sizeof(unsigned long long), s_));
+    HIPCHK(hipMemsetAsync(flags, 0, 2 * sizeof(int), s_));
+    ResidentBatch b;
+    b.probs = d_args;
+    b.first = d_first;
+    b.nprob = (int)rj.size();
+    b.total = total;
+    b.next = flags + 1;
+    const int grid = std::min(total, resident_capacity());
+    void* kargs[] = {&b};
+    HIPCHK(hipEventRecord(ev0_, s_));
+    HIPCHK(hipLaunchCooperativeKernel((const void*)k_resident_batch<kResidentBlock, kResidentIpt, kResidentWaves>, dim3(grid),
+                                      dim3(kResidentBlock), kargs, 0, s_));
+    HIPCHK(hipEventRecord(ev1_, s_));
+    int* hfail = al.host<int>(1);
+    HIPCHK(hipMemcpyAsync(hfail, flags, sizeof(int), hipMemcpyDeviceToHost, s_));
+    read_states();
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+    loop_ms_total_ += ms;
+    for (Job* j : rj) {
+        j->resident = true;
+        j->loop_ms = ms;
+    }
+    if (*hfail) {
+        set_last_error("resident solver: a grid wait exceeded its bound");
+        throw StatusError{FINOM_E_HIP};
     }
 }
 
@@ -881,14 +986,15 @@ std::vector<Job*> Engine::harvest()
         t.mode = 2;
         t.b = kappa;
         t.out = j->F; t.mesh = j->d.x1; t.n = j->p.na; ft.push_back(t);
-        t.out = j->G[hps_[j->slot].iters & 1]; t.mesh = j->d.x2; t.n = j->p.nb; ft.push_back(t);
+        t.out = j->resident ? j->G[0] : j->G[hps_[j->slot].iters & 1]; t.mesh = j->d.x2; t.n = j->p.nb;
+        ft.push_back(t);
     }
     enqueue_fast_state(al, ft, s_);
     int P = 0;
     for (Job* j : fin) {
         const JobDesc& d = j->d;
         const ProbState& st = hps_[j->slot];
-        double* Gf = j->G[st.iters & 1];
+        double* Gf = j->resident ? j->G[0] : j->G[st.iters & 1];
         const double eps = d.eps;
         const int base = P;
         if (d.dim == 1) {
@@ -955,7 +1061,7 @@ std::vector<Job*> Engine::harvest()
         r.sweeps = j->d.dim == 1 ? 2 * st.iters + 1 : 4 * st.iters + 2;
         r.loop_ms = j->loop_ms;
         r.status = st.status ? FINOM_E_NUMERIC : (st.converged ? FINOM_OK : FINOM_NOT_CONVERGED);
-        r.fast = j->fast ? 1 : 0;
+        r.fast = j->fast ? (j->resident ? 2 : 1) : 0;
         free_slots_.push(j->slot);
         j->slot = -1;
     }
@@ -1083,8 +1189,11 @@ int finom_batch(const finom_problem* probs, int64_t count, const finom_opts* opt
         }
         const int k = o.graph_iters > 0 ? o.graph_iters : 16;
         bool any_nc = false;
+        eng.solve_resident();
+        bool first = true;
         while (eng.live() > 0) {
-            eng.round(k);
+            if (!first) eng.round(k);
+            first = false;
             for (Job* j : eng.harvest()) {
                 res[j->tag] = j->res;
                 if (j->res.status < 0 && first_err == FINOM_OK) first_err = j->res.status;

@@ -59,6 +59,7 @@ struct Job {
     Ext<float>* Bx = nullptr;   // 1D FP32: 2^{2 x kappa} and 2^{2 y kappa} for the fast sweeps
     Ext<float>* By = nullptr;
     bool fast = false;          // runs on the fast sweeps
+    bool resident = false;      // solved by the resident batch kernel (final psi in G[0])
     Part pk[2], pkt[2], pc[2];   // per axis: K, K^T, cost partition of K
     void bind();
     double points() const { return 0.5 * (double)(p.na + p.nb); }
@@ -77,6 +78,10 @@ public:
     // Joins a prepared job to the iteration (between rounds). False when no
     // state slot is free.
     bool add(Job* j);
+    // Solves the 1D FP32 jobs that joined since the last round and fit the
+    // resident solver, to the end of their loops, in one persistent launch;
+    // they are then ready for harvest. The other jobs are left to round().
+    void solve_resident();
     // k iterations (k even) of every live job; then reads their states.
     void round(int k);
     // Jobs that stopped in the last round: costs, outputs, results. They
@@ -106,7 +111,7 @@ private:
     std::vector<Job*> active_;      // live jobs, in join order
     std::vector<Job*> pending_init_;   // joined since the last rebuild
     std::vector<Job*> listed_;      // jobs in the current launch lists
-    Arena ar_setup_, ar_loop_, ar_cost_;
+    Arena ar_setup_, ar_loop_, ar_cost_, ar_res_;
     std::vector<std::unique_ptr<Sweep>> sweeps_;
     std::vector<Sweep*> seq_[2];
     std::vector<bool> dec_[2];

@@ -37,6 +37,14 @@ struct HipError {
     hipError_t e;
 };
 
+// A failure with its own status and message (the message is already in the
+// library's last-error text, set with set_last_error).
+struct StatusError {
+    int status;
+};
+
+void set_last_error(const char* msg);
+
 #define HIPCHK(x)                                  \
     do {                                           \
         hipError_t _e = (x);                       \
@@ -274,6 +282,17 @@ int map_exception();
 
 // Fast sweeps are used for eligible FP32 lines unless FINOM_FAST=0.
 bool fast_allowed();
+// The resident solver is used for eligible 1D FP32 problems unless
+// FINOM_RESIDENT=0.
+bool resident_allowed();
+// Blocks of the resident kernels (single problem and batch) that can be
+// resident at once on the current device; 0 when it cannot launch them
+// cooperatively. resident_batch_capacity is the batch kernel's alone.
+int resident_capacity();
+int resident_batch_capacity();
+// Whether a 1D problem of n + m points on tiles of T runs on the resident
+// solver, alone or in a batch, once its tiles pass the fast sweeps' bound.
+bool resident_fits(long long n, long long m, int T);
 // Classifies the 1D pair (x: n, y: m) on partition pk (rows x) and its
 // transpose pkt for the fast sweeps; fills 2^{c kappa} for both meshes when
 // eligible. Synchronises the stream. Returns true when the pair is eligible.

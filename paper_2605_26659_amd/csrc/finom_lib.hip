@@ -192,6 +192,8 @@ void arena_release_all()
 
 static thread_local char g_last_error[256] = "";
 
+void set_last_error(const char* msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
 int map_exception()
 {
     try {
@@ -199,6 +201,8 @@ int map_exception()
     } catch (const std::bad_alloc&) {
         snprintf(g_last_error, sizeof(g_last_error), "allocation failed");
         return FINOM_E_NOMEM;
+    } catch (const StatusError& e) {
+        return e.status;
     } catch (const HipError& e) {
         snprintf(g_last_error, sizeof(g_last_error), "%s (%d)", hipGetErrorString(e.e), (int)e.e);
         if (e.e == hipErrorOutOfMemory) return FINOM_E_NOMEM;
@@ -772,6 +776,44 @@ static void set_decision(Sweep& sw, int off, int n)
     }
 }
 
+// ---- resident solver: eligibility
+
+bool resident_allowed()
+{
+    const char* e = getenv("FINOM_RESIDENT");
+    return !(e && e[0] == '0');
+}
+
+// The smaller of the two kernels' capacities, so that a problem is resident
+// alone exactly when it is resident in a batch. Computed once per process on
+// the device current at the first call.
+int resident_capacity()
+{
+    static int cap = -1;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cap < 0) {
+        int dev = 0, coop = 0, cus = 0, per_cu = 0;
+        cap = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves>,
+                                                         kResidentBlock, 0) == hipSuccess)
+            cap = std::min(cus * per_cu, resident_batch_capacity());
+    }
+    return cap;
+}
+
+// Tiles of T (at most the kernel's slots per block), at most one record per
+// thread and all resident at once.
+bool resident_fits(long long n, long long m, int T)
+{
+    if (!resident_allowed() || T < 1 || T > kResidentSlots) return false;
+    const long long nt = (n + m + T - 1) / T;
+    return nt >= 1 && nt <= kResidentMaxTiles && nt <= resident_capacity();
+}
+
 }  // namespace finom
 
 using namespace finom;
@@ -863,44 +905,7 @@ int dense_matvec(const double* x_rows, int64_t n, const double* y_cols, int64_t 
 // ---------------------------------------------------------------------------
 // Resident-state solver (one cooperative launch per solve)
 // ---------------------------------------------------------------------------
-constexpr int kResBlock = 512, kResIpt = 8, kResWaves = 4;
-constexpr int kResT = kResBlock * kResIpt;
 
-static bool resident_allowed()
-{
-    const char* e = getenv("FINOM_RESIDENT");
-    return !(e && e[0] == '0');
-}
-
-// Blocks of the resident kernel that can be resident at once on the current
-// device (0 when the device cannot launch it cooperatively).
-static int resident_capacity()
-{
-    int dev = 0, coop = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resident_1d<kResBlock, kResIpt, kResWaves>, kResBlock, 0) !=
-        hipSuccess)
-        return 0;
-    return cus * per_cu;
-}
-
-// A 1D problem of n + m points whose tiles of kResT all fit on the device at
-// once (two fixed carry slots per thread bound the tile count as well).
-static bool resident_fits(long long n, long long m)
-{
-    if (!resident_allowed()) return false;
-    const long long nt = (n + m + kResT - 1) / kResT;
-    if (nt < 2 || nt > kResBlock) return false;   // one record per thread
-    static int cap = -1;
-    static std::mutex mu;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        if (cap < 0) cap = resident_capacity();
-    }
-    return nt <= cap;
-}
 
 // Runs the whole loop; the final phi is left in UF and the returned psi in UG
 // (both as the fast state).
@@ -922,6 +927,7 @@ static int run_resident(Alloc& al, const Part& pk, const Part& pkt, Ext<float>* 
     a.n = pk.R;
     a.m = pk.C;
     a.ntiles = pk.ntiles;
+    a.T = pk.T;
     a.rec = al.dev<unsigned long long>(5 * (size_t)pk.ntiles);
     a.fail = al.dev<int>(1);
     // records start at zero (tag 0: written 0 times)
@@ -937,8 +943,8 @@ static int run_resident(Alloc& al, const Part& pk, const Part& pkt, Ext<float>* 
         HIPCHK(hipEventCreate(&ev1));
         HIPCHK(hipEventRecord(ev0, s));
         void* args[] = {&a};
-        HIPCHK(hipLaunchCooperativeKernel((const void*)k_resident_1d<kResBlock, kResIpt, kResWaves>, dim3(pk.ntiles),
-                                          dim3(kResBlock), args, 0, s));
+        HIPCHK(hipLaunchCooperativeKernel((const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves>,
+                                          dim3(pk.ntiles), dim3(kResidentBlock), args, 0, s));
         HIPCHK(hipEventRecord(ev1, s));
         int* hfail = al.host<int>(1);
         HIPCHK(hipMemcpyAsync(hfail, a.fail, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -982,10 +988,11 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
     hipStream_t s = (hipStream_t)stream;
     try {
         Alloc al(stream);
-        // the resident solver runs tiles of 512 x 8
-        const bool try_resident = o.precision == 1 && fast_allowed() && resident_fits(n, m);
-        const int cfg = try_resident ? 2 : tuned_cfg(o.precision, n + m);
+        // the tile shape does not depend on the kernel that runs the tiles,
+        // so a problem gets the same tiles alone and in a batch
+        const int cfg = tuned_cfg(o.precision, n + m);
         const int T = kCfgs[cfg].T();
+        const bool try_resident = o.precision == 1 && fast_allowed() && resident_fits(n, m, T);
         const size_t eb = ext_bytes(o.precision);
 
         // validation and log masses
@@ -1040,7 +1047,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         ProbState* ps = al.dev<ProbState>(2);      // [0] iteration, [1] cost
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
-        const bool resident = try_resident && fast && T == kResT;
+        const bool resident = try_resident && fast;
         if (resident) {
             al.uploaded();
             const int st = run_resident(al, pk, pkt, (Ext<float>*)F, (Ext<float>*)G[0], (const Ext<float>*)lu,

@@ -34,8 +34,8 @@ struct ResidentArgs {
     const int* zy;            // y among x: #{i : x_i <= y_j}
     const int* trs;           // x starts of the tiles (ntiles + 1)
     long long n, m;
-    int ntiles;               // at most the block size
-    int pad;
+    int ntiles;               // tiles of the problem (at most kResidentMaxTiles)
+    int T;                    // merged points per tile (at most the block's slots)
     unsigned long long* rec;  // tagged records: [ntiles][2] x totals, [ntiles][2] y totals, [ntiles] partial errors; zero at launch
     int* fail;                // set when a wait exceeds its bound
     unsigned spin_limit;      // polls before a wait gives up
@@ -64,6 +64,11 @@ struct ResidentArgs {
 // the high half and its exponent in the low half; a partial error is a
 // non-negative double. Both are restored exactly.
 constexpr unsigned kResidentSpin = 1u << 22;   // default bound of a wait, in polls (~seconds)
+constexpr int kResidentMaxTiles = 512;         // tiles of one problem (one record per thread)
+// The kernels' shape: 512 threads of 8 slots (tiles of up to 4096 merged
+// points), two blocks per CU (four waves per SIMD, at most 128 registers).
+constexpr int kResidentBlock = 512, kResidentIpt = 8, kResidentWaves = 4;
+constexpr int kResidentSlots = kResidentBlock * kResidentIpt;
 
 __device__ __forceinline__ unsigned long long rec_of(Ext<float> v, unsigned tag)
 {
@@ -143,11 +148,11 @@ struct ResidentIn {
 };
 
 template <bool PART>
-__device__ __forceinline__ void resident_read(const ResidentArgs& a, const unsigned long long* tot,
+__device__ __forceinline__ void resident_read(const ResidentArgs& a, int tile, const unsigned long long* tot,
                                               const unsigned long long* part, unsigned tag, int* s_flag,
                                               ResidentIn& in)
 {
-    const int t = threadIdx.x, tile = blockIdx.x, nt = a.ntiles;
+    const int t = threadIdx.x, nt = a.ntiles;
     in.cl = in.cu = ext_zero<float>();
     in.part = 0.0;
     if (t < nt) {
@@ -347,35 +352,53 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
 
 // MINW: waves per SIMD the kernel must allow (two blocks of 512 per CU need
 // four, so at most 128 registers per lane).
-template <int BLOCK, int IPT, int MINW>
-__global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
+// The block's LDS: the tile's column scans, per-wave partial results, the
+// slots' masses and their dividing indices (as rows, within the tile).
+template <int BLOCK, int IPT>
+struct ResidentLds {
+    static constexpr int T = BLOCK * IPT;
+    static constexpr int NW = BLOCK / kWave;
+    __align__(16) float l[T + 4];
+    __align__(16) float u[T + 4];
+    float f[6 * NW];
+    int i[6 * NW];
+    double d[NW];
+    Ext<float> a[T];
+    unsigned short z[T];
+    int flag;   // 0 once a wait of this block has failed
+};
+
+// Solves one problem's tile to the end of its loop (every tile of the problem
+// must be running on some block of the grid at the same time).
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int tile, ResidentLds<BLOCK, IPT>& L)
 {
     static_assert(IPT % 4 == 0, "chunks are read as float4");
-    constexpr int T = BLOCK * IPT;
     constexpr int NW = BLOCK / kWave;
-    __shared__ __align__(16) float s_l[T + 4];
-    __shared__ __align__(16) float s_u[T + 4];
-    __shared__ float s_f[6 * NW];
-    __shared__ int s_i[6 * NW];
-    __shared__ double s_d[NW];
-    __shared__ Ext<float> s_a[T];           // the slots' masses
-    __shared__ unsigned short s_z[T];       // the slots' dividing indices (as rows), within the tile
-
-    const int tile = blockIdx.x;
+    float* const s_l = L.l;
+    float* const s_u = L.u;
+    float* const s_f = L.f;
+    int* const s_i = L.i;
+    double* const s_d = L.d;
+    Ext<float>* const s_a = L.a;
+    unsigned short* const s_z = L.z;
+    int& s_flag = L.flag;
+    const int T = a.T;
     const int nt = a.ntiles;
     unsigned long long* rec_x = a.rec;                       // totals of the x points' column terms
     unsigned long long* rec_y = a.rec + 2 * (size_t)nt;      // totals of the y points' column terms
     unsigned long long* rec_p = a.rec + 4 * (size_t)nt;      // partial errors of the checking sweep
     // the tile: x points [r0, r0 + nr), y points [c0, c0 + nc)
     const long long m0 = (long long)tile * T;
-    const long long m1 = min(m0 + T, a.n + a.m);
+    const long long m1 = min(m0 + (long long)T, a.n + a.m);
     const long long r0 = min(max((long long)a.trs[tile], 0LL), a.n);
     const long long r1 = min(max((long long)a.trs[tile + 1], r0), a.n);
     const long long c0 = min(max(m0 - r0, 0LL), a.m);
     long long c1 = min(max(m1 - r1, c0), a.m);
     if (c1 - c0 > T) c1 = c0 + T;
-    const int nc = (int)(c1 - c0);
-    const int nr = (int)min(r1 - r0, (long long)(T - nc));
+    // block-uniform (scalar registers, whatever memory the bounds came from)
+    const int nc = __builtin_amdgcn_readfirstlane((int)(c1 - c0));
+    const int nr = __builtin_amdgcn_readfirstlane((int)min(r1 - r0, (long long)(T - nc)));
 
     // per slot: state and B in registers; mass and, as a row, its dividing
     // index as a column index of this tile (y rows over the tile's x, x rows
@@ -400,7 +423,6 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
     // SIMDs favour the older block's waves: a block raises its waves' issue
     // priority from its records to its publication, so that a block on the
     // critical path is not held back by its neighbour's column work.
-    __shared__ int s_flag;   // 0 once a wait of this block has failed
     if (threadIdx.x == 0) s_flag = 1;
     // the first sweep's column totals (x points) from the initial state
     Ext<float> own_l, own_u;
@@ -437,7 +459,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         // records of this iteration's sweeps: write l + 1 of their buffers
         const unsigned tag = (unsigned)((l + 1) & 1);
         __builtin_amdgcn_s_setprio(2);
-        resident_read<false>(a, rec_x, nullptr, tag, &s_flag, in);
+        resident_read<false>(a, tile, rec_x, nullptr, tag, &s_flag, in);
         block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.0, s_f + 2 * NW,
                                          s_i + 2 * NW, s_d);
         __syncthreads();
@@ -461,7 +483,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         resident_columns<BLOCK, IPT>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
         const int ryl = own_l.e, ryu = own_u.e;
         __builtin_amdgcn_s_setprio(2);
-        resident_read<true>(a, rec_y, rec_p, tag, &s_flag, in);
+        resident_read<true>(a, tile, rec_y, rec_p, tag, &s_flag, in);
         block_totals_write<BLOCK, true>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, in.part, s_f + 2 * NW,
                                         s_i + 2 * NW, s_d);
         __syncthreads();
@@ -501,6 +523,58 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
         P->converged = (ok && err <= tol) ? 1 : 0;
         P->status = (!(err == err) || err == __builtin_inf()) ? 1 : 0;
         P->done = 1;
+    }
+}
+
+// One problem, one tile per block.
+template <int BLOCK, int IPT, int MINW>
+__global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
+{
+    __shared__ ResidentLds<BLOCK, IPT> L;
+    resident_solve<BLOCK, IPT>(a, blockIdx.x, L);
+}
+
+// Many problems on one persistent grid. Blocks take the problems' tiles in
+// order from a counter (problem p owns the tiles [first[p], first[p + 1]))
+// and solve each to the end of its problem's loop before taking another. A
+// block waits only for tiles of its own problem; those are handed out before
+// any later problem's, and every problem has at most as many tiles as the
+// grid has blocks, so the blocks of earlier problems, which wait for nothing
+// that has not been handed out, finish and take the missing tiles.
+static_assert(sizeof(ResidentArgs) % 4 == 0, "read as 32-bit words");
+
+struct ResidentBatch {
+    const ResidentArgs* probs;
+    const int* first;         // nprob + 1 tile offsets
+    int nprob;
+    int total;                // first[nprob]
+    int* next;                // tile counter, zero at launch
+};
+
+template <int BLOCK, int IPT, int MINW>
+__global__ __launch_bounds__(BLOCK, MINW) void k_resident_batch(ResidentBatch b)
+{
+    __shared__ ResidentLds<BLOCK, IPT> L;
+    __shared__ int s_g;
+    for (;;) {
+        __syncthreads();   // the previous tile's LDS is no longer read
+        if (threadIdx.x == 0) s_g = __hip_atomic_fetch_add(b.next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        // block-uniform values in scalar registers, as in the one-problem kernel
+        const int g = __builtin_amdgcn_readfirstlane(s_g);
+        if (g >= b.total) break;
+        int lo = 0, hi = b.nprob - 1;   // the last problem whose first tile is at most g
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (__builtin_amdgcn_readfirstlane(b.first[mid]) <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        ResidentArgs a;
+        const unsigned* src = reinterpret_cast<const unsigned*>(b.probs + lo);
+        unsigned* dst = reinterpret_cast<unsigned*>(&a);
+#pragma unroll
+        for (int w = 0; w < (int)(sizeof(ResidentArgs) / 4); ++w) dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+        resident_solve<BLOCK, IPT>(a, __builtin_amdgcn_readfirstlane(g - b.first[lo]), L);
     }
 }
 

@@ -39,10 +39,13 @@ def _desc_2d(p, tol=None, itr_max=None):
 
 
 def _alone(d, precision, resident=False):
-    """The member solved by a single call. Batches run the streaming sweeps,
-    so by default the single call does too (FINOM_RESIDENT=0): then the
-    results agree bit for bit. With resident=True a 1D FP32 call may take the
-    resident solver, whose results agree to rounding."""
+    """The member solved by a single call. A batch solves its 1D FP32 members
+    that fit on the resident solver, as a single call does, and the rest on
+    the streaming sweeps; the server runs everything on the streaming sweeps.
+    resident=True lets the single call take the resident solver (compare with
+    a batch); resident=False keeps it on the streaming sweeps
+    (FINOM_RESIDENT=0; compare with the server). Either way the results agree
+    bit for bit: the tiles do not depend on the kernel that runs them."""
     import os
     from paper_2605_26659_amd import sinkhorn_w1_1d, sinkhorn_w1_2d
     if d["dim"] == 1:
@@ -94,8 +97,10 @@ def test_1d_members_equal_alone_solves(precision):
     st, res = finom_batch(descs, precision=precision)
     assert st in (FINOM_OK, FINOM_NOT_CONVERGED)
     for d, r in zip(descs, res):
-        ra, fa, ga = _alone(d, precision)
+        ra, fa, ga = _alone(d, precision, resident=True)
         _assert_same(r, d, ra, fa, ga)
+    if precision == 1:   # members on the resident solver and on the streaming sweeps
+        assert any(r["fast"] == 2 for r in res) and any(r["fast"] != 2 for r in res)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -117,7 +122,7 @@ def test_mixed_1d_2d_members_equal_alone_solves(precision):
     descs.append(_desc_2d(p4))
     st, res = finom_batch(descs, precision=precision)
     for d, r in zip(descs, res):
-        ra, fa, ga = _alone(d, precision)
+        ra, fa, ga = _alone(d, precision, resident=True)
         _assert_same(r, d, ra, fa, ga)
 
 
@@ -151,7 +156,7 @@ def test_validation_failures_are_reported_and_skipped():
     assert st == FINOM_E_UNSORTED
     assert [r["status"] for r in res] == [FINOM_OK, FINOM_E_UNSORTED, FINOM_E_MASS, FINOM_E_ARG,
                                           FINOM_OK]
-    ra, fa, ga = _alone(descs[0], 1)
+    ra, fa, ga = _alone(descs[0], 1, resident=True)
     _assert_same(res[0], descs[0], ra, fa, ga)
     _assert_same(res[4], descs[4], ra, fa, ga)
 
