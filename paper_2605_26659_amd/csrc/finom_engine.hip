@@ -549,7 +549,9 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
     for (int i = 0; i < nj; ++i) {
         Job* j = jobs[i];
         j->fast = j->d.dim == 1 && j->Bx && fast_allowed() && hfflags[i] == 0;
-        if (!j->fast) continue;
+        j->gen = !j->fast && resident_ && j->d.dim == 1 && j->Bx && fast_allowed() &&
+                 resident_fits(j->p.na, j->p.nb, j->pk[0].T, true);
+        if (!j->fast && !j->gen) continue;
         const double kappa = 1.0 / (j->d.eps * kLn2);
         FastStateTask t;
         memset(&t, 0, sizeof(t));
@@ -586,14 +588,20 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
 // ---------------------------------------------------------------------------
 // resident batch
 // ---------------------------------------------------------------------------
-int resident_batch_capacity()
+static const void* resident_batch_kernel(bool gen)
+{
+    return gen ? (const void*)k_resident_batch<kResidentBlock, kResidentIpt, kResidentWavesGen, true>
+               : (const void*)k_resident_batch<kResidentBlock, kResidentIpt, kResidentWaves, false>;
+}
+
+int resident_batch_capacity(bool gen)
 {
     int dev = 0, coop = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resident_batch<kResidentBlock, kResidentIpt, kResidentWaves>, kResidentBlock,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_batch_kernel(gen), kResidentBlock, 0) !=
+        hipSuccess)
         return 0;
     return cus * per_cu;
 }
@@ -601,10 +609,18 @@ int resident_batch_capacity()
 void Engine::solve_resident()
 {
     if (precision_ != 1 || !fast_allowed() || !resident_allowed()) return;
-    std::vector<Job*> rj;
-    for (Job* j : pending_init_)
-        if (j->d.dim == 1 && j->fast && resident_fits(j->p.na, j->p.nb, j->pk[0].T)) rj.push_back(j);
-    if (rj.empty()) return;
+    for (int gen = 0; gen < 2; ++gen) {
+        std::vector<Job*> rj;
+        for (Job* j : pending_init_)
+            if (gen ? j->gen : (j->d.dim == 1 && j->fast && resident_fits(j->p.na, j->p.nb, j->pk[0].T, false)))
+                rj.push_back(j);
+        if (!rj.empty()) run_resident_batch(rj, gen != 0);
+    }
+}
+
+void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen)
+{
+    std::vector<Job*> rj = jobs;
     // larger problems first: the tiles are handed out in this order
     std::stable_sort(rj.begin(), rj.end(), [](const Job* a, const Job* b) { return a->pk[0].ntiles > b->pk[0].ntiles; });
     std::vector<Job*> rest;
@@ -663,11 +679,10 @@ void Engine::solve_resident()
     b.nprob = (int)rj.size();
     b.total = total;
     b.next = flags + 1;
-    const int grid = std::min(total, resident_capacity());
+    const int grid = std::min(total, resident_capacity(gen));
     void* kargs[] = {&b};
     HIPCHK(hipEventRecord(ev0_, s_));
-    HIPCHK(hipLaunchCooperativeKernel((const void*)k_resident_batch<kResidentBlock, kResidentIpt, kResidentWaves>, dim3(grid),
-                                      dim3(kResidentBlock), kargs, 0, s_));
+    HIPCHK(hipLaunchCooperativeKernel(resident_batch_kernel(gen), dim3(grid), dim3(kResidentBlock), kargs, 0, s_));
     HIPCHK(hipEventRecord(ev1_, s_));
     int* hfail = al.host<int>(1);
     HIPCHK(hipMemcpyAsync(hfail, flags, sizeof(int), hipMemcpyDeviceToHost, s_));
@@ -979,7 +994,7 @@ std::vector<Job*> Engine::harvest()
     // the fast sweeps' state back to log potentials, in place, before the costs
     std::vector<FastStateTask> ft;
     for (Job* j : fin) {
-        if (!j->fast) continue;
+        if (!j->fast && !j->gen) continue;
         const double kappa = 1.0 / (j->d.eps * kLn2);
         FastStateTask t;
         memset(&t, 0, sizeof(t));
@@ -1061,7 +1076,7 @@ std::vector<Job*> Engine::harvest()
         r.sweeps = j->d.dim == 1 ? 2 * st.iters + 1 : 4 * st.iters + 2;
         r.loop_ms = j->loop_ms;
         r.status = st.status ? FINOM_E_NUMERIC : (st.converged ? FINOM_OK : FINOM_NOT_CONVERGED);
-        r.fast = j->fast ? (j->resident ? 2 : 1) : 0;
+        r.fast = j->fast ? (j->resident ? 2 : 1) : (j->gen ? 3 : 0);
         free_slots_.push(j->slot);
         j->slot = -1;
     }
@@ -1178,6 +1193,7 @@ int finom_batch(const finom_problem* probs, int64_t count, const finom_opts* opt
             j->bind();
         }
         Engine eng(o.precision, s, (int)valid.size(), true);
+        eng.enable_resident();
         eng.setup(valid, !o.skip_checks);
         for (Job* j : valid) {
             if (j->status != FINOM_OK) {

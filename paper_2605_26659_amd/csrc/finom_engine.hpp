@@ -59,6 +59,8 @@ struct Job {
     Ext<float>* Bx = nullptr;   // 1D FP32: 2^{2 x kappa} and 2^{2 y kappa} for the fast sweeps
     Ext<float>* By = nullptr;
     bool fast = false;          // runs on the fast sweeps
+    bool gen = false;           // 1D FP32 beyond the fast bound, for the resident solver's extended-number
+                                // variant (state as for the fast sweeps); only when the engine solves resident
     bool resident = false;      // solved by the resident batch kernel (final psi in G[0])
     Part pk[2], pkt[2], pc[2];   // per axis: K, K^T, cost partition of K
     void bind();
@@ -78,9 +80,13 @@ public:
     // Joins a prepared job to the iteration (between rounds). False when no
     // state slot is free.
     bool add(Job* j);
+    // Lets setup() prepare 1D FP32 jobs beyond the fast bound for the resident
+    // solver; the caller then runs solve_resident() before any round.
+    void enable_resident() { resident_ = true; }
     // Solves the 1D FP32 jobs that joined since the last round and fit the
-    // resident solver, to the end of their loops, in one persistent launch;
-    // they are then ready for harvest. The other jobs are left to round().
+    // resident solver, to the end of their loops, in one persistent launch per
+    // variant; they are then ready for harvest. The other jobs are left to
+    // round().
     void solve_resident();
     // k iterations (k even) of every live job; then reads their states.
     void round(int k);
@@ -97,6 +103,7 @@ public:
 
 private:
     void rebuild();
+    void run_resident_batch(const std::vector<Job*>& rj, bool gen);
     void launch_iterations(int k, hipStream_t s);
     void read_states();
 
@@ -104,6 +111,7 @@ private:
     hipStream_t s_;
     int cap_;
     bool use_graphs_;
+    bool resident_ = false;
     ProbState* ps_ = nullptr;       // cap_ + 1 states; the last is the cost sweeps' (never done)
     ProbState* hps_ = nullptr;      // pinned mirror
     std::priority_queue<int, std::vector<int>, std::greater<int>> free_slots_;   // lowest first

@@ -285,14 +285,16 @@ bool fast_allowed();
 // The resident solver is used for eligible 1D FP32 problems unless
 // FINOM_RESIDENT=0.
 bool resident_allowed();
-// Blocks of the resident kernels (single problem and batch) that can be
-// resident at once on the current device; 0 when it cannot launch them
-// cooperatively. resident_batch_capacity is the batch kernel's alone.
-int resident_capacity();
-int resident_batch_capacity();
+// Blocks of the resident kernels (single problem and batch; gen: the variant
+// with extended-number scans) that can be resident at once on the current
+// device; 0 when it cannot launch them cooperatively.
+// resident_batch_capacity is the batch kernel's alone.
+int resident_capacity(bool gen);
+int resident_batch_capacity(bool gen);
 // Whether a 1D problem of n + m points on tiles of T runs on the resident
-// solver, alone or in a batch, once its tiles pass the fast sweeps' bound.
-bool resident_fits(long long n, long long m, int T);
+// solver, alone or in a batch: the fast variant once its tiles pass the fast
+// sweeps' bound, the gen variant otherwise.
+bool resident_fits(long long n, long long m, int T, bool gen);
 // Classifies the 1D pair (x: n, y: m) on partition pk (rows x) and its
 // transpose pkt for the fast sweeps; fills 2^{c kappa} for both meshes when
 // eligible. Synchronises the stream. Returns true when the pair is eligible.
@@ -314,8 +316,12 @@ void enqueue_fast_state(Alloc& al, const std::vector<FastStateTask>& tasks, hipS
 // Static range bound of every tile of both products of a 1D problem; when
 // it holds, B = 2^{2 c kappa} of both meshes into *Bx / *By and the masses u,
 // v as Ext<float> over the log masses lu, lv (which the bound has read).
+// With convert_always the conversions are made also when the bound fails
+// (for the resident solver's extended-number variant); the return value is
+// still the bound's.
 bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, double* lu, double* lv, const double* u,
-                   const double* v, double eps, Ext<float>** Bx, Ext<float>** By, hipStream_t s);
+                   const double* v, double eps, Ext<float>** Bx, Ext<float>** By, hipStream_t s,
+                   bool convert_always = false);
 
 constexpr double kCoordLimit = 33554432.0;   // 2^25: bound on |coordinate| / (eps ln 2)
 

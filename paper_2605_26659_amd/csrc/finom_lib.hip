@@ -585,7 +585,8 @@ bool fast_allowed()
 
 
 bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, double* lu, double* lv, const double* u,
-                   const double* v, double eps, Ext<float>** Bx, Ext<float>** By, hipStream_t s)
+                   const double* v, double eps, Ext<float>** Bx, Ext<float>** By, hipStream_t s,
+                   bool convert_always)
 {
     *Bx = *By = nullptr;
     const double kappa = 1.0 / (eps * kLn2);
@@ -623,7 +624,8 @@ bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, double* lu, doubl
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hflag[0]) return false;
+    const bool bounded = hflag[0] == 0;
+    if (!bounded && !convert_always) return false;
     *Bx = al.dev<Ext<float>>(pk.R);
     *By = al.dev<Ext<float>>(pk.C);
     std::vector<FastStateTask> ft(4);
@@ -633,7 +635,7 @@ bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, double* lu, doubl
     ft[2].out = lu; ft[2].in = u; ft[2].n = pk.R; ft[2].mode = 1;
     ft[3].out = lv; ft[3].in = v; ft[3].n = pk.C; ft[3].mode = 1;
     enqueue_fast_state(al, ft, s);
-    return true;
+    return bounded;
 }
 
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -787,31 +789,33 @@ bool resident_allowed()
 // The smaller of the two kernels' capacities, so that a problem is resident
 // alone exactly when it is resident in a batch. Computed once per process on
 // the device current at the first call.
-int resident_capacity()
+int resident_capacity(bool gen)
 {
-    static int cap = -1;
+    static int cap[2] = {-1, -1};
     static std::mutex mu;
     std::lock_guard<std::mutex> lk(mu);
-    if (cap < 0) {
+    int& c = cap[gen ? 1 : 0];
+    if (c < 0) {
         int dev = 0, coop = 0, cus = 0, per_cu = 0;
-        cap = 0;
+        c = 0;
+        const void* k = gen ? (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWavesGen, true>
+                            : (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves, false>;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves>,
-                                                         kResidentBlock, 0) == hipSuccess)
-            cap = std::min(cus * per_cu, resident_batch_capacity());
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kResidentBlock, 0) == hipSuccess)
+            c = std::min(cus * per_cu, resident_batch_capacity(gen));
     }
-    return cap;
+    return c;
 }
 
 // Tiles of T (at most the kernel's slots per block), at most one record per
 // thread and all resident at once.
-bool resident_fits(long long n, long long m, int T)
+bool resident_fits(long long n, long long m, int T, bool gen)
 {
     if (!resident_allowed() || T < 1 || T > kResidentSlots) return false;
     const long long nt = (n + m + T - 1) / T;
-    return nt >= 1 && nt <= kResidentMaxTiles && nt <= resident_capacity();
+    return nt >= 1 && nt <= kResidentMaxTiles && nt <= resident_capacity(gen);
 }
 
 }  // namespace finom
@@ -911,7 +915,7 @@ int dense_matvec(const double* x_rows, int64_t n, const double* y_cols, int64_t 
 // (both as the fast state).
 static int run_resident(Alloc& al, const Part& pk, const Part& pkt, Ext<float>* UF, Ext<float>* UG,
                         const Ext<float>* Ax, const Ext<float>* Ay, const Ext<float>* Bx, const Ext<float>* By,
-                        ProbState* ps, ProbState* hps, hipStream_t s, finom_result* res)
+                        ProbState* ps, ProbState* hps, hipStream_t s, finom_result* res, bool gen)
 {
     ResidentArgs a;
     memset(&a, 0, sizeof(a));
@@ -943,8 +947,9 @@ static int run_resident(Alloc& al, const Part& pk, const Part& pkt, Ext<float>* 
         HIPCHK(hipEventCreate(&ev1));
         HIPCHK(hipEventRecord(ev0, s));
         void* args[] = {&a};
-        HIPCHK(hipLaunchCooperativeKernel((const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves>,
-                                          dim3(pk.ntiles), dim3(kResidentBlock), args, 0, s));
+        const void* k = gen ? (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWavesGen, true>
+                            : (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves, false>;
+        HIPCHK(hipLaunchCooperativeKernel(k, dim3(pk.ntiles), dim3(kResidentBlock), args, 0, s));
         HIPCHK(hipEventRecord(ev1, s));
         int* hfail = al.host<int>(1);
         HIPCHK(hipMemcpyAsync(hfail, a.fail, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -992,7 +997,8 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         // so a problem gets the same tiles alone and in a batch
         const int cfg = tuned_cfg(o.precision, n + m);
         const int T = kCfgs[cfg].T();
-        const bool try_resident = o.precision == 1 && fast_allowed() && resident_fits(n, m, T);
+        const bool try_resident = o.precision == 1 && fast_allowed() && resident_fits(n, m, T, false);
+        const bool try_gen = o.precision == 1 && fast_allowed() && resident_fits(n, m, T, true);
         const size_t eb = ext_bytes(o.precision);
 
         // validation and log masses
@@ -1026,15 +1032,19 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         const Part pc = make_part_like(al, pk, cost_tile_size(), s);
         Ext<float>* Bx = nullptr;
         Ext<float>* By = nullptr;
-        const bool fast =
-            o.precision == 1 && fast_allowed() && setup_fast_1d(al, pk, pkt, lu, lv, u, v, eps, &Bx, &By, s);
+        const bool fast = o.precision == 1 && fast_allowed() &&
+                          setup_fast_1d(al, pk, pkt, lu, lv, u, v, eps, &Bx, &By, s, try_gen);
+        // tiles beyond the fast bound: the resident solver's extended-number
+        // variant, on the same state representation
+        const bool gen = !fast && try_gen;
+        const bool ext_state = fast || gen;
         const double kappa = 1.0 / (eps * kLn2);
 
         // state: phi = 1/n, psi = 1/m, as log2 potentials, or for the fast
         // sweeps as U = w 2^{-c kappa} in the same buffers
         double* F = al.dev<double>(n);
         double* G[2] = {al.dev<double>(m), al.dev<double>(m)};
-        if (fast) {
+        if (ext_state) {
             std::vector<FastStateTask> ft(2);
             memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
             ft[0].out = F; ft[0].in = x; ft[0].n = n; ft[0].a = -log2((double)n); ft[0].b = -kappa;
@@ -1047,11 +1057,11 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         ProbState* ps = al.dev<ProbState>(2);      // [0] iteration, [1] cost
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
-        const bool resident = try_resident && fast;
+        const bool resident = (try_resident && fast) || gen;
         if (resident) {
             al.uploaded();
             const int st = run_resident(al, pk, pkt, (Ext<float>*)F, (Ext<float>*)G[0], (const Ext<float>*)lu,
-                                        (const Ext<float>*)lv, Bx, By, ps, hps, s, res);
+                                        (const Ext<float>*)lv, Bx, By, ps, hps, s, res, gen);
             if (st != FINOM_OK) return fail(st);
         }
         const int nparts = std::max(pkt.ntiles, pc.ntiles);
@@ -1106,7 +1116,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         // returned pair (F, G[l % 2]) (the resident solver leaves it in
         // (F, G[0])); <C, Gamma> from the FP64 moment sums
         double* Gf = resident ? G[0] : G[hps[0].iters & 1];
-        if (fast) {
+        if (ext_state) {
             std::vector<FastStateTask> ft(2);
             memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
             ft[0].out = F; ft[0].mesh = x; ft[0].n = n; ft[0].b = kappa; ft[0].mode = 2;
@@ -1131,7 +1141,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         finish_result(res, hps[0], hps[1].w1);
-        res->fast = fast ? (resident ? 2 : 1) : 0;
+        res->fast = fast ? (resident ? 2 : 1) : (gen ? 3 : 0);
         if (hps[0].status) return fail(FINOM_E_NUMERIC);
         return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
     } catch (...) {

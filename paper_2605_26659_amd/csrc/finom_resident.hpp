@@ -19,6 +19,8 @@
 // way round. The arithmetic per element is that of k_sweep_fast; the tile
 // reference exponents come from the tile's own totals.
 #pragma once
+#include <type_traits>
+
 #include "finom_fast.hpp"
 
 namespace finom {
@@ -66,8 +68,10 @@ struct ResidentArgs {
 constexpr unsigned kResidentSpin = 1u << 22;   // default bound of a wait, in polls (~seconds)
 constexpr int kResidentMaxTiles = 512;         // tiles of one problem (one record per thread)
 // The kernels' shape: 512 threads of 8 slots (tiles of up to 4096 merged
-// points), two blocks per CU (four waves per SIMD, at most 128 registers).
-constexpr int kResidentBlock = 512, kResidentIpt = 8, kResidentWaves = 4;
+// points). The fast variant runs two blocks per CU (four waves per SIMD, at
+// most 128 registers); the variant with extended-number scans needs twice the
+// LDS for them and runs one (two waves per SIMD).
+constexpr int kResidentBlock = 512, kResidentIpt = 8, kResidentWaves = 4, kResidentWavesGen = 2;
 constexpr int kResidentSlots = kResidentBlock * kResidentIpt;
 
 __device__ __forceinline__ unsigned long long rec_of(Ext<float> v, unsigned tag)
@@ -269,12 +273,59 @@ __device__ __forceinline__ void block_totals_read(const float* s_f, const int* s
     }
 }
 
-// The local half of a sweep: the column terms (slots [c_first, c_first +
-// ncol), column index k - c_first) against the tile's own totals, to LDS, and
-// their in-tile scan. Needs nothing from other blocks.
+// Exclusive prefix (s_l) and inclusive suffix (s_u) of a tile's extended
+// column terms in place, thread t owning columns [t IPT, t IPT + IPT), and the
+// total before the end at s_l[BLOCK IPT]; the caller has passed a barrier
+// since the columns were written. Terms past ncol count as zero.
 template <int BLOCK, int IPT>
+__device__ __forceinline__ void resident_scan_ext(Ext<float>* s_l, Ext<float>* s_u, int nc, Ext<float>* s_tmp)
+{
+    Ext<float> vl[IPT], vu[IPT];
+    const int base = threadIdx.x * IPT;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const bool live = base + q < nc;
+        vl[q] = live ? s_l[base + q] : ext_zero<float>();
+        vu[q] = live ? s_u[base + q] : ext_zero<float>();
+    }
+    Ext<float> sl = ext_zero<float>(), su = ext_zero<float>();
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        sl = ext_add(sl, vl[q]);
+        su = ext_add(su, vu[q]);
+    }
+    Ext<float> el, eu, tl, tu;
+    block_scan_both<float, BLOCK>(sl, su, el, eu, tl, tu, s_tmp);
+    // every chunk was read before the scan's barrier: overwrite in place
+    Ext<float> run = el;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const Ext<float> t = vl[q];
+        s_l[base + q] = run;
+        run = ext_add(run, t);
+    }
+    Ext<float> runu = eu;
+#pragma unroll
+    for (int q = IPT - 1; q >= 0; --q) {
+        runu = ext_add(runu, vu[q]);
+        s_u[base + q] = runu;
+    }
+    if (threadIdx.x == BLOCK - 1) {
+        s_l[BLOCK * IPT] = run;
+        s_u[BLOCK * IPT] = ext_zero<float>();
+    }
+    __syncthreads();
+}
+
+// The local half of a sweep: the column terms (slots [c_first, c_first +
+// ncol), column index k - c_first) to LDS, and their in-tile scan. Needs
+// nothing from other blocks. On the fast sweeps' tiles the terms are plain
+// FP32 against the tile's own totals (r0l, r0u); with GEN they are extended
+// numbers, for tiles whose terms span more than FP32's range.
+template <int BLOCK, int IPT, bool GEN, typename Term>
 __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l, int r0u, const Ext<float>* U,
-                                                 const Ext<float>* B, float* s_l, float* s_u, float* s_f)
+                                                 const Ext<float>* B, Term* s_l, Term* s_u, float* s_f,
+                                                 Ext<float>* s_tmp)
 {
     // Opaque copies of the slot bounds and the thread index: without them the
     // compiler hoists every slot's masks and LDS offsets of both sweeps out of
@@ -286,12 +337,18 @@ __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l,
     for (int q = 0; q < IPT; ++q) {
         const int k = tid + q * BLOCK - c_first;
         if (k >= 0 && k < ncol) {
-            s_l[k] = ldexp_m(U[q].m * B[q].m, U[q].e + B[q].e - r0l);
-            s_u[k] = ldexp_m(U[q].m, U[q].e - r0u);
+            if constexpr (GEN) {
+                s_l[k] = Ext<float>{U[q].m * B[q].m, U[q].e + B[q].e};
+                s_u[k] = U[q];
+            } else {
+                s_l[k] = ldexp_m(U[q].m * B[q].m, U[q].e + B[q].e - r0l);
+                s_u[k] = ldexp_m(U[q].m, U[q].e - r0u);
+            }
         }
     }
     __syncthreads();
-    fast_tile_scan<BLOCK, IPT>(s_l, s_u, ncol, s_f);
+    if constexpr (GEN) resident_scan_ext<BLOCK, IPT>(s_l, s_u, ncol, s_tmp);
+    else fast_tile_scan<BLOCK, IPT>(s_l, s_u, ncol, s_f);
 }
 
 // The rows of a sweep (slots [r_first, r_first + nrow), dividing index Z as a
@@ -299,11 +356,11 @@ __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l,
 // states and leaves the next sweep's tile totals (and for CHECK the tile's
 // partial error) in the block's LDS slots. CHECK also keeps the rows' old
 // states in `old` (the pair the loop head returns when it stops).
-template <int BLOCK, int IPT, bool CHECK>
-__device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<float> CU, int ncol, int r_first, int nrow, int r0l,
-                                              int r0u, Ext<float>* U, const Ext<float>* s_a, const Ext<float>* B,
-                                              const unsigned short* s_z, Ext<float>* old, const float* s_l,
-                                              const float* s_u, float* s_f, int* s_i, double* s_d)
+template <int BLOCK, int IPT, bool CHECK, bool GEN, typename Term>
+__device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<float> CU, int ncol, int r_first,
+                                              int nrow, int r0l, int r0u, Ext<float>* U, const Ext<float>* s_a,
+                                              const Ext<float>* B, const unsigned short* s_z, Ext<float>* old,
+                                              const Term* s_l, const Term* s_u, float* s_f, int* s_i, double* s_d)
 {
     constexpr int NW = BLOCK / kWave;
     int tid = threadIdx.x;
@@ -316,7 +373,7 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
     RefAcc n1{0.f, kZeroExp}, n2{0.f, kZeroExp};
     // every slot's scan values first (unconditional: each slot's dividing
     // index is within the scans), so that no row waits on its own LDS reads
-    float sl[IPT], su[IPT];
+    Term sl[IPT], su[IPT];
     Ext<float> A[IPT];
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
@@ -330,9 +387,16 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
         const int k = tid + q * BLOCK - r_first;
         if (k >= 0 && k < nrow) {
             const Ext<float> Aq = A[q];
-            const float pm = cl_rel + ldexp_m(sl[q], shl);
-            const float qm = ldexp_m(su[q], shu) + cu_rel;
-            const Ext<float> W = ext_add(Ext<float>{pm, rl}, Ext<float>{qm * B[q].m, ru + B[q].e});
+            Ext<float> W;
+            if constexpr (GEN) {
+                const Ext<float> L = ext_add(CL, sl[q]);
+                const Ext<float> R = ext_add(su[q], CU);
+                W = ext_add(L, Ext<float>{R.m * B[q].m, R.e + B[q].e});
+            } else {
+                const float pm = cl_rel + ldexp_m(sl[q], shl);
+                const float qm = ldexp_m(su[q], shu) + cu_rel;
+                W = ext_add(Ext<float>{pm, rl}, Ext<float>{qm * B[q].m, ru + B[q].e});
+            }
             const Ext<float> Un = ext_norm(Ext<float>{Aq.m * __builtin_amdgcn_rcpf(W.m), Aq.e - W.e});
             if (CHECK) {
                 const int ep = U[q].e + W.e;
@@ -342,8 +406,16 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
                 old[q] = U[q];
             }
             U[q] = Un;
-            ref_add(n1, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
-            ref_add(n2, Un);
+            if constexpr (GEN) {
+                // totals of terms of any range: against the largest so far
+                const Ext<float> t1 = ext_add(Ext<float>{n1.s, n1.r}, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
+                const Ext<float> t2 = ext_add(Ext<float>{n2.s, n2.r}, Un);
+                n1 = RefAcc{t1.m, t1.e};
+                n2 = RefAcc{t2.m, t2.e};
+            } else {
+                ref_add(n1, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
+                ref_add(n2, Un);
+            }
         }
     }
     block_totals_write<BLOCK, CHECK>(n1, n2, red, s_f + 4 * NW, s_i + 4 * NW, s_d);
@@ -354,12 +426,14 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
 // four, so at most 128 registers per lane).
 // The block's LDS: the tile's column scans, per-wave partial results, the
 // slots' masses and their dividing indices (as rows, within the tile).
-template <int BLOCK, int IPT>
+template <int BLOCK, int IPT, bool GEN>
 struct ResidentLds {
     static constexpr int T = BLOCK * IPT;
     static constexpr int NW = BLOCK / kWave;
-    __align__(16) float l[T + 4];
-    __align__(16) float u[T + 4];
+    using Term = typename std::conditional<GEN, Ext<float>, float>::type;
+    __align__(16) Term l[T + 4];
+    __align__(16) Term u[T + 4];
+    Ext<float> tmp[GEN ? 2 * NW : 1];
     float f[6 * NW];
     int i[6 * NW];
     double d[NW];
@@ -370,13 +444,16 @@ struct ResidentLds {
 
 // Solves one problem's tile to the end of its loop (every tile of the problem
 // must be running on some block of the grid at the same time).
-template <int BLOCK, int IPT>
-__device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int tile, ResidentLds<BLOCK, IPT>& L)
+template <int BLOCK, int IPT, bool GEN>
+__device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int tile,
+                                               ResidentLds<BLOCK, IPT, GEN>& L)
 {
     static_assert(IPT % 4 == 0, "chunks are read as float4");
     constexpr int NW = BLOCK / kWave;
-    float* const s_l = L.l;
-    float* const s_u = L.u;
+    using Term = typename ResidentLds<BLOCK, IPT, GEN>::Term;
+    Term* const s_l = L.l;
+    Term* const s_u = L.u;
+    Ext<float>* const s_tmp = L.tmp;
     float* const s_f = L.f;
     int* const s_i = L.i;
     double* const s_d = L.d;
@@ -432,8 +509,15 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         for (int q = 0; q < IPT; ++q) {
             const int k = threadIdx.x + q * BLOCK - nc;
             if (k >= 0 && k < nr) {
-                ref_add(n1, Ext<float>{U[q].m * B[q].m, U[q].e + B[q].e});
-                ref_add(n2, U[q]);
+                if constexpr (GEN) {
+                    const Ext<float> t1 = ext_add(Ext<float>{n1.s, n1.r}, Ext<float>{U[q].m * B[q].m, U[q].e + B[q].e});
+                    const Ext<float> t2 = ext_add(Ext<float>{n2.s, n2.r}, U[q]);
+                    n1 = RefAcc{t1.m, t1.e};
+                    n2 = RefAcc{t2.m, t2.e};
+                } else {
+                    ref_add(n1, Ext<float>{U[q].m * B[q].m, U[q].e + B[q].e});
+                    ref_add(n2, U[q]);
+                }
             }
         }
         block_total2_write<BLOCK>(n1, n2, s_f + 4 * NW, s_i + 4 * NW);
@@ -454,7 +538,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
     Ext<float> uold[IPT];   // the y points' states the loop head checks
     for (;;) {
         // ---- K^T phi with the marginal check: columns x, rows y
-        resident_columns<BLOCK, IPT>(nc, nr, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
+        resident_columns<BLOCK, IPT, GEN>(nc, nr, own_l.e, own_u.e, U, B, s_l, s_u, s_f, s_tmp);
         const int rxl = own_l.e, rxu = own_u.e;
         // records of this iteration's sweeps: write l + 1 of their buffers
         const unsigned tag = (unsigned)((l + 1) & 1);
@@ -468,7 +552,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         Ext<float> CL, CU;
         double pe;
         block_totals_read<BLOCK, false>(s_f + 2 * NW, s_i + 2 * NW, s_d, CL, CU, pe);
-        resident_rows<BLOCK, IPT, true>(CL, CU, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
+        resident_rows<BLOCK, IPT, true, GEN>(CL, CU, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
         block_totals_read<BLOCK, true>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
         if (threadIdx.x < kWave) {
             resident_publish(3, rec_y + 2 * tile, rec_of(own_l, tag), rec_y + 2 * tile + 1, rec_of(own_u, tag),
@@ -480,7 +564,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         // is needed before the columns: the scans were last read before the
         // rows' barrier, and the LDS read since then is written again only
         // after the column phase's barriers.
-        resident_columns<BLOCK, IPT>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f);
+        resident_columns<BLOCK, IPT, GEN>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f, s_tmp);
         const int ryl = own_l.e, ryu = own_u.e;
         __builtin_amdgcn_s_setprio(2);
         resident_read<true>(a, tile, rec_y, rec_p, tag, &s_flag, in);
@@ -500,7 +584,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
             break;
         }
         // ---- K psi: rows x
-        resident_rows<BLOCK, IPT, false>(CL, CU, nc, nc, nr, ryl, ryu, U, s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i,
+        resident_rows<BLOCK, IPT, false, GEN>(CL, CU, nc, nc, nr, ryl, ryu, U, s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i,
                                          s_d);
         block_totals_read<BLOCK, false>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
         if (threadIdx.x < kWave)
@@ -527,11 +611,11 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
 }
 
 // One problem, one tile per block.
-template <int BLOCK, int IPT, int MINW>
+template <int BLOCK, int IPT, int MINW, bool GEN>
 __global__ __launch_bounds__(BLOCK, MINW) void k_resident_1d(ResidentArgs a)
 {
-    __shared__ ResidentLds<BLOCK, IPT> L;
-    resident_solve<BLOCK, IPT>(a, blockIdx.x, L);
+    __shared__ ResidentLds<BLOCK, IPT, GEN> L;
+    resident_solve<BLOCK, IPT, GEN>(a, blockIdx.x, L);
 }
 
 // Many problems on one persistent grid. Blocks take the problems' tiles in
@@ -551,10 +635,10 @@ struct ResidentBatch {
     int* next;                // tile counter, zero at launch
 };
 
-template <int BLOCK, int IPT, int MINW>
+template <int BLOCK, int IPT, int MINW, bool GEN>
 __global__ __launch_bounds__(BLOCK, MINW) void k_resident_batch(ResidentBatch b)
 {
-    __shared__ ResidentLds<BLOCK, IPT> L;
+    __shared__ ResidentLds<BLOCK, IPT, GEN> L;
     __shared__ int s_g;
     for (;;) {
         __syncthreads();   // the previous tile's LDS is no longer read
@@ -574,7 +658,7 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_batch(ResidentBatch b)
         unsigned* dst = reinterpret_cast<unsigned*>(&a);
 #pragma unroll
         for (int w = 0; w < (int)(sizeof(ResidentArgs) / 4); ++w) dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
-        resident_solve<BLOCK, IPT>(a, __builtin_amdgcn_readfirstlane(g - b.first[lo]), L);
+        resident_solve<BLOCK, IPT, GEN>(a, __builtin_amdgcn_readfirstlane(g - b.first[lo]), L);
     }
 }
 

@@ -99,8 +99,8 @@ def test_1d_members_equal_alone_solves(precision):
     for d, r in zip(descs, res):
         ra, fa, ga = _alone(d, precision, resident=True)
         _assert_same(r, d, ra, fa, ga)
-    if precision == 1:   # members on the resident solver and on the streaming sweeps
-        assert any(r["fast"] == 2 for r in res) and any(r["fast"] != 2 for r in res)
+    if precision == 1:   # members on both variants of the resident solver
+        assert any(r["fast"] == 2 for r in res) and any(r["fast"] == 3 for r in res)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -205,7 +205,9 @@ def test_uneven_4096_problem_workload():
         assert abs(r["iters"] - ito) <= max(3, 0.01 * ito), (i, r["iters"], ito)
         assert r["converged"] == (erro <= p.tol)
         if not r["converged"]:
-            assert abs(r["marginal_err"] - erro) <= 1e-3 * erro
+            # the loop head's error in FP32: each term |psi_old (K^T phi) - v|
+            # carries a few 2^-24 v, so the sum (mass 1) is good to ~3e-7
+            assert abs(r["marginal_err"] - erro) <= 3e-7 + 1e-4 * erro, (i, r["marginal_err"], erro)
         # marginals of the returned pair, recomputed by the oracle
         f, g = host(d["f_out"]), host(d["g_out"])
         s = dense.logmatvec(p.x, p.y, g, p.eps)

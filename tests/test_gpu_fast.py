@@ -41,9 +41,11 @@ def _against_oracle(p, iters, tol=TOL_ITER):
 
 
 @pytest.mark.parametrize("n,eps,fast", [(3000, 1e-1, True), (3000, 1e-2, False), (1 << 16, 1e-2, True)])
-def test_graded_lines_match_oracle_on_either_path(n, eps, fast):
+def test_graded_lines_match_oracle_on_either_path(n, eps, fast, monkeypatch):
     """n = 3000, eps = 1e-2: a tile of ~1000 columns spans ~0.67 near x = 1,
-    2 kappa span ~ 193 binary orders > the bound, so the general sweeps run."""
+    2 kappa span ~ 193 binary orders > the bound, so the general sweeps run
+    (the streaming sweeps: the resident solver is off)."""
+    monkeypatch.setenv("FINOM_RESIDENT", "0")
     p = wl.config_graded_1d(n, eps)
     res = _against_oracle(p, 40)
     assert bool(res["fast"]) == fast
@@ -62,8 +64,10 @@ def test_dominant_carries():
     assert res["fast"]
 
 
-def test_ineligible_line_runs_general_sweeps():
-    """Coarse mesh and small eps: a tile spans thousands of binary orders."""
+def test_ineligible_line_runs_general_sweeps(monkeypatch):
+    """Coarse mesh and small eps: a tile spans thousands of binary orders (the
+    streaming sweeps: the resident solver is off)."""
+    monkeypatch.setenv("FINOM_RESIDENT", "0")
     p = wl.config_batch_problem(3, 300)
     p = wl.Problem1D(p.x, p.y, p.u, p.v, 1e-3, 0.0, 30)
     res = _against_oracle(p, 30)

@@ -1,6 +1,8 @@
 """The resident solver: one cooperative launch runs the whole 1D loop with
-every tile's points held on chip by one block (FP32 fast sweeps, tiles of
-512 x 8; taken by sinkhorn_w1_1d when the tiles fit the GPU at once).
+every tile's points held on chip by one block (FP32; taken by sinkhorn_w1_1d
+when the tiles fit the GPU at once). Tiles within the fast sweeps' range bound
+run the variant with plain FP32 scans (result fast = 2), the others the
+variant with extended-number scans (fast = 3).
 
 * Against Algorithm 1 on the CPU at fixed iteration counts, on the graded
   workload and on uneven meshes (tiles holding only x or only y points).
@@ -60,6 +62,31 @@ def test_resident_matches_oracle_at_fixed_iterations(n):
     assert res["fast"] == 2
 
 
+@pytest.mark.parametrize("n,eps,iters", [(300, 1e-3, 30), (3000, 1e-2, 40), (20000, 1e-3, 24)])
+def test_extended_variant_matches_oracle(n, eps, iters):
+    """Tiles beyond the fast bound (coarse meshes, small eps: terms of one
+    tile span hundreds to thousands of binary orders): one tile, and a few."""
+    if n == 300:
+        q = wl.config_batch_problem(3, n)
+        p = wl.Problem1D(q.x, q.y, q.u, q.v, eps, 0.0, 0)
+    else:
+        p = wl.config_graded_1d(n, eps)
+    res = _against_oracle(p, iters)
+    assert res["fast"] == 3
+
+
+def test_extended_variant_and_general_sweeps_converge_to_the_same_plan(monkeypatch):
+    p = wl.config_graded_1d(3000, 1e-2)
+    rr, fr, gr = _solve(p, 1e-6, 20000)
+    monkeypatch.setenv("FINOM_RESIDENT", "0")
+    rs, fs, gs = _solve(p, 1e-6, 20000)
+    assert rr["fast"] == 3 and rs["fast"] == 0
+    assert rr["converged"] and rs["converged"]
+    assert abs(rr["w1"] - rs["w1"]) <= 1e-6 * rs["w1"]
+    assert abs(rr["iters"] - rs["iters"]) <= max(3, 0.01 * rs["iters"])
+    assert np.max(np.abs(fr - fs)) / p.eps <= 1e-4
+
+
 @pytest.mark.parametrize("n,m", [(2100, 2000), (30000, 60), (60, 30000), (5000, 9000)])
 def test_resident_uneven_meshes(n, m):
     """Few tiles, and tiles with columns of one kind only."""
@@ -98,8 +125,9 @@ def test_batch_with_more_tiles_than_the_grid():
     """Forty multi-tile members (about a thousand tiles in all, more than the
     grid holds) share the persistent grid: blocks take tiles in order and wait
     for their problem's other tiles. Members whose tiles fail the fast sweeps'
-    range bound (the smallest eps) run on the streaming sweeps, alone as in the
-    batch. Every member checked equals its single call bit for bit."""
+    range bound (the smallest eps) run on the extended-number variant's grid,
+    alone as in the batch. Every member checked equals its single call bit
+    for bit."""
     from paper_2605_26659_amd import FINOM_NOT_CONVERGED, FINOM_OK, finom_batch
     from test_gpu_batch import _alone, _assert_same, _desc_1d
     probs = [wl.config_batch_problem(100 + i, 20000 + 700 * i) for i in range(40)]
@@ -109,6 +137,7 @@ def test_batch_with_more_tiles_than_the_grid():
     assert all(r["status"] in (FINOM_OK, FINOM_NOT_CONVERGED) for r in res)
     resident = [i for i, r in enumerate(res) if r["fast"] == 2]
     other = [i for i, r in enumerate(res) if r["fast"] != 2]
+    assert all(res[i]["fast"] == 3 for i in other)   # beyond the bound: the extended variant
     tiles = sum(-(-(2 * len(probs[i].x)) // wl_tile(len(probs[i].x))) for i in resident)
     assert len(resident) >= 10 and tiles > 512, (len(resident), tiles)
     for i in resident[::max(1, len(resident) // 5)] + other[:2]:
