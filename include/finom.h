@@ -70,11 +70,14 @@ typedef struct {
     double loop_ms;       /* GPU time of the iteration loop (HIP events on `stream`),
                              excluding setup and the final cost reduction             */
     int64_t sweeps;       /* half-iteration products executed in the loop: 2 l + 1     */
-    int32_t fast;         /* 1D, precision 1, every tile inside the FP32 exponent range:
-                             1 when the loop ran the FP32 fast sweeps, 2 when it ran them
-                             in the resident solver (one cooperative launch holding the
-                             state on chip; sinkhorn_w1_1d when the tiles fit the GPU);
-                             0 otherwise                                                  */
+    int32_t fast;         /* 1D, precision 1: which loop ran. With every tile inside
+                             the FP32 exponent range: 1 for the streaming FP32 fast sweeps,
+                             2 for the resident solver (one cooperative launch holding the
+                             state on chip; single calls and finom_batch members whose
+                             tiles fit the GPU at once). Beyond that range: 3 for the
+                             resident solver's extended-number variant (same condition),
+                             else 0 (the streaming general sweeps). 0 for precision 0 and
+                             2D; the server runs 0 or 1.                                 */
     int32_t reserved;
 } finom_result;
 
