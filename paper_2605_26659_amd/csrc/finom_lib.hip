@@ -445,11 +445,11 @@ int tuned_cfg(int precision, long long merged)
 
 int default_cfg(int precision, long long merged)
 {
-    // one tile per line when it fits; otherwise the largest tile (fewest
-    // tiles, one memory latency per block)
+    // one tile per line when it fits; otherwise tiles of 2048, and of 4096
+    // once 2048 would give more tiles than the resident solver holds at once
     if (merged <= 1024) return 0;
     (void)precision;
-    return 1;
+    return merged <= 512LL * 2048 ? 1 : 2;
 }
 
 // ---------------------------------------------------------------------------
