@@ -273,6 +273,36 @@ __device__ __forceinline__ void block_totals_read(const float* s_f, const int* s
     }
 }
 
+// Exclusive prefix and exclusive suffix (thread order) of extended values over
+// the block: wave scans, then the waves' totals combined across lanes (lane j
+// of every wave reads wave j's total) rather than one after another.
+template <int BLOCK>
+__device__ __forceinline__ void block_scan_ext(Ext<float> vl, Ext<float> vu, Ext<float>& excl_l, Ext<float>& excl_u,
+                                               Ext<float>* s_tmp)
+{
+    constexpr int NW = BLOCK / kWave;
+    static_assert(NW == 8, "three DPP steps combine eight waves");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const Ext<float> il = wave_incl_prefix(vl);
+    const Ext<float> iu = wave_incl_suffix(vu);
+    if (lane == kWave - 1) s_tmp[wid] = il;
+    if (lane == 0) s_tmp[NW + wid] = iu;
+    __syncthreads();
+    const int j = lane & (NW - 1);
+    Ext<float> a = s_tmp[j], b = s_tmp[NW + j];
+    if (!(lane < NW && j < wid)) a = ext_zero<float>();
+    if (!(lane < NW && j > wid)) b = ext_zero<float>();
+    a = ext_add(a, dpp_ext<0x111>(a));   // row_shr:1
+    b = ext_add(b, dpp_ext<0x111>(b));
+    a = ext_add(a, dpp_ext<0x112>(a));   // row_shr:2
+    b = ext_add(b, dpp_ext<0x112>(b));
+    a = ext_add(a, dpp_ext<0x114>(a));   // row_shr:4
+    b = ext_add(b, dpp_ext<0x114>(b));
+    excl_l = ext_add(readlane_ext(a, NW - 1), dpp_ext<0x138>(il));   // wave_shr:1
+    excl_u = ext_add(dpp_ext<0x130>(iu), readlane_ext(b, NW - 1));   // wave_shl:1
+}
+
 // Exclusive prefix (s_l) and inclusive suffix (s_u) of a tile's extended
 // column terms in place, thread t owning columns [t IPT, t IPT + IPT), and the
 // total before the end at s_l[BLOCK IPT]; the caller has passed a barrier
@@ -294,8 +324,8 @@ __device__ __forceinline__ void resident_scan_ext(Ext<float>* s_l, Ext<float>* s
         sl = ext_add(sl, vl[q]);
         su = ext_add(su, vu[q]);
     }
-    Ext<float> el, eu, tl, tu;
-    block_scan_both<float, BLOCK>(sl, su, el, eu, tl, tu, s_tmp);
+    Ext<float> el, eu;
+    block_scan_ext<BLOCK>(sl, su, el, eu, s_tmp);
     // every chunk was read before the scan's barrier: overwrite in place
     Ext<float> run = el;
 #pragma unroll
