@@ -151,22 +151,23 @@ struct ResidentIn {
     double part;
 };
 
+// own_part: this tile's partial error, which its thread takes from the
+// block rather than from its record (the same value: records keep it exactly).
 template <bool PART>
 __device__ __forceinline__ void resident_read(const ResidentArgs& a, int tile, const unsigned long long* tot,
                                               const unsigned long long* part, unsigned tag, int* s_flag,
-                                              ResidentIn& in)
+                                              double own_part, ResidentIn& in)
 {
     const int t = threadIdx.x, nt = a.ntiles;
     in.cl = in.cu = ext_zero<float>();
     in.part = 0.0;
-    if (t < nt) {
-        if (t != tile) {
-            const Ext<float> v = ext_of_rec(rec_read(a, tot + 2 * t + (t > tile ? 1 : 0), tag, s_flag));
-            if (t < tile) in.cl = v;
-            else in.cu = v;
-        }
+    if (t < nt && t != tile) {
+        const Ext<float> v = ext_of_rec(rec_read(a, tot + 2 * t + (t > tile ? 1 : 0), tag, s_flag));
+        if (t < tile) in.cl = v;
+        else in.cu = v;
         if (PART) in.part = double_of_rec(rec_read(a, part + t, tag, s_flag));
     }
+    if (PART && t == tile) in.part = own_part;
 }
 
 // ---- block totals
@@ -573,7 +574,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         // records of this iteration's sweeps: write l + 1 of their buffers
         const unsigned tag = (unsigned)((l + 1) & 1);
         __builtin_amdgcn_s_setprio(2);
-        resident_read<false>(a, tile, rec_x, nullptr, tag, &s_flag, in);
+        resident_read<false>(a, tile, rec_x, nullptr, tag, &s_flag, 0.0, in);
         block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.0, s_f + 2 * NW,
                                          s_i + 2 * NW, s_d);
         __syncthreads();
@@ -597,7 +598,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         resident_columns<BLOCK, IPT, GEN>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f, s_tmp);
         const int ryl = own_l.e, ryu = own_u.e;
         __builtin_amdgcn_s_setprio(2);
-        resident_read<true>(a, tile, rec_y, rec_p, tag, &s_flag, in);
+        resident_read<true>(a, tile, rec_y, rec_p, tag, &s_flag, pe, in);
         block_totals_write<BLOCK, true>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, in.part, s_f + 2 * NW,
                                         s_i + 2 * NW, s_d);
         __syncthreads();
