@@ -52,8 +52,8 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # recorded beside them; after any change to those sources the traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
-TRAFFIC_RESIDENT = {"sources_sha256": "97aab2370c68f72a46c0512cc79f078838ff46622f1500597b8978221fe36bc8",
-                    "fetch_kib": 421493.0, "write_kib": 213368.0, "n": 1 << 20}
+TRAFFIC_RESIDENT = {"sources_sha256": "a8c0e16cbe0f876b096e625f9e19f5c9fe428c9874cf505c2ffc245d18be7948",
+                    "fetch_kib": 419616.0, "write_kib": 201081.0, "n": 1 << 20}
 TRAFFIC_STREAM = {"sources_sha256": "cdedeb22e36a32830477ce4c70afdf9dc1a95834a628ae1f32b2934952ca0711",
                   "fetch_kib": (22823.5 + 18713.6) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
@@ -427,7 +427,7 @@ def main():
         roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
                     "frac": achieved / ALU_PEAK_TOPS,
                     "traffic": measured_traffic(TRAFFIC_RESIDENT, RESIDENT_SOURCES, args.n),
-                    "kernel": "k_resident_1d: the whole loop in one cooperative launch",
+                    "kernel": "k_resident_1d<512, 8, 4, false>: the whole loop in one cooperative launch",
                     "avg_launch_ms": launch_ms, "avg_sweep_us": sweep_ms * 1e3,
                     "ops_per_grid_pt_iter": OPS_PER_PT_ITER,
                     "unit_note": "lane operations (each add, multiply, fma, ldexp, reciprocal counts once) "
