@@ -5,13 +5,15 @@ run the variant with plain FP32 scans (result fast = 2), the others the
 variant with extended-number scans (fast = 3).
 
 * Against Algorithm 1 on the CPU at fixed iteration counts, on the graded
-  workload and on uneven meshes (tiles holding only x or only y points).
-* Against the streaming fast sweeps at convergence (same plan to rounding)
-  and against a batch member (the batch runs the streaming sweeps).
+  workload, on uneven meshes (tiles holding only x or only y points) and,
+  for the extended variant, on tiles far beyond the FP32 range.
+* Against the streaming sweeps at convergence (same plan to rounding), and
+  batch members against single calls bit for bit, also with more tiles than
+  the persistent grid holds.
 * The loop head's edge cases (no iteration, one iteration), determinism, and
-  the bounded wait of its grid barrier (forced from the host with a wait
-  bound of zero polls: every block leaves the loop, the call reports a HIP
-  failure, the next call is unaffected).
+  the bounded wait for the other tiles' records (forced from the host with a
+  wait bound of zero polls: every block leaves the loop, the call reports a
+  HIP failure, the next call is unaffected), alone and in a batch.
 """
 import numpy as np
 import pytest
