@@ -54,8 +54,8 @@ FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
 TRAFFIC_RESIDENT = {"sources_sha256": "a8c0e16cbe0f876b096e625f9e19f5c9fe428c9874cf505c2ffc245d18be7948",
                     "fetch_kib": 419616.0, "write_kib": 201081.0, "n": 1 << 20}
-TRAFFIC_STREAM = {"sources_sha256": "cdedeb22e36a32830477ce4c70afdf9dc1a95834a628ae1f32b2934952ca0711",
-                  "fetch_kib": (22823.5 + 18713.6) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
+TRAFFIC_STREAM = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
+                  "fetch_kib": (22818.1 + 18715.2) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
