@@ -692,6 +692,7 @@ void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen)
     loop_ms_total_ += ms;
     for (Job* j : rj) {
         j->resident = true;
+        j->started = true;
         j->loop_ms = ms;
     }
     if (*hfail) {
@@ -707,6 +708,7 @@ bool Engine::add(Job* j)
     free_slots_.pop();
     max_slot_ = std::max(max_slot_, j->slot);
     j->loop_ms = 0.0;
+    j->started = false;
     active_.push_back(j);
     pending_init_.push_back(j);
     dirty_ = true;
@@ -748,7 +750,10 @@ void Engine::rebuild()
     // states of the jobs that joined since the last rebuild
     if (!pending_init_.empty()) {
         std::vector<StateInit> ini;
-        for (Job* j : pending_init_) ini.push_back(StateInit{j->slot, 0, j->d.itr_max, j->d.tol});
+        for (Job* j : pending_init_) {
+            ini.push_back(StateInit{j->slot, 0, j->d.itr_max, j->d.tol});
+            j->started = true;
+        }
         const StateInit* d_ini = upload_vec(al, ini);
         hipLaunchKernelGGL(k_init_states, dim3(blocks_for((long long)ini.size())), dim3(kBlock), 0, s_, d_ini,
                            (int)ini.size(), ps_);
@@ -972,7 +977,7 @@ std::vector<Job*> Engine::harvest()
 {
     std::vector<Job*> fin;
     for (Job* j : active_)
-        if (hps_[j->slot].done) fin.push_back(j);
+        if (j->started && hps_[j->slot].done) fin.push_back(j);
     if (fin.empty()) return fin;
 
     Alloc al(&ar_cost_, s_);

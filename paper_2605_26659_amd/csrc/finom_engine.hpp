@@ -62,6 +62,7 @@ struct Job {
     bool gen = false;           // 1D FP32 beyond the fast bound, for the resident solver's extended-number
                                 // variant (state as for the fast sweeps); only when the engine solves resident
     bool resident = false;      // solved by the resident batch kernel (final psi in G[0])
+    bool started = false;       // its iteration state has been set (harvest looks at it only then)
     Part pk[2], pkt[2], pc[2];   // per axis: K, K^T, cost partition of K
     void bind();
     double points() const { return 0.5 * (double)(p.na + p.nb); }

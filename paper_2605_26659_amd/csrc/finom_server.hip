@@ -101,6 +101,25 @@ void finom_server::run()
             delete r;
         }
     };
+    // the results of jobs that stopped: their memory back to the slab, their
+    // completions to the caller
+    auto publish = [&](const std::vector<Job*>& fin) {
+        for (Job* j : fin) {
+            Req* r = nullptr;
+            for (size_t i = 0; i < live.size(); ++i)
+                if (&live[i]->job == j) {
+                    r = live[i];
+                    live[i] = live.back();
+                    live.pop_back();
+                    break;
+                }
+            slab->release(j->mem, j->p.bytes);
+            if (r) {
+                complete(r, j->res);
+                delete r;
+            }
+        }
+    };
     try {
         for (;;) {
             std::vector<Req*> admit;
@@ -149,24 +168,15 @@ void finom_server::run()
                 std::lock_guard<std::mutex> lk(mu);
                 st.admitted += (int64_t)admit.size();
             }
+            // 1D FP32 requests that fit the resident solver are solved at once,
+            // as a single call would solve them; the others join the rounds
+            if (!admit.empty()) {
+                eng->solve_resident();
+                publish(eng->harvest());
+            }
             if (eng->live() == 0) continue;
             eng->round(k);
-            std::vector<Job*> fin = eng->harvest();
-            for (Job* j : fin) {
-                Req* r = nullptr;
-                for (size_t i = 0; i < live.size(); ++i)
-                    if (&live[i]->job == j) {
-                        r = live[i];
-                        live[i] = live.back();
-                        live.pop_back();
-                        break;
-                    }
-                slab->release(j->mem, j->p.bytes);
-                if (r) {
-                    complete(r, j->res);
-                    delete r;
-                }
-            }
+            publish(eng->harvest());
             eng->maybe_compact(0.75);
             std::lock_guard<std::mutex> lk(mu);
             st.rounds += 1;
@@ -178,6 +188,7 @@ void finom_server::run()
         fail_all(map_exception());
     }
 }
+
 
 extern "C" {
 
@@ -200,6 +211,7 @@ int finom_server_create(uint64_t hbm_budget_bytes, const finom_opts* opts, finom
         HIPCHK(hipStreamCreateWithFlags(&srv->s, hipStreamNonBlocking));
         srv->slab.reset(new Slab((size_t)hbm_budget_bytes));
         srv->eng.reset(new Engine(o.precision, srv->s, kServerSlots, false));
+        srv->eng->enable_resident();
         srv->st.hbm_budget = srv->slab->capacity();
         srv->th = std::thread([srv] { srv->run(); });
     } catch (...) {

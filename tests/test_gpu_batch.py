@@ -39,13 +39,13 @@ def _desc_2d(p, tol=None, itr_max=None):
 
 
 def _alone(d, precision, resident=False):
-    """The member solved by a single call. A batch solves its 1D FP32 members
-    that fit on the resident solver, as a single call does, and the rest on
-    the streaming sweeps; the server runs everything on the streaming sweeps.
-    resident=True lets the single call take the resident solver (compare with
-    a batch); resident=False keeps it on the streaming sweeps
-    (FINOM_RESIDENT=0; compare with the server). Either way the results agree
-    bit for bit: the tiles do not depend on the kernel that runs them."""
+    """The member solved by a single call. A batch and the server solve
+    their 1D FP32 members that fit on the resident solver, as a single call
+    does, and the rest on the streaming sweeps. resident=True lets the single
+    call take the resident solver (compare with a batch or the server);
+    resident=False keeps it on the streaming sweeps (FINOM_RESIDENT=0). The
+    results agree bit for bit: the tiles do not depend on the kernel that
+    runs them."""
     import os
     from paper_2605_26659_amd import sinkhorn_w1_1d, sinkhorn_w1_2d
     if d["dim"] == 1:

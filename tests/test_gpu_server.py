@@ -2,7 +2,8 @@
 device-memory footprint.
 
 * Every completed request equals the single-problem solve of the same
-  problem alone (bit for bit: the tile plan depends only on the problem),
+  problem alone (bit for bit: the tile plan depends only on the problem, and
+  1D FP32 requests that fit the resident solver take it, as single calls do),
   whatever else shares its rounds.
 * A budget that holds only a few requests at a time: the rest waits in
   arrival order and still completes.
@@ -57,7 +58,7 @@ def test_requests_equal_alone_solves(precision):
         d = descs[tickets[c["ticket"]]]
         assert c["problem"] is d
         assert 0.0 <= c["queue_ms"] <= c["latency_ms"]
-        ra, fa, ga = _alone(d, precision)
+        ra, fa, ga = _alone(d, precision, resident=True)
         _assert_same(c, d, ra, fa, ga)
 
 
@@ -75,7 +76,7 @@ def test_small_budget_queues_in_arrival_order():
     assert st["hbm_used"] == 0
     for c in done:
         d = descs[tk.index(c["ticket"])]
-        ra, fa, ga = _alone(d, 1)
+        ra, fa, ga = _alone(d, 1, resident=True)
         _assert_same(c, d, ra, fa, ga)
 
 
