@@ -64,6 +64,15 @@ def test_resident_matches_oracle_at_fixed_iterations(n):
     assert res["fast"] == 2
 
 
+@pytest.mark.parametrize("n,m", [(1, 1), (1, 7), (7, 1), (3, 5), (64, 1)])
+def test_resident_tiny_problems(n, m):
+    """One tile with a handful of points, one side possibly a single point
+    (most of the block's slots idle)."""
+    p = _uneven(7 * n + m, n, m, 5e-2)
+    res = _against_oracle(p, 12)
+    assert res["fast"] in (2, 3)
+
+
 @pytest.mark.parametrize("n,eps,iters", [(300, 1e-3, 30), (3000, 1e-2, 40), (20000, 1e-3, 24)])
 def test_extended_variant_matches_oracle(n, eps, iters):
     """Tiles beyond the fast bound (coarse meshes, small eps: terms of one
