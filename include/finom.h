@@ -139,6 +139,55 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
                    double* g_out, finom_result* res, void* stream);
 
 /*
+ * The transport plan Gamma = diag(phi) K diag(psi) (section 2.1), written
+ * densely from the potentials f = eps ln phi (n) and g = eps ln psi (m) that
+ * sinkhorn_w1_1d returns; these are the plans whose difference the tables of
+ * section 4 report. gamma (device, caller-owned, n * ld doubles, row-major,
+ * ld >= m) receives gamma[i*ld + j] = exp(((f_i + g_j) - |x_i - y_j|) / eps)
+ * in FP64; the entries j >= m of a row are left untouched. x and y need not
+ * be sorted. Asynchronous on `stream`; nothing is allocated.
+ * Errors (nothing written): FINOM_E_ARG (NULL pointer, size < 1, ld < m,
+ * eps <= 0 or not finite, n * ld overflows), FINOM_E_HIP.
+ */
+int finom_plan_1d(const double* x, int64_t n, const double* y, int64_t m,
+                  const double* f, const double* g, double eps, double* gamma,
+                  int64_t ld, void* stream);
+
+/*
+ * The same on tensor-product meshes (eq. 2d-kron): source grid x1 (n1) x
+ * y1 (m1), target grid x2 (n2) x y2 (m2), potentials f (n1*m1) and g (n2*m2)
+ * column-major as sinkhorn_w1_2d returns them. Row r = k + i*n1 is source
+ * point (x1_k, y1_i), column c = l + j*n2 is target point (x2_l, y2_j), and
+ * gamma[r*ld + c] = exp(((f_r + g_c) - (|x1_k - x2_l| + |y1_i - y2_j|)) / eps),
+ * ld >= n2*m2. Errors as finom_plan_1d.
+ */
+int finom_plan_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
+                  const double* x2, int64_t n2, const double* y2, int64_t m2,
+                  const double* f, const double* g, double eps, double* gamma,
+                  int64_t ld, void* stream);
+
+/*
+ * ||Gamma_a - Gamma_b||_F for two plans on the same 1D meshes, each given by
+ * its potentials (fa, ga) and (fb, gb) as in finom_plan_1d: the plan
+ * difference column of section 4's tables. Each entry difference is taken
+ * between the two FP64 plan entries as finom_plan_1d would write them; no
+ * plan is stored. out: one double in DEVICE memory, written asynchronously
+ * on `stream`. The sum of squares is reduced in a fixed order, so repeated
+ * calls give the same bits. Uses the per-stream workspace (16 KB).
+ * Errors (nothing written): FINOM_E_ARG (NULL pointer, size < 1, eps <= 0 or
+ * not finite), FINOM_E_NOMEM, FINOM_E_HIP.
+ */
+int finom_plan_diff_1d(const double* x, int64_t n, const double* y, int64_t m,
+                       const double* fa, const double* ga, const double* fb,
+                       const double* gb, double eps, double* out, void* stream);
+
+/* The same on tensor-product meshes, with the layout of finom_plan_2d. */
+int finom_plan_diff_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
+                       const double* x2, int64_t n2, const double* y2, int64_t m2,
+                       const double* fa, const double* ga, const double* fb,
+                       const double* gb, double eps, double* out, void* stream);
+
+/*
  * One problem of a batch or a serving request. dim = 1: Algorithm 1 on
  * x = x1 (n1 points, masses u) and y = x2 (n2 points, masses v); m1, m2, y1,
  * y2 are ignored. dim = 2: Algorithm 2 on the grids x1 (n1) x y1 (m1) and

@@ -6,6 +6,7 @@ Everything here is the plain O(N*M) definition, written for reading, not speed:
 * Sinkhorn scaling iteration psi = v / K^T phi, phi = u / K psi  (eq. iteration)
 * loop head check ||diag(psi) K^T phi - v||_1 > tol, cap itr_max (Algorithm 1)
 * plan Gamma = diag(phi) K diag(psi) and cost <C, Gamma>         (section 2.1)
+* ||Gamma_a - Gamma_b||_F, the plans' difference                  (section 4)
 * 2D: K = K_y (x) K_x on column-major grids; products evaluated
   axis by axis as vec(K_x Psi K_y^T) and vec(K_x^T Phi K_y)      (eqs. 2d-kron,
   2d-kpsi, 2d-ktphi; Algorithm 2)
@@ -112,8 +113,33 @@ def transport_cost_1d(x, y, f, g, eps) -> float:
 
 
 def plan_1d(x, y, f, g, eps) -> np.ndarray:
+    """Gamma = diag(phi) K diag(psi) as an n x m matrix (section 2.1):
+    Gamma_ij = exp((f_i + g_j - |x_i - y_j|)/eps)."""
+    x = np.asarray(x, np.float64); y = np.asarray(y, np.float64)
+    f = np.asarray(f, np.float64); g = np.asarray(g, np.float64)
     c = cost_matrix(x, y)
     return np.exp((f[:, None] + g[None, :] - c) / eps)
+
+
+def plan_2d(x1, y1, x2, y2, F, G, eps) -> np.ndarray:
+    """Gamma of tensor meshes as an (N1 M1) x (N2 M2) matrix, rows and columns
+    in column-major grid order: row k + i N1 is source point (x1_k, y1_i),
+    column l + j N2 target point (x2_l, y2_j), and the cost is
+    |x1_k - x2_l| + |y1_i - y2_j| (eq. 2d-block-entry). F, G: grids or flat
+    column-major vectors."""
+    XR, YR = np.meshgrid(np.asarray(x1, np.float64), np.asarray(y1, np.float64), indexing="ij")
+    XC, YC = np.meshgrid(np.asarray(x2, np.float64), np.asarray(y2, np.float64), indexing="ij")
+    c = (np.abs(XR.ravel(order="F")[:, None] - XC.ravel(order="F")[None, :])
+         + np.abs(YR.ravel(order="F")[:, None] - YC.ravel(order="F")[None, :]))
+    f = np.asarray(F, np.float64).ravel(order="F")
+    g = np.asarray(G, np.float64).ravel(order="F")
+    return np.exp((f[:, None] + g[None, :] - c) / eps)
+
+
+def plan_difference(gamma_a, gamma_b) -> float:
+    """||Gamma_a - Gamma_b||_F, the plan-difference column of section 4's tables."""
+    d = np.asarray(gamma_a, np.float64) - np.asarray(gamma_b, np.float64)
+    return float(np.sqrt(np.sum(d * d)))
 
 
 def sinkhorn_1d(x, y, u, v, eps, tol, itr_max) -> SinkhornResult:

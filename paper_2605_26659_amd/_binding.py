@@ -122,6 +122,12 @@ def load(path: os.PathLike | None = None):
     if hasattr(L, "sinkhorn_w1_2d"):
         L.sinkhorn_w1_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _d, _d,
                                      _i64, C.POINTER(Opts), _vp, _vp, C.POINTER(Result), _vp]
+    L.finom_plan_1d.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _d, _vp, _i64, _vp]
+    L.finom_plan_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _d, _vp,
+                                _i64, _vp]
+    L.finom_plan_diff_1d.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _d, _vp, _vp]
+    L.finom_plan_diff_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp,
+                                     _vp, _d, _vp, _vp]
     L.finom_batch.argtypes = [C.POINTER(Problem), _i64, C.POINTER(Opts), C.POINTER(Result), _vp]
     L.finom_footprint.argtypes = [C.POINTER(Problem), C.POINTER(Opts)]
     L.finom_footprint.restype = _i64
@@ -252,6 +258,63 @@ def sinkhorn_w1_2d(x1, y1, x2, y2, u, v, eps, tol, itr_max, *, precision=0, skip
                                C.byref(res), _stream_ptr(stream))
     _check(st, "sinkhorn_w1_2d")
     return res.as_dict(), f_out, g_out
+
+
+def finom_plan_1d(x, y, f, g, eps, gamma=None, *, ld=None, stream=None):
+    """Dense plan (n, ld) with gamma[i, j] = exp((f_i + g_j - |x_i - y_j|)/eps)
+    for j < m (device tensor; columns j >= m are left as they were)."""
+    torch = _torch()
+    n, m = x.numel(), y.numel()
+    ld = m if ld is None else int(ld)
+    if gamma is None:
+        gamma = torch.empty((n, ld), dtype=torch.float64, device=x.device)
+    if gamma.numel() < n * ld:
+        raise ValueError("gamma holds fewer than n * ld doubles")
+    st = load().finom_plan_1d(_dev(x, "x"), n, _dev(y, "y"), m, _dev(f, "f"), _dev(g, "g"),
+                              float(eps), _dev(gamma, "gamma"), ld, _stream_ptr(stream))
+    _check(st, "finom_plan_1d")
+    return gamma
+
+
+def finom_plan_2d(x1, y1, x2, y2, f, g, eps, gamma=None, *, ld=None, stream=None):
+    """Dense plan of tensor meshes, (n1 m1, ld), rows and columns in
+    column-major grid order; f, g flat column-major (as sinkhorn_w1_2d returns)."""
+    torch = _torch()
+    n1, m1, n2, m2 = x1.numel(), y1.numel(), x2.numel(), y2.numel()
+    ld = n2 * m2 if ld is None else int(ld)
+    if gamma is None:
+        gamma = torch.empty((n1 * m1, ld), dtype=torch.float64, device=x1.device)
+    if gamma.numel() < n1 * m1 * ld:
+        raise ValueError("gamma holds fewer than n1 * m1 * ld doubles")
+    st = load().finom_plan_2d(_dev(x1, "x1"), n1, _dev(y1, "y1"), m1, _dev(x2, "x2"), n2,
+                              _dev(y2, "y2"), m2, _dev(f, "f"), _dev(g, "g"), float(eps),
+                              _dev(gamma, "gamma"), ld, _stream_ptr(stream))
+    _check(st, "finom_plan_2d")
+    return gamma
+
+
+def finom_plan_diff_1d(x, y, fa, ga, fb, gb, eps, out=None, *, stream=None):
+    """||Gamma_a - Gamma_b||_F as a one-element device tensor."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    st = load().finom_plan_diff_1d(_dev(x, "x"), x.numel(), _dev(y, "y"), y.numel(),
+                                   _dev(fa, "fa"), _dev(ga, "ga"), _dev(fb, "fb"), _dev(gb, "gb"),
+                                   float(eps), _dev(out, "out"), _stream_ptr(stream))
+    _check(st, "finom_plan_diff_1d")
+    return out
+
+
+def finom_plan_diff_2d(x1, y1, x2, y2, fa, ga, fb, gb, eps, out=None, *, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x1.device)
+    st = load().finom_plan_diff_2d(_dev(x1, "x1"), x1.numel(), _dev(y1, "y1"), y1.numel(),
+                                   _dev(x2, "x2"), x2.numel(), _dev(y2, "y2"), y2.numel(),
+                                   _dev(fa, "fa"), _dev(ga, "ga"), _dev(fb, "fb"), _dev(gb, "gb"),
+                                   float(eps), _dev(out, "out"), _stream_ptr(stream))
+    _check(st, "finom_plan_diff_2d")
+    return out
 
 
 def finom_release():

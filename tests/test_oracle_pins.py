@@ -375,3 +375,72 @@ def test_c_algorithm2_matches_dense():
     assert np.max(np.abs(F - r.f)) / p.eps <= 1e-10
     assert np.max(np.abs(G - r.g)) / p.eps <= 1e-10
     assert abs(err - r.err) <= 1e-12
+
+
+# ----------------------------------------------------------------------------
+# Transport plans (section 2.1) and their difference (section 4's tables)
+# ----------------------------------------------------------------------------
+
+def test_plan_1d_marginals_of_a_solve():
+    """The returned pair's last update is phi = u / K psi, so the plan's row
+    sums are u; its column sums are psi * K^T phi, whose L1 distance to v is
+    the marginal error the loop checked last."""
+    rng = np.random.default_rng(31)
+    x = np.sort(rng.uniform(0, 1, 70)); y = np.sort(rng.uniform(0, 1, 55))
+    u = wl.normalise(rng.uniform(0.1, 1, 70)); v = wl.normalise(rng.uniform(0.1, 1, 55))
+    r = dense.sinkhorn_1d(x, y, u, v, 0.03, 1e-8, 100000)
+    assert r.iters > 5
+    P = dense.plan_1d(x, y, r.f, r.g, 0.03)
+    np.testing.assert_allclose(P.sum(axis=1), u, rtol=1e-12, atol=0)
+    assert abs(np.sum(np.abs(P.sum(axis=0) - v)) - r.err) <= 1e-13
+    # the cost is <C, Gamma>
+    assert abs(np.sum(dense.cost_matrix(x, y) * P) - r.w1) <= 1e-13 * r.w1
+
+
+def test_plan_2d_kronecker_factorisation():
+    """With F_ki = a_k + b_i and G_lj = c_l + d_j the tensor-mesh plan
+    factorises as Gamma_y (x) Gamma_x (eq. 2d-kron); the Kronecker product
+    fixes the row order k + i N1 and the column order l + j N2."""
+    rng = np.random.default_rng(32)
+    x1, y1 = np.sort(rng.uniform(0, 1, 4)), np.sort(rng.uniform(0, 1, 3))
+    x2, y2 = np.sort(rng.uniform(0, 1, 5)), np.sort(rng.uniform(0, 1, 2))
+    a, b = rng.uniform(-.1, .1, 4), rng.uniform(-.1, .1, 3)
+    c, d = rng.uniform(-.1, .1, 5), rng.uniform(-.1, .1, 2)
+    eps = 0.07
+    P = dense.plan_2d(x1, y1, x2, y2, a[:, None] + b[None, :], c[:, None] + d[None, :], eps)
+    ref = np.kron(dense.plan_1d(y1, y2, b, d, eps), dense.plan_1d(x1, x2, a, c, eps))
+    assert P.shape == (12, 10)
+    np.testing.assert_allclose(P, ref, rtol=1e-13, atol=0)
+
+
+def test_plan_2d_marginals_and_axis_cost():
+    """Row sums are u, the column sums' distance to v is the checked error,
+    and <C, Gamma> equals the cost evaluated axis by axis with moment
+    products (a different evaluation)."""
+    p = wl.paper_random_2d(5, seed=77)
+    r = dense.sinkhorn_2d(p.x1, p.y1, p.x2, p.y2, p.u, p.v, 0.05, 1e-9, 100000)
+    P = dense.plan_2d(p.x1, p.y1, p.x2, p.y2, r.f, r.g, 0.05)
+    np.testing.assert_allclose(P.sum(axis=1), p.u.ravel(order="F"), rtol=1e-11, atol=0)
+    assert abs(np.sum(np.abs(P.sum(axis=0) - p.v.ravel(order="F"))) - r.err) <= 1e-13
+    XR, YR = np.meshgrid(p.x1, p.y1, indexing="ij"); XC, YC = np.meshgrid(p.x2, p.y2, indexing="ij")
+    C = (np.abs(XR.ravel("F")[:, None] - XC.ravel("F")[None, :])
+         + np.abs(YR.ravel("F")[:, None] - YC.ravel("F")[None, :]))
+    assert abs(np.sum(C * P) - r.w1) <= 1e-12 * r.w1
+
+
+def test_plan_difference_closed_forms():
+    """Zero for equal plans; shifting f by delta scales every entry by
+    e^{delta/eps}; a 2 x 2 case by hand."""
+    x, y = np.array([0.0, 1.0]), np.array([0.0, 1.0])
+    Pa = dense.plan_1d(x, y, np.zeros(2), np.zeros(2), 1.0)
+    Pb = dense.plan_1d(x, y, np.array([0.0, np.log(2.0)]), np.zeros(2), 1.0)
+    assert dense.plan_difference(Pa, Pa) == 0.0
+    assert abs(dense.plan_difference(Pa, Pb) - np.sqrt(np.exp(-2.0) + 1.0)) <= 1e-15
+    rng = np.random.default_rng(33)
+    x = np.sort(rng.uniform(0, 1, 30)); y = np.sort(rng.uniform(0, 1, 20))
+    f, g = rng.uniform(-.02, .02, 30), rng.uniform(-.02, .02, 20)
+    eps, delta = 0.05, 1e-3
+    Pa = dense.plan_1d(x, y, f, g, eps)
+    Pb = dense.plan_1d(x, y, f + delta, g, eps)
+    ref = abs(1.0 - np.exp(delta / eps)) * np.sqrt(np.sum(Pa * Pa))
+    assert abs(dense.plan_difference(Pa, Pb) - ref) <= 1e-12 * ref
