@@ -62,6 +62,11 @@ RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_device.hpp",
                     "paper_2605_26659_amd/csrc/finom_types.hpp")
 STREAM_SOURCES = RESIDENT_SOURCES[1:]
+# The plan export (k_plan_export<true>) on the 160 x 160 paper workload, per
+# launch; `n` is the plan's row count.
+TRAFFIC_PLAN = {"sources_sha256": "81b9b566466ba8e5e64e2344982331be9e619045dded8b616bc7067ae99449a2",
+                "fetch_kib": 1701.02, "write_kib": 5120010.0, "n": 25600}
+PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
 
 
 def sources_digest(paths):
@@ -99,6 +104,8 @@ def parse():
                     help="full serving sweep (several arrival rates and the nominal 2000/s)")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving sample")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--plan-only", action="store_true",
+                    help="only the plan export / plan difference record (--steps launches each)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2605_26659_amd", "tune_gfx950.txt"),
                     help="tile-shape table: read if present, else tuned here and written")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -269,6 +276,62 @@ def bench_other_configs(precision):
     return out
 
 
+def bench_plan(reps=10):
+    """Plan export and plan difference on the paper's largest plan: the 2D
+    160 x 160 workload of section 4.3 (four sorted U[0,1] node vectors,
+    masses U[0,1], eps = 0.01, 1000 iterations), whose plan has 25600 x 25600
+    FP64 entries (5.2 GB). Potentials from FINOM solves with FP64 and FP32
+    scans; the export of the FP64 plan and ||Gamma_fp32 - Gamma_fp64||_F are
+    timed with HIP events on the stream the kernels run on."""
+    import torch
+    from paper_2605_26659_amd import finom_plan_2d, finom_plan_diff_2d, sinkhorn_w1_2d, workloads as wl
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    p = wl.paper_random_2d(160)
+    mesh = (dev(p.x1), dev(p.y1), dev(p.x2), dev(p.y2))
+    uv = (dev(p.u.ravel(order="F")), dev(p.v.ravel(order="F")))
+    pot = {}
+    for prec in (0, 1):
+        r, F, G = sinkhorn_w1_2d(*mesh, *uv, p.eps, 0.0, p.itr_max, precision=prec)
+        pot[prec] = (F, G)
+    rows, cols = p.u.size, p.v.size
+    gamma = torch.empty((rows, cols), dtype=torch.float64, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    F64, G64 = pot[0]
+    F32, G32 = pot[1]
+    finom_plan_2d(*mesh, F64, G64, p.eps, gamma)
+    finom_plan_diff_2d(*mesh, F32, G32, F64, G64, p.eps, out)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(s)
+    for _ in range(reps):
+        finom_plan_2d(*mesh, F64, G64, p.eps, gamma)
+    ev[1].record(s)
+    for _ in range(reps):
+        finom_plan_diff_2d(*mesh, F32, G32, F64, G64, p.eps, out)
+    ev[2].record(s)
+    torch.cuda.synchronize()
+    export_ms = ev[0].elapsed_time(ev[1]) / reps
+    diff_ms = ev[1].elapsed_time(ev[2]) / reps
+    total = float(gamma.sum())
+    del gamma
+    # algorithmic bytes of one export: the plan written once, the potentials
+    # and coordinates read once
+    bytes_export = 8.0 * rows * cols + 8.0 * 2 * (rows + cols)
+    gbs = bytes_export / (export_ms * 1e-3) / 1e9
+    return {"workload": "2D 160 x 160 sorted U[0,1] meshes, masses U[0,1], eps=0.01, 1000 iterations "
+                        "(section 4.3); plan 25600 x 25600 FP64",
+            "export": {"kernel": "k_plan_export<true>", "avg_launch_ms": export_ms,
+                       "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": gbs / HBM_PEAK_GBS,
+                                    "traffic": measured_traffic(TRAFFIC_PLAN, PLAN_SOURCES, rows),
+                                    "algorithmic_bytes": bytes_export},
+                       "plan_sum": total},
+            "difference": {"kernel": "k_plan_diff<true> + k_plan_diff_final", "avg_ms": diff_ms,
+                           "entries_per_s": rows * cols / (diff_ms * 1e-3),
+                           "fro_fp32_vs_fp64_scans": float(out.item())}}
+
+
 def _serving_pool(size, precision):
     """Materialised requests of the serving mix (70 % 1D graded n log-uniform
     in [1e3, 1e6], 30 % 2D tanh side log-uniform in [64, 512], eps 1e-2 or
@@ -379,6 +442,10 @@ def main():
         print(json.dumps({"copy_bytes": 8 * n, "copies": 10}), flush=True)
         return
 
+    if args.plan_only:
+        print(json.dumps(bench_plan(args.steps)), flush=True)
+        return
+
     if not args.no_autotune:
         from paper_2605_26659_amd import finom_autotune
         for p in (1, 0):
@@ -479,6 +546,7 @@ def main():
 
     if not args.no_other:
         extra.update(bench_other_configs(prec))
+        extra["plan_2d_160"] = bench_plan()
     if not args.no_batch:
         extra["batch_4096"] = bench_batch(prec)
     if args.serving or not args.no_serving:

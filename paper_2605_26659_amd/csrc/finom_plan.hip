@@ -12,14 +12,17 @@
 // x part + y part, and the exponential is the device library's FP64 one.
 //
 // Every entry is independent, so both kernels are a plain map over
-// (row, column chunk) items: an item is one row and kPlanBlock * kPlanIpt
-// consecutive columns, thread t taking columns t + q kPlanBlock, so each store
-// of a wave covers 64 consecutive doubles of the row. Export writes n*m
-// doubles and reads O(n + m): it is bound by HBM writes, 8 B per entry. The
-// difference writes nothing and evaluates two exponentials per entry: it is
-// bound by FP64 arithmetic. Its sum of squares is reduced per block in a
-// fixed order over a fixed grid, then the block partials by one block in a
-// fixed order, so the result is the same on every run.
+// (row group, column chunk) items: an item is kPlanRows consecutive rows and
+// kPlanBlock * kPlanIpt consecutive columns. Thread t takes the columns
+// t + q kPlanBlock, loads their potentials and coordinates once into
+// registers and reuses them for every row of the group; the row values are
+// the same for the whole block. Each store of a wave covers 64 consecutive
+// doubles of a row. Export writes n*m doubles and reads O(n + m): it is bound
+// by HBM writes, 8 B per entry. The difference writes nothing and evaluates
+// two exponentials per entry: it is bound by FP64 arithmetic. Its sum of
+// squares is reduced per block in a fixed order over a fixed grid, then the
+// block partials by one block in a fixed order, so the result is the same on
+// every run.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,7 +33,7 @@
 
 namespace finom {
 
-constexpr int kPlanBlock = 256, kPlanIpt = 8;
+constexpr int kPlanBlock = 256, kPlanIpt = 8, kPlanRows = 8;
 constexpr int kPlanChunk = kPlanBlock * kPlanIpt;
 constexpr int kPlanDiffGrid = 2048;      // blocks of the difference kernel
 constexpr long long kPlanMaxGrid = 1LL << 30;
@@ -54,70 +57,114 @@ struct PlanArgs {
     double* part;       // difference: one partial sum of squares per block
 };
 
-// Source coordinates and potential of row r.
-template <bool TD>
-__device__ __forceinline__ void plan_row(const PlanArgs& a, long long r, double& xr, double& yr)
+// Column data of one thread for one chunk: for each of its columns the
+// target coordinates and the potential(s). Columns past the end get cost 0
+// and potential 0 and are never stored or summed.
+template <bool TD, bool DIFF>
+struct PlanCols {
+    double cx[kPlanIpt], cy[kPlanIpt], ga[kPlanIpt], gb[kPlanIpt];
+};
+
+template <bool TD, bool DIFF>
+__device__ __forceinline__ void plan_load_cols(const PlanArgs& a, long long c0, PlanCols<TD, DIFF>& cc)
 {
+    long long l = c0, j = 0;
     if (TD) {
-        const long long i = r / a.ns1;
-        const long long k = r - i * a.ns1;
-        xr = a.xs[k];
-        yr = a.ys[i];
-    } else {
-        xr = a.xs[r];
-        yr = 0.0;
+        // first split by a rounded reciprocal, corrected by one step
+        j = (long long)((double)c0 * a.rinv_t1);
+        l = c0 - j * a.nt1;
+        if (l < 0) {
+            --j;
+            l += a.nt1;
+        } else if (l >= a.nt1) {
+            ++j;
+            l -= a.nt1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kPlanIpt; ++q) {
+        const long long c = c0 + (long long)q * kPlanBlock;
+        const bool in = c < a.cols;
+        cc.cx[q] = in ? a.xt[l] : 0.0;
+        cc.cy[q] = (TD && in) ? a.yt[j] : 0.0;
+        cc.ga[q] = in ? a.ga[c] : 0.0;
+        cc.gb[q] = (DIFF && in) ? a.gb[c] : 0.0;
+        if (TD) {
+            l += a.dl;
+            j += a.dj;
+            if (l >= a.nt1) {
+                l -= a.nt1;
+                ++j;
+            }
+        } else {
+            l += kPlanBlock;
+        }
     }
 }
 
-// The column indices (l, j) of column c on tensor meshes.
-__device__ __forceinline__ void plan_split(const PlanArgs& a, long long c, long long& l, long long& j)
+// Grid indices of the rows of a group: row r = k + i ns1. The first row is
+// split once per item; the next rows step k with a wrap into i.
+struct PlanRowIdx {
+    long long k, i;
+};
+
+template <bool TD>
+__device__ __forceinline__ PlanRowIdx plan_row_first(const PlanArgs& a, long long r0)
 {
-    j = (long long)((double)c * a.rinv_t1);
-    l = c - j * a.nt1;
-    if (l < 0) {
-        --j;
-        l += a.nt1;
-    } else if (l >= a.nt1) {
-        ++j;
-        l -= a.nt1;
-    }
+    if (!TD) return PlanRowIdx{r0, 0};
+    const long long i = r0 / a.ns1;
+    return PlanRowIdx{r0 - i * a.ns1, i};
 }
 
 template <bool TD>
-__device__ __forceinline__ double plan_cost(const PlanArgs& a, double xr, double yr, long long l, long long j)
+__device__ __forceinline__ void plan_row_next(const PlanArgs& a, PlanRowIdx& ri)
 {
-    if (TD) return fabs(xr - a.xt[l]) + fabs(yr - a.yt[j]);
-    return fabs(xr - a.xt[l]);
+    ++ri.k;
+    if (TD && ri.k == a.ns1) {
+        ri.k = 0;
+        ++ri.i;
+    }
+}
+
+// Source coordinates of a row (the same for the whole block).
+template <bool TD>
+__device__ __forceinline__ void plan_row(const PlanArgs& a, const PlanRowIdx& ri, double& xr, double& yr)
+{
+    xr = a.xs[ri.k];
+    yr = TD ? a.ys[ri.i] : 0.0;
+}
+
+template <bool TD>
+__device__ __forceinline__ double plan_cost(double xr, double yr, double cx, double cy)
+{
+    if (TD) return fabs(xr - cx) + fabs(yr - cy);
+    return fabs(xr - cx);
 }
 
 template <bool TD>
 __global__ __launch_bounds__(kPlanBlock) void k_plan_export(PlanArgs a)
 {
     for (long long it = blockIdx.x; it < a.items; it += gridDim.x) {
-        const long long r = it / a.chunks;
-        const long long c0 = (it - r * a.chunks) * kPlanChunk + threadIdx.x;
-        double xr, yr;
-        plan_row<TD>(a, r, xr, yr);
-        const double fr = a.fa[r];
-        double* out = a.gamma + r * a.ld;
-        long long l = c0, j = 0;
-        if (TD) plan_split(a, c0, l, j);
+        const long long rg = it / a.chunks;
+        const long long c0 = (it - rg * a.chunks) * kPlanChunk + threadIdx.x;
+        PlanCols<TD, false> cc;
+        plan_load_cols<TD, false>(a, c0, cc);
+        const long long r0 = rg * kPlanRows;
+        const int nr = (int)min((long long)kPlanRows, a.rows - r0);
+        PlanRowIdx ri = plan_row_first<TD>(a, r0);
+        for (int rr = 0; rr < nr; ++rr, plan_row_next<TD>(a, ri)) {
+            const long long r = r0 + rr;
+            double xr, yr;
+            plan_row<TD>(a, ri, xr, yr);
+            const double fr = a.fa[r];
+            double* out = a.gamma + r * a.ld;
 #pragma unroll
-        for (int q = 0; q < kPlanIpt; ++q) {
-            const long long c = c0 + (long long)q * kPlanBlock;
-            if (c < a.cols) {
-                const double arg = ((fr + a.ga[c]) - plan_cost<TD>(a, xr, yr, l, j)) / a.eps;
-                __builtin_nontemporal_store(exp(arg), out + c);
-            }
-            if (TD) {
-                l += a.dl;
-                j += a.dj;
-                if (l >= a.nt1) {
-                    l -= a.nt1;
-                    ++j;
+            for (int q = 0; q < kPlanIpt; ++q) {
+                const long long c = c0 + (long long)q * kPlanBlock;
+                if (c < a.cols) {
+                    const double arg = ((fr + cc.ga[q]) - plan_cost<TD>(xr, yr, cc.cx[q], cc.cy[q])) / a.eps;
+                    __builtin_nontemporal_store(exp(arg), out + c);
                 }
-            } else {
-                l += kPlanBlock;
             }
         }
     }
@@ -141,30 +188,26 @@ __global__ __launch_bounds__(kPlanBlock) void k_plan_diff(PlanArgs a)
     __shared__ double s_w[kPlanBlock / 64];
     double acc = 0.0;
     for (long long it = blockIdx.x; it < a.items; it += gridDim.x) {
-        const long long r = it / a.chunks;
-        const long long c0 = (it - r * a.chunks) * kPlanChunk + threadIdx.x;
-        double xr, yr;
-        plan_row<TD>(a, r, xr, yr);
-        const double fra = a.fa[r], frb = a.fb[r];
-        long long l = c0, j = 0;
-        if (TD) plan_split(a, c0, l, j);
+        const long long rg = it / a.chunks;
+        const long long c0 = (it - rg * a.chunks) * kPlanChunk + threadIdx.x;
+        PlanCols<TD, true> cc;
+        plan_load_cols<TD, true>(a, c0, cc);
+        const long long r0 = rg * kPlanRows;
+        const int nr = (int)min((long long)kPlanRows, a.rows - r0);
+        PlanRowIdx ri = plan_row_first<TD>(a, r0);
+        for (int rr = 0; rr < nr; ++rr, plan_row_next<TD>(a, ri)) {
+            const long long r = r0 + rr;
+            double xr, yr;
+            plan_row<TD>(a, ri, xr, yr);
+            const double fra = a.fa[r], frb = a.fb[r];
 #pragma unroll
-        for (int q = 0; q < kPlanIpt; ++q) {
-            const long long c = c0 + (long long)q * kPlanBlock;
-            if (c < a.cols) {
-                const double C = plan_cost<TD>(a, xr, yr, l, j);
-                const double d = exp(((fra + a.ga[c]) - C) / a.eps) - exp(((frb + a.gb[c]) - C) / a.eps);
-                acc = fma(d, d, acc);
-            }
-            if (TD) {
-                l += a.dl;
-                j += a.dj;
-                if (l >= a.nt1) {
-                    l -= a.nt1;
-                    ++j;
+            for (int q = 0; q < kPlanIpt; ++q) {
+                const long long c = c0 + (long long)q * kPlanBlock;
+                if (c < a.cols) {
+                    const double C = plan_cost<TD>(xr, yr, cc.cx[q], cc.cy[q]);
+                    const double d = exp(((fra + cc.ga[q]) - C) / a.eps) - exp(((frb + cc.gb[q]) - C) / a.eps);
+                    acc = fma(d, d, acc);
                 }
-            } else {
-                l += kPlanBlock;
             }
         }
     }
@@ -204,8 +247,9 @@ static void plan_shape(PlanArgs& a, long long ns1, long long ms1, long long nt1,
     }
     a.ld = ld;
     a.chunks = (a.cols + kPlanChunk - 1) / kPlanChunk;
-    if (a.rows > INT64_MAX / a.chunks) bad("plan: too many items");
-    a.items = a.rows * a.chunks;
+    const long long groups = (a.rows + kPlanRows - 1) / kPlanRows;
+    if (groups > INT64_MAX / a.chunks) bad("plan: too many items");
+    a.items = groups * a.chunks;
     a.rinv_t1 = 1.0 / (double)nt1;
     a.dl = (int)(kPlanBlock % nt1);
     a.dj = (int)(kPlanBlock / nt1);
