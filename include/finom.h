@@ -138,6 +138,29 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
                    int64_t itr_max, const finom_opts* opts, double* f_out,
                    double* g_out, finom_result* res, void* stream);
 
+/* Largest number of axes sinkhorn_w1_nd accepts. */
+#define FINOM_MAX_DIMS 8
+
+/*
+ * The Sinkhorn loop of Algorithms 1 and 2 on d-dimensional tensor-product
+ * meshes (the remark closing section 3): the kernel factorises as
+ * K = K_{d-1} (x) ... (x) K_0 for the cost sum_a |x_a - y_a|, and each product
+ * is applied along one axis after another with the 1D method.
+ * n_src, n_tgt: HOST arrays of d axis lengths (each >= 1); x_src, x_tgt: HOST
+ * arrays of d DEVICE pointers to the non-decreasing axis coordinates.
+ * u (prod n_src) and v (prod n_tgt) are column-major grids: element
+ * (k_0, ..., k_{d-1}) at k_0 + n_0 (k_1 + n_1 (k_2 + ...)), axis 0 fastest;
+ * f_out / g_out use the same layout. d = 1 is Algorithm 1 and d = 2
+ * Algorithm 2, on the general sweeps. Loop, check, outputs and errors as in
+ * sinkhorn_w1_2d; w1 = <sum_a |x_a - y_a|, Gamma> in FP64. FINOM_E_ARG also
+ * for d < 1 or d > FINOM_MAX_DIMS.
+ */
+int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src,
+                   const int64_t* n_tgt, const double* const* x_tgt,
+                   const double* u, const double* v, double eps, double tol,
+                   int64_t itr_max, const finom_opts* opts, double* f_out,
+                   double* g_out, finom_result* res, void* stream);
+
 /*
  * The transport plan Gamma = diag(phi) K diag(psi) (section 2.1), written
  * densely from the potentials f = eps ln phi (n) and g = eps ln psi (m) that

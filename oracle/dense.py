@@ -261,3 +261,94 @@ def sinkhorn_2d(x1, y1, x2, y2, u, v, eps, tol, itr_max, full=False) -> Sinkhorn
         it += 1
     cost = (transport_cost_2d_full if full else transport_cost_2d)(x1, y1, x2, y2, F, G, eps)
     return SinkhornResult(F, G, it, err, cost, err <= tol)
+
+
+# --------------------------------------------------------------------------
+# d dimensions (the remark closing section 3): K = K_{d-1} (x) ... (x) K_0 on
+# column-major grids (axis 0 fastest), each product applied axis by axis
+# --------------------------------------------------------------------------
+
+def logmatvec_nd(xr, xc, G, eps):
+    """eps ln (K e^{G/eps}) with K_a of rows xr[a] and columns xc[a].
+
+    G has shape (len(xc[0]), ..., len(xc[d-1])); the result has shape
+    (len(xr[0]), ..., len(xr[d-1])). Axis a is replaced by the 1D product
+    along it, one fibre at a time, for a = 0, 1, ..., d-1.
+    """
+    T = np.asarray(G, np.float64)
+    for a in range(len(xr)):
+        A = np.moveaxis(T, a, -1)
+        out = np.empty(A.shape[:-1] + (len(xr[a]),))
+        for idx in np.ndindex(*A.shape[:-1]):
+            out[idx] = logmatvec(xr[a], xc[a], A[idx], eps)
+        T = np.moveaxis(out, -1, a)
+    return T
+
+
+def _grid_points(axes):
+    """Coordinates of every grid point, in column-major order: (N, d)."""
+    mesh = np.meshgrid(*[np.asarray(a, np.float64) for a in axes], indexing="ij")
+    return np.stack([m.ravel(order="F") for m in mesh], axis=1)
+
+
+def cost_matrix_nd(xs, xt):
+    """C_rc = sum_a |p_r,a - q_c,a| between all source and target grid points."""
+    P, Q = _grid_points(xs), _grid_points(xt)
+    return np.sum(np.abs(P[:, None, :] - Q[None, :, :]), axis=2)
+
+
+def logmatvec_nd_full(xr, xc, G, eps):
+    """The same product through the full kernel (tiny sizes only)."""
+    c = cost_matrix_nd(xr, xc)
+    arg = (np.asarray(G, np.float64).ravel(order="F")[None, :] - c) / eps
+    return (eps * _lse_rows(arg)).reshape(tuple(len(a) for a in xr), order="F")
+
+
+def transport_cost_nd(xs, xt, F, G, eps) -> float:
+    """<C, Gamma> with C = sum_c |x_c - y_c|: for each axis c, the product
+    with the moment kernel C_c o K_c along c and K_a along the other axes,
+    summed against phi."""
+    F = np.asarray(F, np.float64)
+    tot = 0.0
+    for c in range(len(xs)):
+        T = np.asarray(G, np.float64)
+        for a in range(len(xs)):
+            A = np.moveaxis(T, a, -1)
+            out = np.empty(A.shape[:-1] + (len(xs[a]),))
+            mv = log_moment_matvec if a == c else logmatvec
+            for idx in np.ndindex(*A.shape[:-1]):
+                out[idx] = mv(xs[a], xt[a], A[idx], eps)
+            T = np.moveaxis(out, -1, a)
+        tot += float(np.sum(np.exp((F + T) / eps)))
+    return tot
+
+
+def transport_cost_nd_full(xs, xt, F, G, eps) -> float:
+    c = cost_matrix_nd(xs, xt)
+    f = np.asarray(F, np.float64).ravel(order="F")
+    g = np.asarray(G, np.float64).ravel(order="F")
+    return float(np.sum(c * np.exp((f[:, None] + g[None, :] - c) / eps)))
+
+
+def sinkhorn_nd(xs, xt, u, v, eps, tol, itr_max, full=False) -> SinkhornResult:
+    """The loop of Algorithms 1 and 2 on d-dimensional tensor meshes (log
+    form). u has shape (len(xs[0]), ...), v shape (len(xt[0]), ...).
+    Initialisation Phi = 1/|u|, Psi = 1/|v|; each pass updates Psi from
+    K^T Phi, then Phi from K Psi; the loop head checks the v marginal."""
+    u = np.asarray(u, np.float64); v = np.asarray(v, np.float64)
+    mv = logmatvec_nd_full if full else logmatvec_nd
+    F = np.full(u.shape, eps * np.log(1.0 / u.size))
+    G = np.full(v.shape, eps * np.log(1.0 / v.size))
+    lu, lv = eps * np.log(u), eps * np.log(v)
+    it = 0
+    while True:
+        T = mv(xt, xs, F, eps)                       # eps ln K^T phi, target grid
+        err = float(np.sum(np.abs(np.exp((G + T) / eps) - v)))
+        if not (it < itr_max and err > tol):
+            break
+        G = lv - T
+        S = mv(xs, xt, G, eps)                       # eps ln K psi, source grid
+        F = lu - S
+        it += 1
+    cost = (transport_cost_nd_full if full else transport_cost_nd)(xs, xt, F, G, eps)
+    return SinkhornResult(F, G, it, err, cost, err <= tol)

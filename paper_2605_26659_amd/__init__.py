@@ -11,5 +11,5 @@ from ._binding import (  # noqa: F401
     finom_version, load, sinkhorn_w1_1d, sinkhorn_w1_2d, strerror,
     FinomServer, finom_autotune, finom_batch, finom_footprint, finom_tile_config,
     problem_1d, problem_2d, with_outputs,
-    finom_plan_1d, finom_plan_2d, finom_plan_diff_1d, finom_plan_diff_2d,
+    finom_plan_1d, finom_plan_2d, finom_plan_diff_1d, finom_plan_diff_2d, sinkhorn_w1_nd,
 )

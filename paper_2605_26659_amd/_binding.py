@@ -7,6 +7,7 @@ given. If the library is not built, importing the entry points raises.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import re
 from pathlib import Path
@@ -122,6 +123,9 @@ def load(path: os.PathLike | None = None):
     if hasattr(L, "sinkhorn_w1_2d"):
         L.sinkhorn_w1_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _d, _d,
                                      _i64, C.POINTER(Opts), _vp, _vp, C.POINTER(Result), _vp]
+    L.sinkhorn_w1_nd.argtypes = [C.c_int32, C.POINTER(_i64), C.POINTER(_vp), C.POINTER(_i64),
+                                 C.POINTER(_vp), _vp, _vp, _d, _d, _i64, C.POINTER(Opts), _vp, _vp,
+                                 C.POINTER(Result), _vp]
     L.finom_plan_1d.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _d, _vp, _i64, _vp]
     L.finom_plan_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _d, _vp,
                                 _i64, _vp]
@@ -257,6 +261,36 @@ def sinkhorn_w1_2d(x1, y1, x2, y2, u, v, eps, tol, itr_max, *, precision=0, skip
                                _dev(g_out, "g_out") if g_out is not None else None,
                                C.byref(res), _stream_ptr(stream))
     _check(st, "sinkhorn_w1_2d")
+    return res.as_dict(), f_out, g_out
+
+
+def sinkhorn_w1_nd(x_src, x_tgt, u, v, eps, tol, itr_max, *, precision=0, skip_checks=False,
+                   graph_iters=0, f_out=None, g_out=None, want_potentials=True, stream=None):
+    """d-dimensional tensor meshes: x_src, x_tgt are sequences of d axis
+    coordinate tensors; u, v flat column-major grids (axis 0 fastest).
+    Returns (result, F, G) as flat column-major vectors."""
+    torch = _torch()
+    d = len(x_src)
+    if len(x_tgt) != d:
+        raise ValueError("x_src and x_tgt need the same number of axes")
+    ns = (_i64 * d)(*[t.numel() for t in x_src])
+    nt = (_i64 * d)(*[t.numel() for t in x_tgt])
+    ps = (_vp * d)(*[_dev(t, f"x_src[{i}]").value for i, t in enumerate(x_src)])
+    pt = (_vp * d)(*[_dev(t, f"x_tgt[{i}]").value for i, t in enumerate(x_tgt)])
+    na = math.prod(t.numel() for t in x_src)
+    nb = math.prod(t.numel() for t in x_tgt)
+    if want_potentials:
+        if f_out is None:
+            f_out = torch.empty(na, dtype=torch.float64, device=u.device)
+        if g_out is None:
+            g_out = torch.empty(nb, dtype=torch.float64, device=u.device)
+    res = Result()
+    st = load().sinkhorn_w1_nd(d, ns, ps, nt, pt, _dev(u, "u"), _dev(v, "v"), float(eps), float(tol),
+                               int(itr_max), C.byref(_opts(precision, 0, skip_checks, graph_iters)),
+                               _dev(f_out, "f_out") if f_out is not None else None,
+                               _dev(g_out, "g_out") if g_out is not None else None,
+                               C.byref(res), _stream_ptr(stream))
+    _check(st, "sinkhorn_w1_nd")
     return res.as_dict(), f_out, g_out
 
 

@@ -1298,6 +1298,220 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
     }
 }
 
+// ---------------------------------------------------------------------------
+// d-dimensional tensor meshes: the remark closing section 3 applies each
+// product axis by axis, the 1D method along every coordinate direction
+// ---------------------------------------------------------------------------
+int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, const int64_t* n_tgt,
+                   const double* const* x_tgt, const double* u, const double* v, double eps, double tol,
+                   int64_t itr_max, const finom_opts* opts, double* f_out, double* g_out, finom_result* res,
+                   void* stream)
+{
+    finom_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (!res) return FINOM_E_ARG;
+    memset(res, 0, sizeof(*res));
+    auto fail = [&](int st) {
+        res->status = st;
+        return st;
+    };
+    if (d < 1 || d > FINOM_MAX_DIMS || !n_src || !x_src || !n_tgt || !x_tgt || !u || !v) return fail(FINOM_E_ARG);
+    if (!finite_pos(eps) || !(tol >= 0.0) || !std::isfinite(tol) || itr_max < 0) return fail(FINOM_E_ARG);
+    if (o.precision != 0 && o.precision != 1) return fail(FINOM_E_ARG);
+    long long na = 1, nb = 1;
+    for (int a = 0; a < d; ++a) {
+        if (!x_src[a] || !x_tgt[a] || n_src[a] < 1 || n_tgt[a] < 1) return fail(FINOM_E_ARG);
+        if (n_src[a] + n_tgt[a] > INT32_MAX) return fail(FINOM_E_ARG);
+        if (n_src[a] > (1LL << 40) / na || n_tgt[a] > (1LL << 40) / nb) return fail(FINOM_E_ARG);
+        na *= n_src[a];
+        nb *= n_tgt[a];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        Alloc al(stream);
+        const int Tc = cost_tile_size();
+        const size_t eb = ext_bytes(o.precision);
+
+        int* dflag = al.dev<int>(4);
+        double* dsum = al.dev<double>(2);
+        double* lu = al.dev<double>(na);
+        double* lv = al.dev<double>(nb);
+        HIPCHK(hipMemsetAsync(dflag, 0, 4 * sizeof(int), s));
+        if (!o.skip_checks)
+            for (int a = 0; a < d; ++a) {
+                enqueue_sorted_check(x_src[a], n_src[a], dflag, s);
+                enqueue_sorted_check(x_tgt[a], n_tgt[a], dflag, s);
+            }
+        enqueue_log2_mass(u, na, lu, dflag + 1, s);
+        enqueue_log2_mass(v, nb, lv, dflag + 1, s);
+        enqueue_sum(al, u, na, dsum, s);
+        enqueue_sum(al, v, nb, dsum + 1, s);
+        if (!o.skip_checks) {
+            int st = read_checks(al, dflag, dsum);
+            if (st == FINOM_OK) {
+                const double* ms[2 * FINOM_MAX_DIMS];
+                long long ns[2 * FINOM_MAX_DIMS];
+                for (int a = 0; a < d; ++a) {
+                    ms[2 * a] = x_src[a];
+                    ns[2 * a] = n_src[a];
+                    ms[2 * a + 1] = x_tgt[a];
+                    ns[2 * a + 1] = n_tgt[a];
+                }
+                st = check_coord_range(al, ms, ns, 2 * d, eps);
+            }
+            if (st != FINOM_OK) return fail(st);
+        }
+
+        // per axis: K_a (rows source, columns target), K_a^T, and the cost partition
+        std::vector<int> cfg(d);
+        std::vector<Part> pk(d), pkt(d), pc(d);
+        for (int a = 0; a < d; ++a) {
+            cfg[a] = tuned_cfg(o.precision, n_src[a] + n_tgt[a]);
+            pk[a] = make_part(al, x_src[a], n_src[a], x_tgt[a], n_tgt[a], kCfgs[cfg[a]].T(), s);
+            pkt[a] = make_part_transposed(al, pk[a], s);
+            pc[a] = make_part_like(al, pk[a], Tc, s);
+        }
+
+        // Step a of a product maps a grid whose axes before a already have the
+        // output's sizes and whose axes from a on have the input's sizes to
+        // the grid with axis a replaced: `lead` points before the axis,
+        // `trail` after it. Intermediate grids alternate between two buffers.
+        auto step_shape = [&](bool to_target, int a, long long& lead, long long& trail) {
+            const int64_t* so = to_target ? n_tgt : n_src;
+            const int64_t* si = to_target ? n_src : n_tgt;
+            lead = 1;
+            trail = 1;
+            for (int q = 0; q < a; ++q) lead *= so[q];
+            for (int q = a + 1; q < d; ++q) trail *= si[q];
+        };
+        long long smax = 1;
+        for (int a = 0; a + 1 < d; ++a)
+            for (int dir = 0; dir < 2; ++dir) {
+                long long lead, trail;
+                step_shape(dir == 0, a, lead, trail);
+                smax = std::max(smax, lead * (dir == 0 ? n_tgt[a] : n_src[a]) * trail);
+            }
+        double* S[2] = {al.dev<double>(smax), al.dev<double>(smax)};
+        double* F = al.dev<double>(na);
+        double* G[2] = {al.dev<double>(nb), al.dev<double>(nb)};
+        enqueue_fill(F, na, -log2((double)na), s);
+        enqueue_fill(G[0], nb, -log2((double)nb), s);
+        ProbState* ps = al.dev<ProbState>(2);
+        ProbState* hps = al.host<ProbState>(2);
+        init_state(al, ps, hps, 2, itr_max, tol);
+
+        // Lines of step a: line (l, t) reads in[l + t lead n_in + i lead] and
+        // writes out[l + t lead n_out + i lead]; the epilogue operands of the
+        // last step are indexed as its output.
+        auto add_product = [&](Sweep* sw, bool to_target, const std::vector<Part>& parts, const double* in,
+                               double* out, const double* a0, const double* a1, const double* a2, int prob) {
+            for (int a = 0; a < d; ++a) {
+                long long lead, trail;
+                step_shape(to_target, a, lead, trail);
+                const long long nin = to_target ? n_src[a] : n_tgt[a];
+                const long long nout = to_target ? n_tgt[a] : n_src[a];
+                const bool last = a == d - 1;
+                const double* src = a == 0 ? in : S[(a - 1) & 1];
+                double* dst = last ? out : S[a & 1];
+                const Part& p = parts[a];
+                for (long long t = 0; t < trail; ++t)
+                    for (long long l = 0; l < lead; ++l) {
+                        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+                        const long long oi = l + t * lead * nin, oo = l + t * lead * nout;
+                        L.gin = src + oi;
+                        L.gstride = lead;
+                        L.out = dst ? dst + oo : nullptr;
+                        L.ostride = lead;
+                        if (last) {
+                            L.a0 = a0 ? a0 + oo : nullptr;
+                            L.a1 = a1 ? a1 + oo : nullptr;
+                            L.a2 = a2 ? a2 + oo : nullptr;
+                        }
+                        L.dec_part_off = -1;
+                        L.prob = prob;
+                        sw[a].lines.push_back(L);
+                    }
+            }
+        };
+
+        // K^T phi: every axis in turn from the source grid to the target grid,
+        // the last step with the psi update and the marginal check; K psi back,
+        // its first step taking the stop decision and its last the phi update
+        std::vector<Sweep> kt[2], kp[2];
+        int nchk = 0;
+        for (int b = 0; b < 2; ++b) {
+            kt[b].resize(d);
+            kp[b].resize(d);
+            for (int a = 0; a < d; ++a) {
+                kt[b][a].cfg = kp[b][a].cfg = cfg[a];
+                kt[b][a].epi = kp[b][a].epi = EPI_STORE_LOG2;
+            }
+            kt[b][d - 1].epi = EPI_UPDATE_CHECK;
+            kp[b][d - 1].epi = EPI_UPDATE;
+            add_product(kt[b].data(), true, pkt, F, G[1 - b], lv, v, G[b], 0);
+            nchk = assign_parts(kt[b][d - 1], 0);
+            add_product(kp[b].data(), false, pk, G[1 - b], F, lu, nullptr, nullptr, 0);
+        }
+        for (int b = 0; b < 2; ++b) {
+            set_decision(kp[b][0], 0, nchk);
+            for (int a = 0; a < d; ++a) upload_sweep(al, kt[b][a], eb);
+            for (int a = 0; a < d; ++a) upload_sweep(al, kp[b][a], eb);
+        }
+        long long lead_last, trail_last;
+        step_shape(false, d - 1, lead_last, trail_last);
+        const long long ncost = (long long)d * lead_last * pc[d - 1].ntiles;
+        double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
+        al.uploaded();
+
+        LoopSpec lp;
+        for (int b = 0; b < 2; ++b) {
+            for (int a = 0; a < d; ++a) {
+                lp.seq[b].push_back(&kt[b][a]);
+                lp.decides[b].push_back(false);
+            }
+            for (int a = 0; a < d; ++a) {
+                lp.seq[b].push_back(&kp[b][a]);
+                lp.decides[b].push_back(a == 0);
+            }
+        }
+        const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((na + nb) / 2);
+        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
+        if (st != FINOM_OK) return fail(st);
+
+        // <C, Gamma> with C = sum_c |x_c - y_c|: pass c is the product K psi
+        // with the moment kernel C_c o K_c along axis c, summed against phi
+        double* Gf = G[hps[0].iters & 1];
+        std::vector<Sweep> cs((size_t)d * d);
+        int nparts = 0;
+        for (int c = 0; c < d; ++c) {
+            Sweep* w = cs.data() + (size_t)c * d;
+            for (int a = 0; a < d; ++a) {
+                w[a].kind = a == c ? 2 : 1;
+                w[a].epi = a == d - 1 ? EPI_COST : EPI_STORE_LOG2;
+            }
+            add_product(w, false, pc, Gf, nullptr, F, nullptr, nullptr, 1);
+            nparts += assign_parts(w[d - 1], nparts);
+        }
+        for (auto& w : cs) upload_sweep(al, w, sizeof(Ext<double>));
+        al.uploaded();
+        for (auto& w : cs) launch_sweep(o.precision, IN_LOG2, w, ps, partial, nullptr, 0, s);
+        hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, partial, 0, nparts,
+                           &ps[1].w1);
+        if (f_out) enqueue_scale(F, f_out, na, eps * kLn2, s);
+        if (g_out) enqueue_scale(Gf, g_out, nb, eps * kLn2, s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        finish_result(res, hps[0], hps[1].w1);
+        res->sweeps = 2LL * d * hps[0].iters + d;
+        if (hps[0].status) return fail(FINOM_E_NUMERIC);
+        return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
+    } catch (...) {
+        return fail(map_exception());
+    }
+}
+
 const char* finom_strerror(int status)
 {
     switch (status) {

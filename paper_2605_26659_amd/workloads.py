@@ -193,6 +193,19 @@ def paper_random_2d(n: int, seed: int = seed_for(13), eps: float = 0.01,
     return Problem2D(x1, y1, x2, y2, u, v, eps, 0.0, iters, f"paper-random2d-{n}")
 
 
+def paper_random_nd(sizes_src, sizes_tgt, seed: int = seed_for(14), eps: float = 0.01,
+                    iters: int = 1000):
+    """Section 4.3's recipe in d dimensions (the remark closing section 3):
+    independent sorted U[0,1] node vectors per axis, masses U[0,1] normalised,
+    as column-major grids. Returns (source axes, target axes, u, v, eps, iters)."""
+    rng = rng_for(seed)
+    xs = [mesh_uniform_random(rng, k) for k in sizes_src]
+    xt = [mesh_uniform_random(rng, k) for k in sizes_tgt]
+    u = masses_uniform(rng, int(np.prod(sizes_src))).reshape(tuple(sizes_src), order="F")
+    v = masses_uniform(rng, int(np.prod(sizes_tgt))).reshape(tuple(sizes_tgt), order="F")
+    return xs, xt, u, v, eps, iters
+
+
 # --------------------------------------------------------------------------
 # throughput / correctness configurations
 # --------------------------------------------------------------------------

@@ -444,3 +444,64 @@ def test_plan_difference_closed_forms():
     Pb = dense.plan_1d(x, y, f + delta, g, eps)
     ref = abs(1.0 - np.exp(delta / eps)) * np.sqrt(np.sum(Pa * Pa))
     assert abs(dense.plan_difference(Pa, Pb) - ref) <= 1e-12 * ref
+
+
+# ----------------------------------------------------------------------------
+# d dimensions (the remark closing section 3)
+# ----------------------------------------------------------------------------
+
+def _axes(rng, sizes):
+    return [np.sort(rng.uniform(0, 1, k)) for k in sizes]
+
+
+def test_nd_reduces_to_1d_and_2d():
+    rng = np.random.default_rng(41)
+    x, y = _axes(rng, (30, 25))
+    u, v = wl.normalise(rng.uniform(.1, 1, 30)), wl.normalise(rng.uniform(.1, 1, 25))
+    r1 = dense.sinkhorn_1d(x, y, u, v, 0.03, 0.0, 20)
+    rn = dense.sinkhorn_nd([x], [y], u, v, 0.03, 0.0, 20)
+    assert rn.iters == r1.iters == 20
+    np.testing.assert_allclose(rn.f, r1.f, rtol=0, atol=1e-15)
+    assert abs(rn.w1 - r1.w1) <= 1e-15
+    p = wl.paper_random_2d(7, seed=43)
+    r2 = dense.sinkhorn_2d(p.x1, p.y1, p.x2, p.y2, p.u, p.v, 0.05, 0.0, 15)
+    rn = dense.sinkhorn_nd([p.x1, p.y1], [p.x2, p.y2], p.u, p.v, 0.05, 0.0, 15)
+    np.testing.assert_allclose(rn.f, r2.f, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(rn.g, r2.g, rtol=0, atol=1e-15)
+    assert abs(rn.w1 - r2.w1) <= 1e-14 * r2.w1
+
+
+def test_nd_axis_by_axis_equals_full_kernel():
+    """d = 3: the product axis by axis equals the product with the full
+    kernel exp(-sum_a |dx_a| / eps), and so do the iterates and the cost."""
+    rng = np.random.default_rng(44)
+    xs, xt = _axes(rng, (3, 4, 2)), _axes(rng, (4, 2, 3))
+    eps = 0.05
+    G = eps * rng.normal(0, 5, (4, 2, 3))
+    full = dense.logmatvec_nd_full(xs, xt, G, eps)
+    axis = dense.logmatvec_nd(xs, xt, G, eps)
+    assert full.shape == (3, 4, 2)
+    assert np.max(np.abs(full - axis)) / eps <= 1e-12
+    u = wl.normalise(rng.uniform(.1, 1, (3, 4, 2))); v = wl.normalise(rng.uniform(.1, 1, (4, 2, 3)))
+    ra = dense.sinkhorn_nd(xs, xt, u, v, eps, 0.0, 12)
+    rf = dense.sinkhorn_nd(xs, xt, u, v, eps, 0.0, 12, full=True)
+    assert np.max(np.abs(ra.f - rf.f)) / eps <= 1e-11
+    assert abs(ra.w1 - rf.w1) <= 1e-12 * rf.w1
+
+
+def test_nd_product_measures_factorise():
+    """u and v products over three axes: the iterate is the sum of the three
+    1D potentials and <C, Gamma> the sum of the three 1D costs."""
+    rng = np.random.default_rng(45)
+    xs, xt = _axes(rng, (6, 5, 4)), _axes(rng, (5, 7, 3))
+    us = [wl.normalise(rng.uniform(.1, 1, len(a))) for a in xs]
+    vs = [wl.normalise(rng.uniform(.1, 1, len(a))) for a in xt]
+    eps, L = 0.05, 9
+    r = [dense.sinkhorn_1d(xs[a], xt[a], us[a], vs[a], eps, 0.0, L) for a in range(3)]
+    u = np.einsum("i,j,k->ijk", *us); v = np.einsum("i,j,k->ijk", *vs)
+    rn = dense.sinkhorn_nd(xs, xt, u, v, eps, 0.0, L)
+    F = r[0].f[:, None, None] + r[1].f[None, :, None] + r[2].f[None, None, :]
+    G = r[0].g[:, None, None] + r[1].g[None, :, None] + r[2].g[None, None, :]
+    np.testing.assert_allclose(rn.f, F, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(rn.g, G, rtol=0, atol=1e-13)
+    assert abs(rn.w1 - sum(x.w1 for x in r)) <= 1e-13
