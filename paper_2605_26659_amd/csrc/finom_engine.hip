@@ -198,11 +198,16 @@ __global__ __launch_bounds__(kBlock) void k_segment_sums(const double* __restric
     if (threadIdx.x == 0) *t.out = v;
 }
 
+// b = f a over n elements. mode 0: same layout; mode 1: a is a column-major
+// grid of `rows` rows, b receives it row-major; mode 2: a is row-major, b
+// receives it column-major.
 struct ScaleTask {
     const double* a;
     double* b;
     long long n;
     double f;
+    long long rows;
+    int mode;
 };
 
 __global__ __launch_bounds__(kBlock) void k_scale_tasks(const ScaleTask* __restrict__ tasks,
@@ -212,7 +217,18 @@ __global__ __launch_bounds__(kBlock) void k_scale_tasks(const ScaleTask* __restr
     const ScaleTask t = tasks[ti];
     const int lb = blockIdx.x - first[ti];
     const long long stride = (long long)(first[ti + 1] - first[ti]) * kBlock;
-    for (long long k = (long long)lb * kBlock + threadIdx.x; k < t.n; k += stride) t.b[k] = t.a[k] * t.f;
+    const long long cols = t.rows > 0 ? t.n / t.rows : 0;
+    for (long long k = (long long)lb * kBlock + threadIdx.x; k < t.n; k += stride) {
+        long long src = k;
+        if (t.mode == 1) {
+            const long long l = k / cols;
+            src = l + (k - l * cols) * t.rows;
+        } else if (t.mode == 2) {
+            const long long j = k / t.rows;
+            src = j + (k - j * t.rows) * cols;
+        }
+        t.b[k] = t.a[src] * t.f;
+    }
 }
 
 // blocks given to a task of n elements (at least one, at most 1024)
@@ -306,14 +322,18 @@ JobPlan plan_job(const JobDesc& d, int precision)
         p.C[1] = d.m2;
         p.na = d.n1 * d.m1;
         p.nb = d.n2 * d.m2;
-        p.s_len = std::max(d.n2 * d.m1, d.n1 * d.m2);
+        p.s_len = d.n2 * d.m1;
     }
     p.o_lu = take(8 * p.na);
     p.o_lv = take(8 * p.nb);
     p.o_F = take(8 * p.na);
     p.o_G0 = take(8 * p.nb);
     p.o_G1 = take(8 * p.nb);
-    if (d.dim == 2) p.o_S = take(8 * p.s_len);
+    if (d.dim == 2) {
+        p.o_S = take(8 * p.s_len);
+        p.o_lvr = take(8 * p.nb);
+        p.o_vr = take(8 * p.nb);
+    }
     if (d.dim == 1 && precision == 1) {
         p.o_Bx = take(sizeof(Ext<float>) * p.na);
         p.o_By = take(sizeof(Ext<float>) * p.nb);
@@ -341,6 +361,8 @@ void Job::bind()
     G[0] = (double*)(mem + p.o_G0);
     G[1] = (double*)(mem + p.o_G1);
     S = d.dim == 2 ? (double*)(mem + p.o_S) : nullptr;
+    lvr = d.dim == 2 ? (double*)(mem + p.o_lvr) : nullptr;
+    vr = d.dim == 2 ? (double*)(mem + p.o_vr) : nullptr;
     Bx = p.o_Bx ? (Ext<float>*)(mem + p.o_Bx) : nullptr;
     By = p.o_By ? (Ext<float>*)(mem + p.o_By) : nullptr;
     const int Tc = cost_tile_size();
@@ -497,6 +519,23 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
     hipLaunchKernelGGL(k_setup_zeta, dim3(fz.back()), dim3(kBlock), 0, s_, d_pt, d_fz, 2 * npt);
     hipLaunchKernelGGL(k_setup_tiles, dim3(ft.back()), dim3(kBlock), 0, s_, d_pt, d_ft, npt);
     HIPCHK(hipGetLastError());
+    // 2D: the target masses and their logs row-major, as psi
+    std::vector<ScaleTask> tr;
+    std::vector<long long> tr_n;
+    for (Job* j : jobs)
+        if (j->d.dim == 2) {
+            tr.push_back(ScaleTask{j->lv, j->lvr, j->p.nb, 1.0, j->d.n2, 1});
+            tr.push_back(ScaleTask{j->d.v, j->vr, j->p.nb, 1.0, j->d.n2, 1});
+            tr_n.push_back(j->p.nb);
+            tr_n.push_back(j->p.nb);
+        }
+    if (!tr.empty()) {
+        const std::vector<int> fr = prefix_blocks(tr_n);
+        const ScaleTask* d_tr = upload_vec(al, tr);
+        const int* d_fr = upload_vec(al, fr);
+        hipLaunchKernelGGL(k_scale_tasks, dim3(fr.back()), dim3(kBlock), 0, s_, d_tr, d_fr, (int)tr.size());
+        HIPCHK(hipGetLastError());
+    }
     // fast-sweep eligibility of the 1D jobs (the static range bound of every tile)
     std::vector<BoundTask> bt;
     std::vector<long long> bt_n;
@@ -730,7 +769,8 @@ void Engine::maybe_compact(double keep_fraction)
 
 namespace {
 // stages of one iteration, in launch order
-enum Stage { S1_KT = 0, S1_K = 1, S2_KTX = 2, S2_KTY = 3, S2_KX = 4, S2_KY = 5, NSTAGE = 6 };
+// 2D: K^T phi along x then y, K psi along y then x (psi row-major)
+enum Stage { S1_KT = 0, S1_K = 1, S2_KTX = 2, S2_KTY = 3, S2_KY = 4, S2_KX = 5, NSTAGE = 6 };
 constexpr int kStageEpi[NSTAGE] = {EPI_UPDATE_CHECK, EPI_UPDATE, EPI_STORE_LOG2, EPI_UPDATE_CHECK, EPI_STORE_LOG2,
                                    EPI_UPDATE};
 
@@ -840,16 +880,15 @@ void Engine::rebuild()
             const long long n1 = d.n1, m1 = d.m1, n2 = d.n2, m2 = d.m2;
             const int sx = j->p.ntiles[0] > 1 ? 1 : 0, sy = j->p.ntiles[1] > 1 ? 1 : 0;
             const int gtx = group(S2_KTX, j->p.cfg[0], sx), gty = group(S2_KTY, j->p.cfg[1], sy);
-            const int gx = group(S2_KX, j->p.cfg[0], sx), gy = group(S2_KY, j->p.cfg[1], sy);
+            const int gy = group(S2_KY, j->p.cfg[1], sy), gx = group(S2_KX, j->p.cfg[0], sx);
             chk[ji] = LineRange{gty, groups[gty].sw[0]->lines.size(), (size_t)n2};
-            dcd[ji] = LineRange{gx, groups[gx].sw[0]->lines.size(), (size_t)m2};
+            dcd[ji] = LineRange{gy, groups[gy].sw[0]->lines.size(), (size_t)n2};
             for (int b = 0; b < 2; ++b) {
                 add_axis0_lines(*groups[gtx].sw[b], j->pkt[0], eps, j->F, n1, j->S, n2, m1, j->slot);
-                add_axis1_lines(*groups[gty].sw[b], j->pkt[1], eps, j->S, j->G[1 - b], n2, j->lv, d.v, j->G[b],
-                                j->slot);
-                add_axis0_lines(*groups[gx].sw[b], j->pk[0], eps, j->G[1 - b], n2, j->S, n1, m2, j->slot);
-                add_axis1_lines(*groups[gy].sw[b], j->pk[1], eps, j->S, j->F, n1, j->lu, nullptr, nullptr,
-                                j->slot);
+                add_2d_kt_y_lines(*groups[gty].sw[b], j->pkt[1], eps, j->S, n2, j->G[1 - b], m2, j->lvr, j->vr,
+                                  j->G[b], j->slot);
+                add_2d_k_y_lines(*groups[gy].sw[b], j->pk[1], eps, j->G[1 - b], m2, j->S, m1, n2, j->slot);
+                add_2d_k_x_lines(*groups[gx].sw[b], j->pk[0], eps, j->S, m1, j->F, n1, j->lu, j->slot);
             }
         }
     }
@@ -919,7 +958,7 @@ void Engine::rebuild()
     for (int b = 0; b < 2; ++b)
         for (int gi : order) {
             seq_[b].push_back(groups[gi].sw[b]);
-            dec_[b].push_back(groups[gi].stage == S1_K || groups[gi].stage == S2_KX);
+            dec_[b].push_back(groups[gi].stage == S1_K || groups[gi].stage == S2_KY);
         }
     dirty_ = false;
     stable_ = 0;
@@ -985,14 +1024,14 @@ std::vector<Job*> Engine::harvest()
     Sweep kc, cx_m, cy_p, cx_p, cy_m;
     kc.kind = 2;
     kc.epi = EPI_COST;
-    cx_m.kind = 2;
-    cx_m.epi = EPI_STORE_LOG2;
     cy_p.kind = 1;
-    cy_p.epi = EPI_COST;
-    cx_p.kind = 1;
-    cx_p.epi = EPI_STORE_LOG2;
+    cy_p.epi = EPI_STORE_LOG2;
+    cx_m.kind = 2;
+    cx_m.epi = EPI_COST;
     cy_m.kind = 2;
-    cy_m.epi = EPI_COST;
+    cy_m.epi = EPI_STORE_LOG2;
+    cx_p.kind = 1;
+    cx_p.epi = EPI_COST;
     std::vector<SegTask> segs;
     std::vector<ScaleTask> sc;
     std::vector<long long> sc_n;
@@ -1027,34 +1066,35 @@ std::vector<Job*> Engine::harvest()
             P += c.ntiles;
             kc.lines.push_back(c);
         } else {
-            // <C, Gamma> = sum Phi o (M_x Psi K_y^T) + sum Phi o (K_x Psi M_y^T), M = C o K
-            add_axis0_lines(cx_m, j->pc[0], eps, Gf, d.n2, j->S, d.n1, d.m2, dummy);
-            size_t q0 = cy_p.lines.size();
-            add_axis1_lines(cy_p, j->pc[1], eps, j->S, nullptr, d.n1, j->F, nullptr, nullptr, dummy);
-            for (size_t q = q0; q < cy_p.lines.size(); ++q) {
-                cy_p.lines[q].part_base = P;
-                P += cy_p.lines[q].ntiles;
+            // <C, Gamma> = sum Phi o (M_x Psi K_y^T) + sum Phi o (K_x Psi M_y^T), M = C o K,
+            // each product along y first, as in the loop
+            add_2d_k_y_lines(cy_p, j->pc[1], eps, Gf, d.m2, j->S, d.m1, d.n2, dummy);
+            size_t q0 = cx_m.lines.size();
+            add_2d_k_x_lines(cx_m, j->pc[0], eps, j->S, d.m1, nullptr, d.n1, j->F, dummy);
+            for (size_t q = q0; q < cx_m.lines.size(); ++q) {
+                cx_m.lines[q].part_base = P;
+                P += cx_m.lines[q].ntiles;
             }
-            add_axis0_lines(cx_p, j->pc[0], eps, Gf, d.n2, j->S, d.n1, d.m2, dummy);
-            q0 = cy_m.lines.size();
-            add_axis1_lines(cy_m, j->pc[1], eps, j->S, nullptr, d.n1, j->F, nullptr, nullptr, dummy);
-            for (size_t q = q0; q < cy_m.lines.size(); ++q) {
-                cy_m.lines[q].part_base = P;
-                P += cy_m.lines[q].ntiles;
+            add_2d_k_y_lines(cy_m, j->pc[1], eps, Gf, d.m2, j->S, d.m1, d.n2, dummy);
+            q0 = cx_p.lines.size();
+            add_2d_k_x_lines(cx_p, j->pc[0], eps, j->S, d.m1, nullptr, d.n1, j->F, dummy);
+            for (size_t q = q0; q < cx_p.lines.size(); ++q) {
+                cx_p.lines[q].part_base = P;
+                P += cx_p.lines[q].ntiles;
             }
         }
         segs.push_back(SegTask{base, P - base, &ps_[j->slot].w1});
         if (d.f_out) {
-            sc.push_back(ScaleTask{j->F, d.f_out, j->p.na, eps * kLn2});
+            sc.push_back(ScaleTask{j->F, d.f_out, j->p.na, eps * kLn2, 0, 0});
             sc_n.push_back(j->p.na);
         }
         if (d.g_out) {
-            sc.push_back(ScaleTask{Gf, d.g_out, j->p.nb, eps * kLn2});
+            sc.push_back(ScaleTask{Gf, d.g_out, j->p.nb, eps * kLn2, d.dim == 2 ? d.n2 : 0, d.dim == 2 ? 2 : 0});
             sc_n.push_back(j->p.nb);
         }
     }
     double* partial = al.dev<double>(std::max(P, 1));
-    Sweep* order[5] = {&kc, &cx_m, &cy_p, &cx_p, &cy_m};
+    Sweep* order[5] = {&kc, &cy_p, &cx_m, &cy_m, &cx_p};
     for (Sweep* c : order)
         if (!c->lines.empty()) upload_sweep(al, *c, sizeof(Ext<double>));
     const SegTask* d_segs = upload_vec(al, segs);

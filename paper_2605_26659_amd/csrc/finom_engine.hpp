@@ -36,6 +36,7 @@ struct JobPlan {
     long long R[2] = {0, 0}, C[2] = {0, 0};
     int ntiles[2] = {0, 0}, ntiles_c[2] = {0, 0};
     size_t o_lu = 0, o_lv = 0, o_F = 0, o_G0 = 0, o_G1 = 0, o_S = 0, o_Bx = 0, o_By = 0;
+    size_t o_lvr = 0, o_vr = 0;   // 2D: log2 v and v row-major, as psi
     size_t o_zeta[2] = {0, 0}, o_zeta_t[2] = {0, 0}, o_trs[2] = {0, 0}, o_trs_t[2] = {0, 0},
            o_trs_c[2] = {0, 0};
     size_t bytes = 0;
@@ -56,6 +57,8 @@ struct Job {
     // masses as Ext<float> in lu / lv and the state U = w 2^{-c kappa} in F / G
     // until they are harvested.
     double *lu = nullptr, *lv = nullptr, *F = nullptr, *G[2] = {nullptr, nullptr}, *S = nullptr;
+    double *lvr = nullptr, *vr = nullptr;   // 2D: psi is row-major (element (l, j) at j + l m2), and so
+                                            // are these copies of log2 v and v that its check reads
     Ext<float>* Bx = nullptr;   // 1D FP32: 2^{2 x kappa} and 2^{2 y kappa} for the fast sweeps
     Ext<float>* By = nullptr;
     bool fast = false;          // runs on the fast sweeps

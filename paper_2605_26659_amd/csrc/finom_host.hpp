@@ -365,6 +365,98 @@ inline void add_axis1_lines(Sweep& sw, const Part& p, double eps, const double* 
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2D solves keep psi (and the target-side masses the check reads) row-major,
+// element (l, j) of the n2 x m2 target grid at j + l m2, while phi stays
+// column-major (k + i n1). Each product then has at most one strided stream
+// per sweep: K^T phi runs along x (contiguous columns of phi into the n2 x m1
+// column-major intermediate) and then along y (strided rows of the
+// intermediate into contiguous rows of psi); K psi runs along y first
+// (contiguous rows of psi into the row-major n2 x m1 intermediate) and then
+// along x (strided columns of the intermediate into contiguous columns of
+// phi). The products along the two axes commute (eq. 2d-kpsi).
+// ---------------------------------------------------------------------------
+
+// K^T phi, along y: line l (< n2) reads row l of S (stride n2) and writes row
+// l of psi (contiguous, m2 points); the epilogue operands are indexed as psi.
+inline void add_2d_kt_y_lines(Sweep& sw, const Part& p, double eps, const double* S, long long n2,
+                              double* G, long long m2, const double* a0, const double* a1, const double* a2,
+                              int prob = 0)
+{
+    for (long long l = 0; l < n2; ++l) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = S + l;
+        L.gstride = n2;
+        L.out = G + l * m2;
+        L.a0 = a0 ? a0 + l * m2 : nullptr;
+        L.a1 = a1 ? a1 + l * m2 : nullptr;
+        L.a2 = a2 ? a2 + l * m2 : nullptr;
+        L.dec_part_off = -1;
+        L.prob = prob;
+        sw.lines.push_back(L);
+    }
+}
+
+// K psi, along y: line l (< n2) reads row l of psi (contiguous, m2 points)
+// and writes row l of the row-major n2 x m1 intermediate.
+inline void add_2d_k_y_lines(Sweep& sw, const Part& p, double eps, const double* G, long long m2, double* S,
+                             long long m1, long long n2, int prob = 0)
+{
+    for (long long l = 0; l < n2; ++l) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = G + l * m2;
+        L.out = S + l * m1;
+        L.dec_part_off = -1;
+        L.prob = prob;
+        sw.lines.push_back(L);
+    }
+}
+
+// K psi, along x: line i (< m1) reads column i of the row-major intermediate
+// (stride m1) and writes column i of phi (contiguous, n1 points), or only
+// reads phi there (a0) when out is NULL (the cost sweeps).
+inline void add_2d_k_x_lines(Sweep& sw, const Part& p, double eps, const double* S, long long m1, double* F,
+                             long long n1, const double* a0, int prob = 0)
+{
+    for (long long i = 0; i < m1; ++i) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = S + i;
+        L.gstride = m1;
+        L.out = F ? F + i * n1 : nullptr;
+        L.a0 = a0 ? a0 + i * n1 : nullptr;
+        L.dec_part_off = -1;
+        L.prob = prob;
+        sw.lines.push_back(L);
+    }
+}
+
+// b = f a, with a's (rows x cols) column-major grid written row-major
+// (to_rows) or a's row-major grid written column-major (!to_rows).
+template <int = 0>
+__global__ __launch_bounds__(kBlock) void k_transpose_scale(const double* __restrict__ a, double* __restrict__ b,
+                                                            long long rows, long long cols, int to_rows, double f)
+{
+    const long long n = rows * cols;
+    for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < n; k += (long long)gridDim.x * kBlock) {
+        if (to_rows) {
+            const long long l = k / cols, j = k - l * cols;   // b[j + l cols] = a[l + j rows]
+            b[k] = a[l + j * rows] * f;
+        } else {
+            const long long j = k / rows, l = k - j * rows;   // b[l + j rows] = a[j + l cols]
+            b[k] = a[j + l * cols] * f;
+        }
+    }
+}
+
+inline void enqueue_transpose_scale(const double* a, double* b, long long rows, long long cols, bool to_rows,
+                                    double f, hipStream_t s)
+{
+    const long long n = rows * cols;
+    const unsigned grid = (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_transpose_scale<0>, dim3(std::max(1u, grid)), dim3(kBlock), 0, s, a, b, rows, cols,
+                       to_rows ? 1 : 0, f);
+}
+
 // Partial-slot layout of a checking / cost sweep: consecutive per line.
 inline int assign_parts(Sweep& sw, int base)
 {

@@ -1215,77 +1215,83 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         const Part pxc = make_part_like(al, px, Tc, s);
         const Part pyc = make_part_like(al, py, Tc, s);
 
+        // phi column-major; psi, log2 v and v row-major (element (l, j) at j + l m2)
         double* F = al.dev<double>(na);
         double* G[2] = {al.dev<double>(nb), al.dev<double>(nb)};
-        double* S = al.dev<double>(std::max((long long)n2 * m1, (long long)n1 * m2));
+        double* S = al.dev<double>((long long)n2 * m1);
+        double* lvr = al.dev<double>(nb);
+        double* vr = al.dev<double>(nb);
+        enqueue_transpose_scale(lv, lvr, n2, m2, true, 1.0, s);
+        enqueue_transpose_scale(v, vr, n2, m2, true, 1.0, s);
         enqueue_fill(F, na, -log2((double)na), s);
         enqueue_fill(G[0], nb, -log2((double)nb), s);
         ProbState* ps = al.dev<ProbState>(2);
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
 
-        Sweep ktx[2], kty[2], kx[2], ky[2];
+        Sweep ktx[2], kty[2], ky[2], kx[2];
         int nchk = 0;
         for (int b = 0; b < 2; ++b) {
             ktx[b].cfg = kx[b].cfg = cfg_x;
             kty[b].cfg = ky[b].cfg = cfg_y;
-            // K^T phi = vec(K_x^T Phi K_y): S = K_x^T Phi (columns), T = S K_y (rows)
+            // K^T phi = vec(K_x^T Phi K_y): S = K_x^T Phi (columns), then S K_y (rows of S into rows of psi)
             ktx[b].epi = EPI_STORE_LOG2;
             add_axis0_lines(ktx[b], px_t, eps, F, n1, S, n2, m1);
             kty[b].epi = EPI_UPDATE_CHECK;
-            add_axis1_lines(kty[b], py_t, eps, S, G[1 - b], n2, lv, v, G[b]);
+            add_2d_kt_y_lines(kty[b], py_t, eps, S, n2, G[1 - b], m2, lvr, vr, G[b]);
             nchk = assign_parts(kty[b], 0);
-            // K psi = vec(K_x Psi K_y^T): S = K_x Psi (columns), T = S K_y^T (rows)
-            kx[b].epi = EPI_STORE_LOG2;
-            add_axis0_lines(kx[b], px, eps, G[1 - b], n2, S, n1, m2);
-            ky[b].epi = EPI_UPDATE;
-            add_axis1_lines(ky[b], py, eps, S, F, n1, lu, nullptr, nullptr);
+            // K psi = vec(K_x Psi K_y^T): S = Psi K_y^T (rows of psi), then K_x S (columns into phi)
+            ky[b].epi = EPI_STORE_LOG2;
+            add_2d_k_y_lines(ky[b], py, eps, G[1 - b], m2, S, m1, n2);
+            kx[b].epi = EPI_UPDATE;
+            add_2d_k_x_lines(kx[b], px, eps, S, m1, F, n1, lu);
         }
         for (int b = 0; b < 2; ++b) {
-            set_decision(kx[b], 0, nchk);
+            set_decision(ky[b], 0, nchk);
             upload_sweep(al, ktx[b], eb);
             upload_sweep(al, kty[b], eb);
-            upload_sweep(al, kx[b], eb);
             upload_sweep(al, ky[b], eb);
+            upload_sweep(al, kx[b], eb);
         }
-        const long long ncost = 2LL * n1 * pyc.ntiles;
+        const long long ncost = 2LL * m1 * pxc.ntiles;
         double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
         al.uploaded();
 
         LoopSpec lp;
         for (int b = 0; b < 2; ++b) {
-            lp.seq[b] = {&ktx[b], &kty[b], &kx[b], &ky[b]};
+            lp.seq[b] = {&ktx[b], &kty[b], &ky[b], &kx[b]};
             lp.decides[b] = {false, false, true, false};
         }
         const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((na + nb) / 2);
         const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
         if (st != FINOM_OK) return fail(st);
 
-        // <C, Gamma> = sum Phi o (M_x Psi K_y^T) + sum Phi o (K_x Psi M_y^T), M = C o K
+        // <C, Gamma> = sum Phi o (M_x Psi K_y^T) + sum Phi o (K_x Psi M_y^T), M = C o K,
+        // each product along y first, as in the loop
         double* Gf = G[hps[0].iters & 1];
-        Sweep cx_m, cy_p, cx_p, cy_m;
-        cx_m.kind = 2; cx_m.epi = EPI_STORE_LOG2;
-        add_axis0_lines(cx_m, pxc, eps, Gf, n2, S, n1, m2);
-        cy_p.kind = 1; cy_p.epi = EPI_COST;
-        add_axis1_lines(cy_p, pyc, eps, S, nullptr, n1, F, nullptr, nullptr);
-        cx_p.kind = 1; cx_p.epi = EPI_STORE_LOG2;
-        add_axis0_lines(cx_p, pxc, eps, Gf, n2, S, n1, m2);
-        cy_m.kind = 2; cy_m.epi = EPI_COST;
-        add_axis1_lines(cy_m, pyc, eps, S, nullptr, n1, F, nullptr, nullptr);
-        for (Sweep* c : {&cx_m, &cy_p, &cx_p, &cy_m})
+        Sweep cy_p, cx_m, cy_m, cx_p;
+        cy_p.kind = 1; cy_p.epi = EPI_STORE_LOG2;
+        add_2d_k_y_lines(cy_p, pyc, eps, Gf, m2, S, m1, n2);
+        cx_m.kind = 2; cx_m.epi = EPI_COST;
+        add_2d_k_x_lines(cx_m, pxc, eps, S, m1, nullptr, n1, F);
+        cy_m.kind = 2; cy_m.epi = EPI_STORE_LOG2;
+        add_2d_k_y_lines(cy_m, pyc, eps, Gf, m2, S, m1, n2);
+        cx_p.kind = 1; cx_p.epi = EPI_COST;
+        add_2d_k_x_lines(cx_p, pxc, eps, S, m1, nullptr, n1, F);
+        for (Sweep* c : {&cy_p, &cx_m, &cy_m, &cx_p})
             for (auto& L : c->lines) L.prob = 1;
-        const int n_a = assign_parts(cy_p, 0);
-        const int n_b = assign_parts(cy_m, n_a);
-        for (Sweep* c : {&cx_m, &cy_p, &cx_p, &cy_m}) upload_sweep(al, *c, sizeof(Ext<double>));
+        const int n_a = assign_parts(cx_m, 0);
+        const int n_b = assign_parts(cx_p, n_a);
+        for (Sweep* c : {&cy_p, &cx_m, &cy_m, &cx_p}) upload_sweep(al, *c, sizeof(Ext<double>));
         al.uploaded();
-        launch_sweep(o.precision, IN_LOG2, cx_m, ps, partial, nullptr, 0, s);
         launch_sweep(o.precision, IN_LOG2, cy_p, ps, partial, nullptr, 0, s);
-        launch_sweep(o.precision, IN_LOG2, cx_p, ps, partial, nullptr, 0, s);
+        launch_sweep(o.precision, IN_LOG2, cx_m, ps, partial, nullptr, 0, s);
         launch_sweep(o.precision, IN_LOG2, cy_m, ps, partial, nullptr, 0, s);
+        launch_sweep(o.precision, IN_LOG2, cx_p, ps, partial, nullptr, 0, s);
         hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, partial, 0,
                            n_a + n_b, &ps[1].w1);
         if (f_out) enqueue_scale(F, f_out, na, eps * kLn2, s);
-        if (g_out) enqueue_scale(Gf, g_out, nb, eps * kLn2, s);
+        if (g_out) enqueue_transpose_scale(Gf, g_out, n2, m2, false, eps * kLn2, s);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

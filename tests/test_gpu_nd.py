@@ -60,10 +60,11 @@ def test_nd_d1_and_d2_match_the_1d_and_2d_entry_points():
                                 dev(p.v.ravel(order="F")), p.eps, 0.0, 30)
     rn, Fn, Gn = _solve([p.x1, p.y1], [p.x2, p.y2], p.u, p.v, p.eps, 0.0, 30)
     assert rn["iters"] == r2["iters"] == 30
-    # the same sweeps in the same order: the same bits
-    assert np.array_equal(Fn.ravel(order="F"), host(F2))
-    assert np.array_equal(Gn.ravel(order="F"), host(G2))
-    assert rn["w1"] == r2["w1"]
+    # the same sums, with K psi's two axes applied in the other order (the 2D
+    # entry point keeps psi row-major and runs y first): rounding differs
+    assert np.max(np.abs(Fn.ravel(order="F") - host(F2))) / p.eps <= 1e-11
+    assert np.max(np.abs(Gn.ravel(order="F") - host(G2))) / p.eps <= 1e-11
+    assert abs(rn["w1"] - r2["w1"]) <= 1e-12 * r2["w1"]
 
 
 def test_nd_fp32_to_convergence():
