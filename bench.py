@@ -104,6 +104,8 @@ def parse():
                     help="full serving sweep (several arrival rates and the nominal 2000/s)")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving sample")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tanh-2d-only", action="store_true",
+                    help="only the 2D 1024 x 1024 tanh-mesh record (one warm-up and one timed solve)")
     ap.add_argument("--plan-only", action="store_true",
                     help="only the plan export / plan difference record (--steps launches each)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2605_26659_amd", "tune_gfx950.txt"),
@@ -209,13 +211,36 @@ def bench_batch(precision):
     return out
 
 
+def bench_tanh_2d(precision):
+    """The 2D 1024 x 1024 tanh-mesh workload (eps = 5e-3, tol 1e-6): one timed
+    solve after a warm-up."""
+    import torch
+    from paper_2605_26659_amd import sinkhorn_w1_2d, workloads as wl
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    p = wl.config_tanh_2d(1024)
+    args2 = (dev(p.x1), dev(p.y1), dev(p.x2), dev(p.y2), dev(p.u.ravel(order="F")),
+             dev(p.v.ravel(order="F")), p.eps, p.tol, p.itr_max)
+    sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, _, _ = sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
+    dt = time.perf_counter() - t0
+    return {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s",
+            "solve_ms": dt * 1e3, "iters": r["iters"], "w1": r["w1"],
+            "marginal_err": r["marginal_err"], "converged": r["converged"],
+            "loop_ms": r["loop_ms"], "iteration_us": r["loop_ms"] * 1e3 / max(1, r["iters"]),
+            "scan_mantissa": "fp32" if precision == 1 else "fp64",
+            "workload": "1024 x 1024 tanh mesh (beta 2.5), 4-component 2D GMM masses, "
+                        "eps=5e-3, tol=1e-6"}
+
+
 def bench_other_configs(precision):
     """The other single-problem configurations, one timed solve each after a
     warm-up: the headline workload on the streaming sweeps, the small 1D
     correctness case (FP64 scans, tol 1e-9, cap 2000), the graded 1D workload
     at eps = 1e-2, and the 2D 1024 x 1024 tanh mesh (eps = 5e-3, tol 1e-6)."""
     import torch
-    from paper_2605_26659_amd import sinkhorn_w1_1d, sinkhorn_w1_2d, workloads as wl
+    from paper_2605_26659_amd import sinkhorn_w1_1d, workloads as wl
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     out = {}
 
@@ -258,21 +283,7 @@ def bench_other_configs(precision):
     out["small_1d_n512"]["workload"] = "n=m=512 sorted U(0,1), masses U(0.1,1), eps=0.01, tol=1e-9, cap 2000"
     p = wl.config_graded_1d(1 << 20, 1e-2)
     out["graded_1d_eps1e-2"] = run1d(p, precision)
-    p = wl.config_tanh_2d(1024)
-    args2 = (dev(p.x1), dev(p.y1), dev(p.x2), dev(p.y2), dev(p.u.ravel(order="F")),
-             dev(p.v.ravel(order="F")), p.eps, p.tol, p.itr_max)
-    sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r, _, _ = sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
-    dt = time.perf_counter() - t0
-    out["tanh_2d_1024"] = {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s",
-                           "solve_ms": dt * 1e3, "iters": r["iters"], "w1": r["w1"],
-                           "marginal_err": r["marginal_err"], "converged": r["converged"],
-                           "loop_ms": r["loop_ms"],
-                           "scan_mantissa": "fp32" if precision == 1 else "fp64",
-                           "workload": "1024 x 1024 tanh mesh (beta 2.5), 4-component 2D GMM masses, "
-                                       "eps=5e-3, tol=1e-6"}
+    out["tanh_2d_1024"] = bench_tanh_2d(precision)
     # d = 3 tensor meshes, 128^3 grid points per side, a fixed iteration count
     from paper_2605_26659_amd import sinkhorn_w1_nd
     xs, xt, u3, v3, eps3, its3 = wl.paper_random_nd((128, 128, 128), (128, 128, 128), iters=200)
@@ -461,6 +472,9 @@ def main():
 
     if args.plan_only:
         print(json.dumps(bench_plan(args.steps)), flush=True)
+        return
+    if args.tanh_2d_only:
+        print(json.dumps(bench_tanh_2d(1 if args.precision == "fp32" else 0)), flush=True)
         return
 
     if not args.no_autotune:

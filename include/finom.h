@@ -1,12 +1,13 @@
 /*
  * finom.h - C ABI of the MI355X (gfx950) FINOM library.
  *
- * Entropic Wasserstein-1 with L1 cost on non-uniform 1D meshes and 2D
- * tensor-product meshes, solved by Sinkhorn iterations whose kernel-vector
- * products K psi and K^T phi use the dividing-index split of
- * K = exp(-C/eps) into two quasi-collinear blocks and their O(N)
- * recurrences (section 2, eq. decompose to p+q, eq. p-DP, eq. q-DP;
- * section 3, eq. 2d-kron, Algorithms 1 and 2).
+ * Entropic Wasserstein-1 with L1 cost on non-uniform 1D meshes and on
+ * tensor-product meshes in two or more dimensions, solved by Sinkhorn
+ * iterations whose kernel-vector products K psi and K^T phi use the
+ * dividing-index split of K = exp(-C/eps) into two quasi-collinear blocks and
+ * their O(N) recurrences (section 2, eq. decompose to p+q, eq. p-DP,
+ * eq. q-DP; section 3, eq. 2d-kron, Algorithms 1 and 2); the transport plans
+ * of the results and their differences (section 4).
  *
  * Conventions for every entry point
  *  - Array pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors)
@@ -150,10 +151,11 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
  * arrays of d DEVICE pointers to the non-decreasing axis coordinates.
  * u (prod n_src) and v (prod n_tgt) are column-major grids: element
  * (k_0, ..., k_{d-1}) at k_0 + n_0 (k_1 + n_1 (k_2 + ...)), axis 0 fastest;
- * f_out / g_out use the same layout. d = 1 is Algorithm 1 and d = 2
- * Algorithm 2, on the general sweeps. Loop, check, outputs and errors as in
- * sinkhorn_w1_2d; w1 = <sum_a |x_a - y_a|, Gamma> in FP64. FINOM_E_ARG also
- * for d < 1 or d > FINOM_MAX_DIMS.
+ * f_out / g_out use the same layout. d = 1 runs sinkhorn_w1_1d and d = 2
+ * sinkhorn_w1_2d (same results, bit for bit); d >= 3 runs the general sweeps
+ * along every axis. Loop, check, outputs and errors as in sinkhorn_w1_2d;
+ * w1 = <sum_a |x_a - y_a|, Gamma> in FP64. FINOM_E_ARG also for d < 1 or
+ * d > FINOM_MAX_DIMS.
  */
 int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src,
                    const int64_t* n_tgt, const double* const* x_tgt,

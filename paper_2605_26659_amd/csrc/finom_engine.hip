@@ -884,11 +884,11 @@ void Engine::rebuild()
             chk[ji] = LineRange{gty, groups[gty].sw[0]->lines.size(), (size_t)n2};
             dcd[ji] = LineRange{gy, groups[gy].sw[0]->lines.size(), (size_t)n2};
             for (int b = 0; b < 2; ++b) {
-                add_axis0_lines(*groups[gtx].sw[b], j->pkt[0], eps, j->F, n1, j->S, n2, m1, j->slot);
-                add_2d_kt_y_lines(*groups[gty].sw[b], j->pkt[1], eps, j->S, n2, j->G[1 - b], m2, j->lvr, j->vr,
-                                  j->G[b], j->slot);
+                add_2d_kt_x_lines(*groups[gtx].sw[b], j->pkt[0], eps, j->F, n1, j->S, m1, j->slot);
+                add_2d_kt_y_lines(*groups[gty].sw[b], j->pkt[1], eps, j->S, m1, j->G[1 - b], m2, j->lvr, j->vr,
+                                  j->G[b], n2, j->slot);
                 add_2d_k_y_lines(*groups[gy].sw[b], j->pk[1], eps, j->G[1 - b], m2, j->S, m1, n2, j->slot);
-                add_2d_k_x_lines(*groups[gx].sw[b], j->pk[0], eps, j->S, m1, j->F, n1, j->lu, j->slot);
+                add_2d_k_x_lines(*groups[gx].sw[b], j->pk[0], eps, j->S, n2, j->F, n1, j->lu, m1, j->slot);
             }
         }
     }
@@ -1070,14 +1070,14 @@ std::vector<Job*> Engine::harvest()
             // each product along y first, as in the loop
             add_2d_k_y_lines(cy_p, j->pc[1], eps, Gf, d.m2, j->S, d.m1, d.n2, dummy);
             size_t q0 = cx_m.lines.size();
-            add_2d_k_x_lines(cx_m, j->pc[0], eps, j->S, d.m1, nullptr, d.n1, j->F, dummy);
+            add_2d_k_x_lines(cx_m, j->pc[0], eps, j->S, d.n2, nullptr, d.n1, j->F, d.m1, dummy);
             for (size_t q = q0; q < cx_m.lines.size(); ++q) {
                 cx_m.lines[q].part_base = P;
                 P += cx_m.lines[q].ntiles;
             }
             add_2d_k_y_lines(cy_m, j->pc[1], eps, Gf, d.m2, j->S, d.m1, d.n2, dummy);
             q0 = cx_p.lines.size();
-            add_2d_k_x_lines(cx_p, j->pc[0], eps, j->S, d.m1, nullptr, d.n1, j->F, dummy);
+            add_2d_k_x_lines(cx_p, j->pc[0], eps, j->S, d.n2, nullptr, d.n1, j->F, d.m1, dummy);
             for (size_t q = q0; q < cx_p.lines.size(); ++q) {
                 cx_p.lines[q].part_base = P;
                 P += cx_p.lines[q].ntiles;

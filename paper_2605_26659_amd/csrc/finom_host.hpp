@@ -368,25 +368,41 @@ inline void add_axis1_lines(Sweep& sw, const Part& p, double eps, const double* 
 // ---------------------------------------------------------------------------
 // 2D solves keep psi (and the target-side masses the check reads) row-major,
 // element (l, j) of the n2 x m2 target grid at j + l m2, while phi stays
-// column-major (k + i n1). Each product then has at most one strided stream
-// per sweep: K^T phi runs along x (contiguous columns of phi into the n2 x m1
-// column-major intermediate) and then along y (strided rows of the
-// intermediate into contiguous rows of psi); K psi runs along y first
-// (contiguous rows of psi into the row-major n2 x m1 intermediate) and then
-// along x (strided columns of the intermediate into contiguous columns of
-// phi). The products along the two axes commute (eq. 2d-kpsi).
+// column-major (k + i n1). Every sweep then reads contiguous lines, and the
+// only strided stream of a product is the store of its intermediate: K^T phi
+// runs along x (columns of phi into the n2 x m1 intermediate, stored
+// row-major) and then along y (rows of the intermediate into rows of psi);
+// K psi runs along y first (rows of psi into the intermediate, stored
+// column-major) and then along x (its columns into columns of phi). The
+// products along the two axes commute (eq. 2d-kpsi).
 // ---------------------------------------------------------------------------
 
-// K^T phi, along y: line l (< n2) reads row l of S (stride n2) and writes row
-// l of psi (contiguous, m2 points); the epilogue operands are indexed as psi.
-inline void add_2d_kt_y_lines(Sweep& sw, const Part& p, double eps, const double* S, long long n2,
+// K^T phi, along x: line i (< m1) reads column i of phi (contiguous, n1
+// points) and writes column i of the row-major n2 x m1 intermediate (stride m1).
+inline void add_2d_kt_x_lines(Sweep& sw, const Part& p, double eps, const double* F, long long n1, double* S,
+                              long long m1, int prob = 0)
+{
+    for (long long i = 0; i < m1; ++i) {
+        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+        L.gin = F + i * n1;
+        L.out = S + i;
+        L.ostride = m1;
+        L.dec_part_off = -1;
+        L.prob = prob;
+        sw.lines.push_back(L);
+    }
+}
+
+// K^T phi, along y: line l (< n2) reads row l of the row-major intermediate
+// (contiguous, m1 points) and writes row l of psi (contiguous, m2 points); the
+// epilogue operands are indexed as psi.
+inline void add_2d_kt_y_lines(Sweep& sw, const Part& p, double eps, const double* S, long long m1,
                               double* G, long long m2, const double* a0, const double* a1, const double* a2,
-                              int prob = 0)
+                              long long n2, int prob = 0)
 {
     for (long long l = 0; l < n2; ++l) {
         LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
-        L.gin = S + l;
-        L.gstride = n2;
+        L.gin = S + l * m1;
         L.out = G + l * m2;
         L.a0 = a0 ? a0 + l * m2 : nullptr;
         L.a1 = a1 ? a1 + l * m2 : nullptr;
@@ -398,30 +414,30 @@ inline void add_2d_kt_y_lines(Sweep& sw, const Part& p, double eps, const double
 }
 
 // K psi, along y: line l (< n2) reads row l of psi (contiguous, m2 points)
-// and writes row l of the row-major n2 x m1 intermediate.
+// and writes row l of the column-major n2 x m1 intermediate (stride n2).
 inline void add_2d_k_y_lines(Sweep& sw, const Part& p, double eps, const double* G, long long m2, double* S,
                              long long m1, long long n2, int prob = 0)
 {
     for (long long l = 0; l < n2; ++l) {
         LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
         L.gin = G + l * m2;
-        L.out = S + l * m1;
+        L.out = S + l;
+        L.ostride = n2;
         L.dec_part_off = -1;
         L.prob = prob;
         sw.lines.push_back(L);
     }
 }
 
-// K psi, along x: line i (< m1) reads column i of the row-major intermediate
-// (stride m1) and writes column i of phi (contiguous, n1 points), or only
-// reads phi there (a0) when out is NULL (the cost sweeps).
-inline void add_2d_k_x_lines(Sweep& sw, const Part& p, double eps, const double* S, long long m1, double* F,
-                             long long n1, const double* a0, int prob = 0)
+// K psi, along x: line i (< m1) reads column i of the column-major
+// intermediate (contiguous, n2 points) and writes column i of phi (contiguous,
+// n1 points), or only reads phi there (a0) when out is NULL (the cost sweeps).
+inline void add_2d_k_x_lines(Sweep& sw, const Part& p, double eps, const double* S, long long n2, double* F,
+                             long long n1, const double* a0, long long m1, int prob = 0)
 {
     for (long long i = 0; i < m1; ++i) {
         LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
-        L.gin = S + i;
-        L.gstride = m1;
+        L.gin = S + i * n2;
         L.out = F ? F + i * n1 : nullptr;
         L.a0 = a0 ? a0 + i * n1 : nullptr;
         L.dec_part_off = -1;

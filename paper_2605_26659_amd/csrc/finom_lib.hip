@@ -1236,15 +1236,15 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
             kty[b].cfg = ky[b].cfg = cfg_y;
             // K^T phi = vec(K_x^T Phi K_y): S = K_x^T Phi (columns), then S K_y (rows of S into rows of psi)
             ktx[b].epi = EPI_STORE_LOG2;
-            add_axis0_lines(ktx[b], px_t, eps, F, n1, S, n2, m1);
+            add_2d_kt_x_lines(ktx[b], px_t, eps, F, n1, S, m1);
             kty[b].epi = EPI_UPDATE_CHECK;
-            add_2d_kt_y_lines(kty[b], py_t, eps, S, n2, G[1 - b], m2, lvr, vr, G[b]);
+            add_2d_kt_y_lines(kty[b], py_t, eps, S, m1, G[1 - b], m2, lvr, vr, G[b], n2);
             nchk = assign_parts(kty[b], 0);
             // K psi = vec(K_x Psi K_y^T): S = Psi K_y^T (rows of psi), then K_x S (columns into phi)
             ky[b].epi = EPI_STORE_LOG2;
             add_2d_k_y_lines(ky[b], py, eps, G[1 - b], m2, S, m1, n2);
             kx[b].epi = EPI_UPDATE;
-            add_2d_k_x_lines(kx[b], px, eps, S, m1, F, n1, lu);
+            add_2d_k_x_lines(kx[b], px, eps, S, n2, F, n1, lu, m1);
         }
         for (int b = 0; b < 2; ++b) {
             set_decision(ky[b], 0, nchk);
@@ -1273,11 +1273,11 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         cy_p.kind = 1; cy_p.epi = EPI_STORE_LOG2;
         add_2d_k_y_lines(cy_p, pyc, eps, Gf, m2, S, m1, n2);
         cx_m.kind = 2; cx_m.epi = EPI_COST;
-        add_2d_k_x_lines(cx_m, pxc, eps, S, m1, nullptr, n1, F);
+        add_2d_k_x_lines(cx_m, pxc, eps, S, n2, nullptr, n1, F, m1);
         cy_m.kind = 2; cy_m.epi = EPI_STORE_LOG2;
         add_2d_k_y_lines(cy_m, pyc, eps, Gf, m2, S, m1, n2);
         cx_p.kind = 1; cx_p.epi = EPI_COST;
-        add_2d_k_x_lines(cx_p, pxc, eps, S, m1, nullptr, n1, F);
+        add_2d_k_x_lines(cx_p, pxc, eps, S, n2, nullptr, n1, F, m1);
         for (Sweep* c : {&cy_p, &cx_m, &cy_m, &cx_p})
             for (auto& L : c->lines) L.prob = 1;
         const int n_a = assign_parts(cx_m, 0);
@@ -1333,6 +1333,14 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         na *= n_src[a];
         nb *= n_tgt[a];
     }
+    // one and two axes have their own paths (the resident and fast 1D sweeps;
+    // the 2D layout with psi row-major)
+    if (d == 1)
+        return sinkhorn_w1_1d(x_src[0], n_src[0], x_tgt[0], n_tgt[0], u, v, eps, tol, itr_max, opts, f_out, g_out,
+                              res, stream);
+    if (d == 2)
+        return sinkhorn_w1_2d(x_src[0], n_src[0], x_src[1], n_src[1], x_tgt[0], n_tgt[0], x_tgt[1], n_tgt[1], u, v,
+                              eps, tol, itr_max, opts, f_out, g_out, res, stream);
     hipStream_t s = (hipStream_t)stream;
     try {
         Alloc al(stream);
