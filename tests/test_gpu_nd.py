@@ -34,7 +34,8 @@ def _solve(xs, xt, u, v, eps, tol, itr_max, precision=0):
 
 
 @pytest.mark.parametrize("ns,nt", [((6, 5, 4), (5, 7, 3)), ((9, 1, 8), (7, 3, 1)), ((3, 4, 2, 3), (2, 3, 4, 2)),
-                                   ((40, 30, 20), (35, 25, 30))])
+                                   ((40, 30, 20), (35, 25, 30)), ((3, 2, 4, 2, 3), (2, 3, 2, 3, 2)),
+                                   ((2,) * 8, (2, 3, 2, 1, 2, 2, 2, 2))])
 def test_nd_fixed_iterations(ns, nt):
     xs, xt, u, v = _case(sum(ns) * 7 + sum(nt), ns, nt)
     eps, L = 0.05, 15
