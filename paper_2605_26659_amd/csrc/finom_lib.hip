@@ -1387,65 +1387,95 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
             pc[a] = make_part_like(al, pk[a], Tc, s);
         }
 
-        // Step a of a product maps a grid whose axes before a already have the
-        // output's sizes and whose axes from a on have the input's sizes to
-        // the grid with axis a replaced: `lead` points before the axis,
-        // `trail` after it. Intermediate grids alternate between two buffers.
-        auto step_shape = [&](bool to_target, int a, long long& lead, long long& trail) {
-            const int64_t* so = to_target ? n_tgt : n_src;
-            const int64_t* si = to_target ? n_src : n_tgt;
-            lead = 1;
-            trail = 1;
-            for (int q = 0; q < a; ++q) lead *= so[q];
-            for (int q = a + 1; q < d; ++q) trail *= si[q];
+        // Grid layouts: rot(r) stores the axes in the order r, r+1, ..., d-1,
+        // 0, ..., r-1, the first fastest. K^T phi runs along axes 0, 1, ...,
+        // d-1 and K psi along d-1, ..., 0. A step along axis a reads its input
+        // in rot(a), so that every line is contiguous, and stores its output
+        // in the layout the next step reads, strided along a; the last step of
+        // a product stores in rot(a), contiguously. So phi lives in rot(0),
+        // the caller's column-major order, and psi in rot(d-1), with the
+        // copies of log2 v and v that the check reads.
+        auto strides_of = [&](const std::vector<long long>& sz, int r, std::vector<long long>& st) {
+            st.assign(d, 0);
+            long long acc = 1;
+            for (int q = 0; q < d; ++q) {
+                const int ax = (r + q) % d;
+                st[ax] = acc;
+                acc *= sz[ax];
+            }
         };
         long long smax = 1;
-        for (int a = 0; a + 1 < d; ++a)
-            for (int dir = 0; dir < 2; ++dir) {
-                long long lead, trail;
-                step_shape(dir == 0, a, lead, trail);
-                smax = std::max(smax, lead * (dir == 0 ? n_tgt[a] : n_src[a]) * trail);
+        for (int dir = 0; dir < 2; ++dir) {
+            const bool tt = dir == 0;
+            std::vector<long long> sz(d);
+            for (int q = 0; q < d; ++q) sz[q] = tt ? n_src[q] : n_tgt[q];
+            for (int k = 0; k + 1 < d; ++k) {
+                const int a = tt ? k : d - 1 - k;
+                sz[a] = tt ? n_tgt[a] : n_src[a];
+                long long tot = 1;
+                for (int q = 0; q < d; ++q) tot *= sz[q];
+                smax = std::max(smax, tot);
             }
+        }
+        const long long rows_t = nb / n_tgt[d - 1];   // psi in rot(d-1): the column-major grid transposed as
+                                                      // rows_t x n_tgt[d-1]
         double* S[2] = {al.dev<double>(smax), al.dev<double>(smax)};
         double* F = al.dev<double>(na);
         double* G[2] = {al.dev<double>(nb), al.dev<double>(nb)};
+        double* lvr = al.dev<double>(nb);
+        double* vr = al.dev<double>(nb);
+        enqueue_transpose_scale(lv, lvr, rows_t, n_tgt[d - 1], true, 1.0, s);
+        enqueue_transpose_scale(v, vr, rows_t, n_tgt[d - 1], true, 1.0, s);
         enqueue_fill(F, na, -log2((double)na), s);
         enqueue_fill(G[0], nb, -log2((double)nb), s);
         ProbState* ps = al.dev<ProbState>(2);
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
 
-        // Lines of step a: line (l, t) reads in[l + t lead n_in + i lead] and
-        // writes out[l + t lead n_out + i lead]; the epilogue operands of the
-        // last step are indexed as its output.
+        // Step k of a product (axis a): line L runs over the other axes in the
+        // input's order, the first fastest, and reads in[L n_in + i]; it
+        // writes at the output offset of the same multi-index with the stride
+        // of axis a in the output layout. The epilogue operands of the last
+        // step are indexed as its output.
         auto add_product = [&](Sweep* sw, bool to_target, const std::vector<Part>& parts, const double* in,
                                double* out, const double* a0, const double* a1, const double* a2, int prob) {
-            for (int a = 0; a < d; ++a) {
-                long long lead, trail;
-                step_shape(to_target, a, lead, trail);
-                const long long nin = to_target ? n_src[a] : n_tgt[a];
-                const long long nout = to_target ? n_tgt[a] : n_src[a];
-                const bool last = a == d - 1;
-                const double* src = a == 0 ? in : S[(a - 1) & 1];
-                double* dst = last ? out : S[a & 1];
+            std::vector<long long> sz(d), st_out, idx(d);
+            for (int q = 0; q < d; ++q) sz[q] = to_target ? n_src[q] : n_tgt[q];
+            for (int k = 0; k < d; ++k) {
+                const int a = to_target ? k : d - 1 - k;
+                const bool last = k == d - 1;
+                const long long nin = sz[a];
+                sz[a] = to_target ? n_tgt[a] : n_src[a];
+                strides_of(sz, last ? a : (to_target ? a + 1 : a - 1), st_out);
+                long long nlines = 1;
+                for (int q = 0; q < d; ++q)
+                    if (q != a) nlines *= sz[q];
+                const double* src = k == 0 ? in : S[(k - 1) & 1];
+                double* dst = last ? out : S[k & 1];
                 const Part& p = parts[a];
-                for (long long t = 0; t < trail; ++t)
-                    for (long long l = 0; l < lead; ++l) {
-                        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
-                        const long long oi = l + t * lead * nin, oo = l + t * lead * nout;
-                        L.gin = src + oi;
-                        L.gstride = lead;
-                        L.out = dst ? dst + oo : nullptr;
-                        L.ostride = lead;
-                        if (last) {
-                            L.a0 = a0 ? a0 + oo : nullptr;
-                            L.a1 = a1 ? a1 + oo : nullptr;
-                            L.a2 = a2 ? a2 + oo : nullptr;
-                        }
-                        L.dec_part_off = -1;
-                        L.prob = prob;
-                        sw[a].lines.push_back(L);
+                std::fill(idx.begin(), idx.end(), 0);
+                for (long long L = 0; L < nlines; ++L) {
+                    long long oo = 0;
+                    for (int q = 0; q < d; ++q)
+                        if (q != a) oo += idx[q] * st_out[q];
+                    LineDesc Ld = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+                    Ld.gin = src + L * nin;
+                    Ld.out = dst ? dst + oo : nullptr;
+                    Ld.ostride = st_out[a];
+                    if (last) {
+                        Ld.a0 = a0 ? a0 + oo : nullptr;
+                        Ld.a1 = a1 ? a1 + oo : nullptr;
+                        Ld.a2 = a2 ? a2 + oo : nullptr;
                     }
+                    Ld.dec_part_off = -1;
+                    Ld.prob = prob;
+                    sw[k].lines.push_back(Ld);
+                    for (int q = 1; q < d; ++q) {
+                        const int ax = (a + q) % d;
+                        if (++idx[ax] < sz[ax]) break;
+                        idx[ax] = 0;
+                    }
+                }
             }
         };
 
@@ -1457,24 +1487,23 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         for (int b = 0; b < 2; ++b) {
             kt[b].resize(d);
             kp[b].resize(d);
-            for (int a = 0; a < d; ++a) {
-                kt[b][a].cfg = kp[b][a].cfg = cfg[a];
-                kt[b][a].epi = kp[b][a].epi = EPI_STORE_LOG2;
+            for (int k = 0; k < d; ++k) {
+                kt[b][k].cfg = cfg[k];
+                kp[b][k].cfg = cfg[d - 1 - k];
+                kt[b][k].epi = kp[b][k].epi = EPI_STORE_LOG2;
             }
             kt[b][d - 1].epi = EPI_UPDATE_CHECK;
             kp[b][d - 1].epi = EPI_UPDATE;
-            add_product(kt[b].data(), true, pkt, F, G[1 - b], lv, v, G[b], 0);
+            add_product(kt[b].data(), true, pkt, F, G[1 - b], lvr, vr, G[b], 0);
             nchk = assign_parts(kt[b][d - 1], 0);
             add_product(kp[b].data(), false, pk, G[1 - b], F, lu, nullptr, nullptr, 0);
         }
         for (int b = 0; b < 2; ++b) {
             set_decision(kp[b][0], 0, nchk);
-            for (int a = 0; a < d; ++a) upload_sweep(al, kt[b][a], eb);
-            for (int a = 0; a < d; ++a) upload_sweep(al, kp[b][a], eb);
+            for (int k = 0; k < d; ++k) upload_sweep(al, kt[b][k], eb);
+            for (int k = 0; k < d; ++k) upload_sweep(al, kp[b][k], eb);
         }
-        long long lead_last, trail_last;
-        step_shape(false, d - 1, lead_last, trail_last);
-        const long long ncost = (long long)d * lead_last * pc[d - 1].ntiles;
+        const long long ncost = (long long)d * (na / n_src[0]) * pc[0].ntiles;
         double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
         al.uploaded();
 
@@ -1500,9 +1529,9 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         int nparts = 0;
         for (int c = 0; c < d; ++c) {
             Sweep* w = cs.data() + (size_t)c * d;
-            for (int a = 0; a < d; ++a) {
-                w[a].kind = a == c ? 2 : 1;
-                w[a].epi = a == d - 1 ? EPI_COST : EPI_STORE_LOG2;
+            for (int k = 0; k < d; ++k) {
+                w[k].kind = d - 1 - k == c ? 2 : 1;
+                w[k].epi = k == d - 1 ? EPI_COST : EPI_STORE_LOG2;
             }
             add_product(w, false, pc, Gf, nullptr, F, nullptr, nullptr, 1);
             nparts += assign_parts(w[d - 1], nparts);
@@ -1513,7 +1542,7 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, partial, 0, nparts,
                            &ps[1].w1);
         if (f_out) enqueue_scale(F, f_out, na, eps * kLn2, s);
-        if (g_out) enqueue_scale(Gf, g_out, nb, eps * kLn2, s);
+        if (g_out) enqueue_transpose_scale(Gf, g_out, rows_t, n_tgt[d - 1], false, eps * kLn2, s);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
