@@ -126,6 +126,23 @@ def test_mixed_1d_2d_members_equal_alone_solves(precision):
         _assert_same(r, d, ra, fa, ga)
 
 
+def test_degenerate_2d_members_equal_alone_solves():
+    """2D members with grids of one row or column (psi row-major inside the
+    engine: its transposes and strides degenerate there)."""
+    from paper_2605_26659_amd import finom_batch
+    descs = []
+    for k, (n1, m1, n2, m2) in enumerate([(1, 5, 7, 1), (5, 1, 1, 6), (1, 1, 4, 3), (2, 300, 3, 257)]):
+        rng = np.random.default_rng(70 + k)
+        x1, y1 = np.sort(rng.uniform(0, 1, n1)), np.sort(rng.uniform(0, 1, m1))
+        x2, y2 = np.sort(rng.uniform(0, 1, n2)), np.sort(rng.uniform(0, 1, m2))
+        u = wl.normalise(rng.uniform(0.1, 1, (n1, m1))); v = wl.normalise(rng.uniform(0.1, 1, (n2, m2)))
+        descs.append(_desc_2d(wl.Problem2D(x1, y1, x2, y2, u, v, 0.05, 0.0, 20)))
+    st, res = finom_batch(descs, precision=1)
+    for d, r in zip(descs, res):
+        ra, fa, ga = _alone(d, 1, resident=True)
+        _assert_same(r, d, ra, fa, ga)
+
+
 def test_members_against_the_oracle():
     from paper_2605_26659_amd import finom_batch
     probs = [wl.config_batch_problem(i, n) for i, n in enumerate([256, 700, 2000])]

@@ -138,3 +138,24 @@ def test_error_statuses_2d():
     with pytest.raises(FinomError) as e:
         _solve(bad)
     assert e.value.status == FINOM_E_MASS
+
+
+@pytest.mark.parametrize("n1,m1,n2,m2", [(1, 5, 7, 1), (5, 1, 1, 6), (1, 1, 4, 3), (6, 4, 1, 1), (2, 300, 3, 257),
+                                         (300, 2, 257, 3)])
+def test_degenerate_and_thin_grids(n1, m1, n2, m2):
+    """Grids of one row or one column and thin grids: psi is row-major inside
+    the solver, so these are the cases where its transposes and the strides
+    of the intermediates degenerate. Some of these problems are solved
+    exactly by one iteration (the error left is rounding, ~1e-16), so the
+    loop runs to tol 1e-12 rather than to a fixed count."""
+    rng = np.random.default_rng(n1 * 1000 + m1 * 100 + n2 * 10 + m2)
+    x1, y1 = np.sort(rng.uniform(0, 1, n1)), np.sort(rng.uniform(0, 1, m1))
+    x2, y2 = np.sort(rng.uniform(0, 1, n2)), np.sort(rng.uniform(0, 1, m2))
+    u = wl.normalise(rng.uniform(0.1, 1, (n1, m1))); v = wl.normalise(rng.uniform(0.1, 1, (n2, m2)))
+    p = wl.Problem2D(x1, y1, x2, y2, u, v, 0.05, 1e-12, 12)
+    res, F, G = _solve(p)
+    ref = dense.sinkhorn_2d(x1, y1, x2, y2, u, v, 0.05, 1e-12, 12)
+    assert res["iters"] == ref.iters
+    assert np.max(np.abs(F - ref.f)) / 0.05 <= 1e-9
+    assert np.max(np.abs(G - ref.g)) / 0.05 <= 1e-9
+    assert abs(res["w1"] - ref.w1) <= 1e-10 * ref.w1
