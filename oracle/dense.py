@@ -136,6 +136,25 @@ def plan_2d(x1, y1, x2, y2, F, G, eps) -> np.ndarray:
     return np.exp((f[:, None] + g[None, :] - c) / eps)
 
 
+def plan_entries(xs, xt, F, G, eps, rows, cols) -> np.ndarray:
+    """Selected entries Gamma[rows[t], cols[t]] of the plan on tensor meshes
+    with any number of axes (1D: one axis each), one by one from the
+    definition. rows / cols index the column-major grids (axis 0 fastest);
+    the cost is sum_a |xs[a]_k - xt[a]_l|."""
+    f = np.asarray(F, np.float64).ravel(order="F")
+    g = np.asarray(G, np.float64).ravel(order="F")
+    out = np.empty(len(rows))
+    for t, (r, c) in enumerate(zip(rows, cols)):
+        cost = 0.0
+        rr, cc = int(r), int(c)
+        for a in range(len(xs)):
+            k, rr = rr % len(xs[a]), rr // len(xs[a])
+            l, cc = cc % len(xt[a]), cc // len(xt[a])
+            cost += abs(float(xs[a][k]) - float(xt[a][l]))
+        out[t] = np.exp(((f[int(r)] + g[int(c)]) - cost) / eps)
+    return out
+
+
 def plan_difference(gamma_a, gamma_b) -> float:
     """||Gamma_a - Gamma_b||_F, the plan-difference column of section 4's tables."""
     d = np.asarray(gamma_a, np.float64) - np.asarray(gamma_b, np.float64)

@@ -203,3 +203,26 @@ def test_paper_2d_plan_difference(side):
     print(f"\n[plan difference] 2D {side}x{side}: GPU {got:.3e}, oracle {ref:.3e}", flush=True)
     assert 0.0 < got <= PAPER_FP64_BOUND and ref <= PAPER_FP64_BOUND
     assert abs(got - ref) <= 0.05 * ref
+
+
+def test_plan_2d_full_paper_size_sampled():
+    """The largest plan of section 4.3 (160 x 160 grids: 25600 x 25600 FP64
+    entries, 5.2 GB), exported whole on the device; sampled entries against
+    the oracle's definition, row sums against the marginal u."""
+    from paper_2605_26659_amd import finom_plan_2d, sinkhorn_w1_2d
+    torch = pytest.importorskip("torch")
+    p = wl.paper_random_2d(160, iters=50)
+    mesh = [dev(a) for a in (p.x1, p.y1, p.x2, p.y2)]
+    res, F, G = sinkhorn_w1_2d(*mesh, dev(p.u.ravel(order="F")), dev(p.v.ravel(order="F")), p.eps, 0.0, 50)
+    gamma = finom_plan_2d(*mesh, F, G, p.eps)
+    assert tuple(gamma.shape) == (25600, 25600)
+    rng = np.random.default_rng(160)
+    r = rng.integers(0, 25600, 20000)
+    c = rng.integers(0, 25600, 20000)
+    got = host(gamma[torch.as_tensor(r, device="cuda"), torch.as_tensor(c, device="cuda")])
+    want = dense.plan_entries([p.x1, p.y1], [p.x2, p.y2], host(F), host(G), p.eps, r, c)
+    np.testing.assert_allclose(got, want, rtol=RTOL_ENTRY, atol=ATOL_ENTRY)
+    # the last update is phi = u / K psi: every row sums to its mass
+    rows = host(gamma.sum(dim=1))
+    del gamma
+    np.testing.assert_allclose(rows, p.u.ravel(order="F"), rtol=1e-10, atol=0)

@@ -505,3 +505,21 @@ def test_nd_product_measures_factorise():
     np.testing.assert_allclose(rn.f, F, rtol=0, atol=1e-13)
     np.testing.assert_allclose(rn.g, G, rtol=0, atol=1e-13)
     assert abs(rn.w1 - sum(x.w1 for x in r)) <= 1e-13
+
+
+def test_plan_entries_match_the_full_plans():
+    """Entries one by one equal the full 1D and 2D plans (and the 2D plan's
+    Kronecker pin fixes the order both use)."""
+    rng = np.random.default_rng(34)
+    x, y = np.sort(rng.uniform(0, 1, 9)), np.sort(rng.uniform(0, 1, 7))
+    f, g = rng.uniform(-.05, .05, 9), rng.uniform(-.05, .05, 7)
+    P = dense.plan_1d(x, y, f, g, 0.03)
+    r, c = np.divmod(np.arange(63), 7)
+    np.testing.assert_allclose(dense.plan_entries([x], [y], f, g, 0.03, r, c), P[r, c], rtol=1e-15, atol=0)
+    x1, y1 = np.sort(rng.uniform(0, 1, 4)), np.sort(rng.uniform(0, 1, 3))
+    x2, y2 = np.sort(rng.uniform(0, 1, 5)), np.sort(rng.uniform(0, 1, 2))
+    F, G = rng.uniform(-.05, .05, 12), rng.uniform(-.05, .05, 10)
+    P2 = dense.plan_2d(x1, y1, x2, y2, F, G, 0.04)
+    r, c = np.divmod(np.arange(120), 10)
+    np.testing.assert_allclose(dense.plan_entries([x1, y1], [x2, y2], F, G, 0.04, r, c), P2[r, c],
+                               rtol=1e-15, atol=0)
