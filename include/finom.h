@@ -77,8 +77,9 @@ typedef struct {
                              state on chip; single calls and finom_batch members whose
                              tiles fit the GPU at once). Beyond that range: 3 for the
                              resident solver's extended-number variant (same condition),
-                             else 0 (the streaming general sweeps). 0 for precision 0 and
-                             2D; the server runs 0 or 1.                                 */
+                             else 0 (the streaming general sweeps). 0 for precision 0, 2D
+                             and d >= 3 (sinkhorn_w1_nd with one axis reports as
+                             sinkhorn_w1_1d); the server runs 0 or 1.                    */
     int32_t reserved;
 } finom_result;
 
