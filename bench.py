@@ -104,6 +104,8 @@ def parse():
                     help="full serving sweep (several arrival rates and the nominal 2000/s)")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving sample")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--random-3d-only", action="store_true",
+                    help="only the 3D 128^3 record (two warm-ups and one timed solve)")
     ap.add_argument("--tanh-2d-only", action="store_true",
                     help="only the 2D 1024 x 1024 tanh-mesh record (one warm-up and one timed solve)")
     ap.add_argument("--plan-only", action="store_true",
@@ -235,6 +237,32 @@ def bench_tanh_2d(precision):
                         "eps=5e-3, tol=1e-6"}
 
 
+def bench_random_3d(precision):
+    """d = 3 tensor meshes, 128^3 grid points per side, 200 iterations: one
+    timed solve after two warm-ups."""
+    import torch
+    from paper_2605_26659_amd import sinkhorn_w1_nd, workloads as wl
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    xs, xt, u3, v3, eps3, its3 = wl.paper_random_nd((128, 128, 128), (128, 128, 128), iters=200)
+    args3 = ([dev(a) for a in xs], [dev(a) for a in xt], dev(u3.ravel(order="F")), dev(v3.ravel(order="F")),
+             eps3, 0.0, its3)
+    # two warm-up solves: the first grows the stream's workspace, the second
+    # merges its blocks into one (the steady state of repeated solves)
+    for _ in range(2):
+        sinkhorn_w1_nd(*args3, precision=precision, want_potentials=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, _, _ = sinkhorn_w1_nd(*args3, precision=precision, want_potentials=False)
+    dt = time.perf_counter() - t0
+    pts3 = 0.5 * (u3.size + v3.size)
+    return {"value": pts3 * r["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
+            "iters": r["iters"], "w1": r["w1"], "marginal_err": r["marginal_err"],
+            "loop_ms": r["loop_ms"], "sweep_us": r["loop_ms"] * 1e3 / (6 * r["iters"]),
+            "scan_mantissa": "fp32" if precision == 1 else "fp64",
+            "workload": "3D 128^3 sorted U[0,1] axes, masses U[0,1], eps=0.01, "
+                        "200 iterations (section 4.3's recipe in three dimensions)"}
+
+
 def bench_other_configs(precision):
     """The other single-problem configurations, one timed solve each after a
     warm-up: the headline workload on the streaming sweeps, the small 1D
@@ -285,26 +313,7 @@ def bench_other_configs(precision):
     p = wl.config_graded_1d(1 << 20, 1e-2)
     out["graded_1d_eps1e-2"] = run1d(p, precision)
     out["tanh_2d_1024"] = bench_tanh_2d(precision)
-    # d = 3 tensor meshes, 128^3 grid points per side, a fixed iteration count
-    from paper_2605_26659_amd import sinkhorn_w1_nd
-    xs, xt, u3, v3, eps3, its3 = wl.paper_random_nd((128, 128, 128), (128, 128, 128), iters=200)
-    args3 = ([dev(a) for a in xs], [dev(a) for a in xt], dev(u3.ravel(order="F")), dev(v3.ravel(order="F")),
-             eps3, 0.0, its3)
-    # two warm-up solves: the first grows the stream's workspace, the second
-    # merges its blocks into one (the steady state of repeated solves)
-    for _ in range(2):
-        sinkhorn_w1_nd(*args3, precision=precision, want_potentials=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r, _, _ = sinkhorn_w1_nd(*args3, precision=precision, want_potentials=False)
-    dt = time.perf_counter() - t0
-    pts3 = 0.5 * (u3.size + v3.size)
-    out["random_3d_128"] = {"value": pts3 * r["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
-                            "iters": r["iters"], "w1": r["w1"], "marginal_err": r["marginal_err"],
-                            "loop_ms": r["loop_ms"], "sweep_us": r["loop_ms"] * 1e3 / (6 * r["iters"]),
-                            "scan_mantissa": "fp32" if precision == 1 else "fp64",
-                            "workload": "3D 128^3 sorted U[0,1] axes, masses U[0,1], eps=0.01, "
-                                        "200 iterations (section 4.3's recipe in three dimensions)"}
+    out["random_3d_128"] = bench_random_3d(precision)
     return out
 
 
@@ -479,6 +488,9 @@ def main():
         return
     if args.tanh_2d_only:
         print(json.dumps(bench_tanh_2d(1 if args.precision == "fp32" else 0)), flush=True)
+        return
+    if args.random_3d_only:
+        print(json.dumps(bench_random_3d(1 if args.precision == "fp32" else 0)), flush=True)
         return
 
     if not args.no_autotune:
