@@ -226,3 +226,25 @@ def test_plan_2d_full_paper_size_sampled():
     rows = host(gamma.sum(dim=1))
     del gamma
     np.testing.assert_allclose(rows, p.u.ravel(order="F"), rtol=1e-10, atol=0)
+
+
+def test_plan_1d_full_paper_size_sampled():
+    """Section 4.1's largest run (Chebyshev nodes, N = 8000, 1000 iterations,
+    eps = 0.01): the 8000 x 8000 plan exported whole, sampled entries against
+    the oracle computed one by one, row sums against u."""
+    from paper_2605_26659_amd import finom_plan_1d
+    torch = pytest.importorskip("torch")
+    p = wl.paper_chebyshev_1d(8000)
+    f, g = _finom_1d(p)
+    gamma = finom_plan_1d(dev(p.x), dev(p.y), f, g, p.eps)
+    rng = np.random.default_rng(8000)
+    r = rng.integers(0, 8000, 20000)
+    c = rng.integers(0, 8000, 20000)
+    # half of the samples near the diagonal, where the mass is
+    c[:10000] = np.clip(r[:10000] + rng.integers(-40, 41, 10000), 0, 7999)
+    got = host(gamma[torch.as_tensor(r, device="cuda"), torch.as_tensor(c, device="cuda")])
+    want = dense.plan_entries([p.x], [p.y], host(f), host(g), p.eps, r, c)
+    np.testing.assert_allclose(got, want, rtol=RTOL_ENTRY, atol=ATOL_ENTRY)
+    rows = host(gamma.sum(dim=1))
+    del gamma
+    np.testing.assert_allclose(rows, p.u, rtol=1e-10, atol=0)
