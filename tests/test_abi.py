@@ -32,3 +32,25 @@ def test_status_strings_without_gpu():
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _binding.load(tmp_path / "nope.so")
+
+
+def test_header_declares_the_plan_and_nd_entry_points():
+    names = _binding.declared_functions()
+    for must in ("finom_plan_1d", "finom_plan_2d", "finom_plan_diff_1d", "finom_plan_diff_2d",
+                 "sinkhorn_w1_nd"):
+        assert must in names
+
+
+def test_binding_rejects_host_tensors_without_gpu():
+    """Argument marshalling refuses host (CPU) tensors, other dtypes and
+    mismatched axis lists before anything reaches the library."""
+    torch = pytest.importorskip("torch")
+    from paper_2605_26659_amd import finom_plan_1d, finom_plan_diff_1d, sinkhorn_w1_nd
+    x = torch.zeros(4, dtype=torch.float64)
+    g = torch.empty((4, 4), dtype=torch.float64)
+    with pytest.raises(TypeError):
+        finom_plan_1d(x, x, x, x, 0.1, g)
+    with pytest.raises(TypeError):
+        finom_plan_diff_1d(x, x, x, x, x, x, 0.1, torch.empty(1, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        sinkhorn_w1_nd([x, x], [x], x, x, 0.1, 0.0, 1)
