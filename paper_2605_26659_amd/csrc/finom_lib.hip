@@ -1453,22 +1453,25 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
                 const double* src = k == 0 ? in : S[(k - 1) & 1];
                 double* dst = last ? out : S[k & 1];
                 const Part& p = parts[a];
+                // every line of the step shares the meshes and the partition
+                LineDesc base = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+                base.ostride = st_out[a];
+                base.dec_part_off = -1;
+                base.prob = prob;
+                sw[k].lines.reserve(sw[k].lines.size() + (size_t)nlines);
                 std::fill(idx.begin(), idx.end(), 0);
                 for (long long L = 0; L < nlines; ++L) {
                     long long oo = 0;
                     for (int q = 0; q < d; ++q)
                         if (q != a) oo += idx[q] * st_out[q];
-                    LineDesc Ld = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
+                    LineDesc Ld = base;
                     Ld.gin = src + L * nin;
                     Ld.out = dst ? dst + oo : nullptr;
-                    Ld.ostride = st_out[a];
                     if (last) {
                         Ld.a0 = a0 ? a0 + oo : nullptr;
                         Ld.a1 = a1 ? a1 + oo : nullptr;
                         Ld.a2 = a2 ? a2 + oo : nullptr;
                     }
-                    Ld.dec_part_off = -1;
-                    Ld.prob = prob;
                     sw[k].lines.push_back(Ld);
                     for (int q = 1; q < d; ++q) {
                         const int ax = (a + q) % d;
