@@ -68,10 +68,13 @@ int get_tuned_cfg(int precision, int cls);   // -1 when not tuned
 
 // ---------------------------------------------------------------------------
 // Workspace: per stream, a list of device blocks and pinned host blocks.
-// A call carves what it needs with a bump pointer; when it overflows, another
-// block is added. At the start of the next call on the stream the blocks are
-// merged into one (after the stream has drained), so steady state is one
-// device block and one host block with no allocation per call.
+// A call carves what it needs with a bump pointer through the blocks in
+// order, moving to the next block when one is full; when the last one
+// overflows, another block is added. The next call on the stream starts again
+// at the first block, so a call that fits the blocks the earlier calls grew
+// allocates nothing, and no block is freed before the workspace is released.
+// Device memory is reused in stream order; the pinned host blocks only after
+// the previous call's uploads have completed (upload_done).
 // ---------------------------------------------------------------------------
 struct Block {
     char* p;
@@ -80,7 +83,8 @@ struct Block {
 
 struct Arena {
     std::vector<Block> dblk, hblk;
-    size_t dused = 0, hused = 0;
+    size_t dcur = 0, hcur = 0;     // block the next carve tries first
+    size_t dused = 0, hused = 0;   // bytes used in that block
     hipEvent_t upload_done = nullptr;
 };
 
@@ -101,43 +105,25 @@ struct Alloc {
     {
         if (a->upload_done) HIPCHK(hipEventSynchronize(a->upload_done));
         else HIPCHK(hipEventCreateWithFlags(&a->upload_done, hipEventDisableTiming));
-        if (a->dblk.size() > 1 || a->hblk.size() > 1) {
-            HIPCHK(hipStreamSynchronize(s));
-            merge(a->dblk, false);
-            merge(a->hblk, true);
-        }
+        a->dcur = a->hcur = 0;
         a->dused = 0;
         a->hused = 0;
     }
-    static void merge(std::vector<Block>& v, bool host)
-    {
-        if (v.size() <= 1) return;
-        size_t tot = 0;
-        for (auto& b : v) {
-            tot += b.cap;
-            if (host) hipHostFree(b.p);
-            else hipFree(b.p);
-        }
-        v.clear();
-        Block b{nullptr, tot};
-        if (host) {
-            if (hipHostMalloc((void**)&b.p, tot, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
-        } else {
-            if (hipMalloc((void**)&b.p, tot) != hipSuccess) throw std::bad_alloc();
-        }
-        v.push_back(b);
-    }
-    static char* carve(std::vector<Block>& v, size_t& used, size_t bytes, size_t align, bool host)
+    // Block bases are at least 256-byte aligned (hipMalloc, hipHostMalloc),
+    // so offsets aligned within a block are aligned addresses.
+    static char* carve(std::vector<Block>& v, size_t& cur, size_t& used, size_t bytes, size_t align, bool host)
     {
         bytes = align_up(std::max<size_t>(bytes, 1), align);
-        if (!v.empty()) {
-            size_t off = align_up(used, align);
-            if (off + bytes <= v.back().cap) {
+        while (cur < v.size()) {
+            const size_t off = align_up(used, align);
+            if (off <= v[cur].cap && bytes <= v[cur].cap - off) {
                 used = off + bytes;
-                return v.back().p + off;
+                return v[cur].p + off;
             }
+            ++cur;
+            used = 0;
         }
-        size_t cap = std::max(bytes, v.empty() ? (size_t)(host ? (1u << 20) : (16u << 20)) : v.back().cap);
+        const size_t cap = std::max(bytes, v.empty() ? (size_t)(host ? (1u << 20) : (16u << 20)) : v.back().cap);
         Block b{nullptr, cap};
         if (host) {
             if (hipHostMalloc((void**)&b.p, cap, hipHostMallocDefault) != hipSuccess) throw std::bad_alloc();
@@ -145,13 +131,20 @@ struct Alloc {
             if (hipMalloc((void**)&b.p, cap) != hipSuccess) throw std::bad_alloc();
         }
         v.push_back(b);
+        cur = v.size() - 1;
         used = bytes;
         return b.p;
     }
     template <typename T>
-    T* dev(size_t count) { return reinterpret_cast<T*>(carve(a->dblk, a->dused, sizeof(T) * count, 256, false)); }
+    T* dev(size_t count)
+    {
+        return reinterpret_cast<T*>(carve(a->dblk, a->dcur, a->dused, sizeof(T) * count, 256, false));
+    }
     template <typename T>
-    T* host(size_t count) { return reinterpret_cast<T*>(carve(a->hblk, a->hused, sizeof(T) * count, 64, true)); }
+    T* host(size_t count)
+    {
+        return reinterpret_cast<T*>(carve(a->hblk, a->hcur, a->hused, sizeof(T) * count, 64, true));
+    }
     void uploaded() { HIPCHK(hipEventRecord(a->upload_done, s)); }
 };
 

@@ -170,6 +170,7 @@ void arena_free(Arena* a)
     for (auto& b : a->hblk) hipHostFree(b.p);
     a->dblk.clear();
     a->hblk.clear();
+    a->dcur = a->hcur = 0;
     a->dused = a->hused = 0;
 }
 
