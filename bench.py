@@ -222,7 +222,7 @@ def bench_tanh_2d(precision):
     p = wl.config_tanh_2d(1024)
     args2 = (dev(p.x1), dev(p.y1), dev(p.x2), dev(p.y2), dev(p.u.ravel(order="F")),
              dev(p.v.ravel(order="F")), p.eps, p.tol, p.itr_max)
-    for _ in range(2):   # as for the 3D record: workspace grown, then merged
+    for _ in range(2):   # as for the headline: the first grows the workspace
         sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -246,8 +246,8 @@ def bench_random_3d(precision):
     xs, xt, u3, v3, eps3, its3 = wl.paper_random_nd((128, 128, 128), (128, 128, 128), iters=200)
     args3 = ([dev(a) for a in xs], [dev(a) for a in xt], dev(u3.ravel(order="F")), dev(v3.ravel(order="F")),
              eps3, 0.0, its3)
-    # two warm-up solves: the first grows the stream's workspace, the second
-    # merges its blocks into one (the steady state of repeated solves)
+    # two warm-up solves, as for the headline (the first grows the stream's
+    # workspace; later solves allocate nothing)
     for _ in range(2):
         sinkhorn_w1_nd(*args3, precision=precision, want_potentials=False)
     torch.cuda.synchronize()
