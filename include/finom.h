@@ -106,6 +106,34 @@ int dense_matvec(const double* x_rows, int64_t n, const double* y_cols, int64_t 
                  double eps, const double* in, double* out, const finom_opts* opts,
                  void* stream);
 
+/* Largest n + m that finom_matvec_noalloc accepts (2^22 merged points). */
+#define FINOM_NOALLOC_MAX_POINTS 4194304
+
+/*
+ * finom_matvec for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, semantics, kernels and tile shape as finom_matvec, so the
+ * output is the same bit for bit. It allocates nothing (no hipMalloc,
+ * hipFree or pinned host memory) and never synchronises: it only enqueues
+ * kernels on `stream`. Its working arrays (dividing index, tile starts, work
+ * list, descriptor, tile aggregates) live in one fixed device array of about
+ * 16.4 MiB per device, which each device that runs it holds until the
+ * process ends. Calls on one device share that array: calls that overlap on
+ * a device (other streams, or host threads without ordering) race and give
+ * wrong results; calls on one stream are ordered and safe.
+ * Not checked on the device (as with opts->skip_checks = 1): the meshes
+ * must be non-decreasing and within the coordinate range of the
+ * conventions above; violating inputs give wrong values, never an
+ * out-of-range access.
+ * Errors (nothing enqueued): FINOM_E_ARG for the argument errors of
+ * finom_matvec and for n + m > FINOM_NOALLOC_MAX_POINTS (finom_last_error
+ * then names the limit); FINOM_E_HIP if the array's device address cannot
+ * be taken or a launch fails.
+ */
+int finom_matvec_noalloc(const double* x_rows, int64_t n, const double* y_cols, int64_t m,
+                         double eps, const double* in, double* out, const finom_opts* opts,
+                         void* stream);
+
 /*
  * Algorithm 1 (1D FINOM Sinkhorn) on meshes x (n) and y (m), masses u (n) and
  * v (m), all > 0 with sum(u) == sum(v) within 1e-12 relative.
@@ -309,7 +337,8 @@ const char* finom_strerror(int status);
 void finom_release(void);
 
 /* Detail of the last FINOM_E_HIP / FINOM_E_NOMEM raised on the calling host
- * thread (the HIP error string and code); empty if none. Static storage. */
+ * thread (the HIP error string and code), or of finom_matvec_noalloc's size
+ * refusal; empty if none. Static storage. */
 const char* finom_last_error(void);
 
 /* Library version string, e.g. "finom-gfx950 0.1". */

@@ -113,6 +113,7 @@ def load(path: os.PathLike | None = None):
     L = C.CDLL(str(p))
     L.finom_matvec.argtypes = [_vp, _i64, _vp, _i64, _d, _vp, _vp, C.POINTER(Opts), _vp]
     L.dense_matvec.argtypes = L.finom_matvec.argtypes
+    L.finom_matvec_noalloc.argtypes = L.finom_matvec.argtypes
     L.sinkhorn_w1_1d.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _d, _d, _i64, C.POINTER(Opts),
                                  _vp, _vp, C.POINTER(Result), _vp]
     L.finom_strerror.restype = C.c_char_p
@@ -204,6 +205,16 @@ def finom_matvec(x_rows, y_cols, eps, inp, out=None, *, precision=0, domain=0,
                              y_cols.numel(), float(eps), _dev(inp, "in"), _dev(out, "out"),
                              C.byref(_opts(precision, domain, skip_checks)), _stream_ptr(stream))
     _check(st, "finom_matvec")
+    return out
+
+
+def finom_matvec_noalloc(x_rows, y_cols, eps, inp, out, *, precision=0, domain=0, stream=None):
+    """finom_matvec through the entry point that allocates nothing; `out` is
+    required (n float64 values on the device). No device-side input checks."""
+    st = load().finom_matvec_noalloc(_dev(x_rows, "x_rows"), x_rows.numel(), _dev(y_cols, "y_cols"),
+                                     y_cols.numel(), float(eps), _dev(inp, "in"), _dev(out, "out"),
+                                     C.byref(_opts(precision, domain, True)), _stream_ptr(stream))
+    _check(st, "finom_matvec_noalloc")
     return out
 
 

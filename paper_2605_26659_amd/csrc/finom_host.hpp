@@ -256,6 +256,10 @@ inline Part part_view(const double* xr, long long R, const double* yc, long long
 
 Part make_part(Alloc& al, const double* xr, long long R, const double* yc, long long C, int T,
                hipStream_t s);
+// The same into caller-provided arrays: zeta (R ints) and the tile row starts
+// trs (ntiles_for(R, C, T) + 1 ints). Allocates nothing.
+void enqueue_partition(const double* xr, long long R, const double* yc, long long C, int T, int* zeta,
+                       int* trs, hipStream_t s);
 // Reuses an existing dividing index with another tile size.
 Part make_part_like(Alloc& al, const Part& base, int T, hipStream_t s);
 // The transposed pair (rows yc, columns xr) on the SAME merged-sequence tiles

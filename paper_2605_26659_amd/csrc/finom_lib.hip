@@ -468,11 +468,17 @@ Part make_part(Alloc& al, const double* xr, long long R, const double* yc, long 
     p.ntiles = ntiles_for(R, C, T);
     p.zeta = al.dev<int>(R);
     p.trs = al.dev<int>(p.ntiles + 1);
-    hipLaunchKernelGGL(k_dividing_index, dim3(blocks_for(R)), dim3(kBlock), 0, s, xr, R, yc, C, p.zeta);
-    hipLaunchKernelGGL(k_tile_rows, dim3(blocks_for(p.ntiles + 1)), dim3(kBlock), 0, s, p.zeta, R, T,
-                       p.ntiles, p.trs);
-    HIPCHK(hipGetLastError());
+    enqueue_partition(xr, R, yc, C, T, p.zeta, p.trs, s);
     return p;
+}
+
+void enqueue_partition(const double* xr, long long R, const double* yc, long long C, int T, int* zeta,
+                       int* trs, hipStream_t s)
+{
+    const int ntiles = ntiles_for(R, C, T);
+    hipLaunchKernelGGL(k_dividing_index, dim3(blocks_for(R)), dim3(kBlock), 0, s, xr, R, yc, C, zeta);
+    hipLaunchKernelGGL(k_tile_rows, dim3(blocks_for(ntiles + 1)), dim3(kBlock), 0, s, zeta, R, T, ntiles, trs);
+    HIPCHK(hipGetLastError());
 }
 
 Part make_part_like(Alloc& al, const Part& base, int T, hipStream_t s)
