@@ -243,6 +243,67 @@ def test_eps_to_zero_limit():
     assert gaps[0] > gaps[1] > gaps[2] >= -1e-10
 
 
+def test_c_dense_cost_is_pinned():
+    """clib.dense_cost_1d (the W1 of the converged references in
+    tests/golden): after a converged solve it lies within the closed-form
+    entropic bounds (integral of |F_mu - F_nu|), agrees with the NumPy plan's
+    sum of C o Gamma, scales with the coordinates, tends to the LP value as eps
+    shrinks, and drops below the bounds if its cost factor is dropped."""
+    rng = np.random.default_rng(31)
+    n, m = 150, 170
+    x = np.sort(rng.uniform(0, 1, n)); y = np.sort(rng.uniform(0, 1, m))
+    u = wl.normalise(rng.uniform(0.1, 1, n)); v = wl.normalise(rng.uniform(0.1, 1, m))
+    wstar = cf.w1_closed_form(x, u, y, v)
+    gaps = []
+    for eps in (1e-1, 3e-2, 1e-2):
+        f, g, it, err = clib.sinkhorn_1d(x, y, u, v, eps, 1e-11, 200000)
+        assert err <= 1e-11
+        w = clib.dense_cost_1d(x, y, f, g, eps, threads=2)
+        lo, hi = cf.entropic_w1_bounds(x, u, y, v, eps, err)
+        assert lo <= w <= hi, (eps, lo, w, hi)
+        G = dense.plan_1d(x, y, f, g, eps)
+        assert abs(np.sum(G * np.abs(x[:, None] - y[None, :])) - w) <= 1e-13 * w
+        # a planted mistake, the cost factor dropped, gives the plan's mass (1),
+        # which the bounds reject
+        assert abs(G.sum() - 1.0) <= 1e-10
+        assert not (lo <= G.sum() <= hi)
+        # coordinates and eps scaled by s: the same potentials scaled by s give s W1
+        w2 = clib.dense_cost_1d(2.0 * x, 2.0 * y, 2.0 * f, 2.0 * g, 2.0 * eps, threads=2)
+        assert abs(w2 - 2.0 * w) <= 1e-12 * w
+        gaps.append(w - wstar)
+    assert gaps[0] > gaps[1] > gaps[2] >= -1e-10
+    # the LP value (scipy HiGHS) is the eps -> 0 limit the gaps close on
+    lp = cf.w1_lp(x[:40], wl.normalise(u[:40]), y[:40], wl.normalise(v[:40]))
+    assert abs(lp - cf.w1_closed_form(x[:40], wl.normalise(u[:40]), y[:40], wl.normalise(v[:40]))) <= 1e-12
+
+
+def test_goldens_within_closed_form_bounds():
+    """The converged references of the timed workloads satisfy what the
+    mathematics fixes: error within tol, the u side exact, W1 inside the
+    closed-form entropic bounds (1D) and the LP-free bounds of the axis costs
+    (2D: each axis cost is at least its 1D marginal W1)."""
+    for name in ("graded_1d_2p20_eps1e-2.json", "graded_1d_2p20_eps1e-3.json"):
+        path = os.path.join(GOLD, name)
+        if not os.path.exists(path):
+            pytest.skip(f"{name} not written yet")
+        with open(path) as fh:
+            gd = json.load(fh)
+        p = wl.config_graded_1d(eps=gd["eps"])
+        assert gd["err"] <= gd["tol"] and gd["u_err"] <= 1e-12
+        lo, hi = cf.entropic_w1_bounds(p.x, p.u, p.y, p.v, p.eps, gd["err"])
+        assert lo <= gd["w1"] <= hi, (name, lo, gd["w1"], hi)
+    with open(os.path.join(GOLD, "tanh_2d_1024_eps5e-3.json")) as fh:
+        gd = json.load(fh)
+    p = wl.config_tanh_2d()
+    assert gd["err"] <= gd["tol"] and gd["u_err"] <= 1e-12
+    # marginal W1 of each axis is a lower bound of the 2D cost (|dx| + |dy| >=
+    # either term, and a coupling's axis marginals couple the axis marginals)
+    wx = cf.w1_closed_form(p.x1, p.u.sum(1), p.x2, p.v.sum(1))
+    wy = cf.w1_closed_form(p.y1, p.u.sum(0), p.y2, p.v.sum(0))
+    diam = 2.0
+    assert wx + wy - diam * gd["err"] <= gd["w1"], (wx + wy, gd["w1"])
+
+
 def test_iteration_cap_and_zero_iterations():
     p = wl.config_small_1d(n=64)
     r0 = dense.sinkhorn_1d(p.x, p.y, p.u, p.v, p.eps, 0.0, 0)
