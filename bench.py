@@ -56,6 +56,8 @@ TRAFFIC_RESIDENT = {"sources_sha256": "a8c0e16cbe0f876b096e625f9e19f5c9fe428c987
                     "fetch_kib": 419616.0, "write_kib": 201081.0, "n": 1 << 20}
 TRAFFIC_STREAM = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
                   "fetch_kib": (22818.1 + 18715.2) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
+# the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
+TRAFFIC_FP64 = {"sources_sha256": None, "fetch_kib": 0.0, "write_kib": 0.0, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
@@ -67,6 +69,38 @@ STREAM_SOURCES = RESIDENT_SOURCES[1:]
 TRAFFIC_PLAN = {"sources_sha256": "81b9b566466ba8e5e64e2344982331be9e619045dded8b616bc7067ae99449a2",
                 "fetch_kib": 1701.02, "write_kib": 5120010.0, "n": 25600}
 PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
+
+
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def golden(name):
+    """A converged reference result of the oracle (tests/golden, written by
+    oracle/make_goldens.py), or None if the file is absent."""
+    path = os.path.join(GOLDEN_DIR, name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def vs_oracle(res, name):
+    """Error of a result against the oracle's converged run of the same
+    workload: W1 relative, iteration counts, the oracle's own marginal error."""
+    gd = golden(name)
+    if gd is None:
+        return None
+    return {"w1_rel_err": abs(res["w1"] - gd["w1"]) / gd["w1"], "w1_oracle": gd["w1"],
+            "iters_oracle": gd["iters"], "iters_diff": int(res["iters"]) - int(gd["iters"]),
+            "marginal_err": res["marginal_err"], "marginal_err_oracle": gd["err"],
+            "golden": f"tests/golden/{name}"}
+
+
+def state_repr(res):
+    """What the loop kept as its iteration state (result field `fast`)."""
+    if res.get("fast", 0) in (1, 2, 3):
+        return "ext-f32 scalings (FP32 mantissa + int32 exponent)"
+    return "f64 log potentials"
 
 
 def sources_digest(paths):
@@ -164,6 +198,9 @@ def cpu_baseline(prob, seconds):
                            "sample": f"{iters} iterations of Algorithm 1 (FP64 log-form "
                                      f"recurrences, C) on the full workload in {dt:.2f} s"},
         "cpu_model": _cpu_model(),
+        "host_cpu_count": os.cpu_count(),
+        "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+        "threads_used": threads,
     }
 
 
@@ -232,7 +269,8 @@ def bench_tanh_2d(precision):
             "solve_ms": dt * 1e3, "iters": r["iters"], "w1": r["w1"],
             "marginal_err": r["marginal_err"], "converged": r["converged"],
             "loop_ms": r["loop_ms"], "iteration_us": r["loop_ms"] * 1e3 / max(1, r["iters"]),
-            "scan_mantissa": "fp32" if precision == 1 else "fp64",
+            "scan_mantissa": "fp32" if precision == 1 else "fp64", "state": state_repr(r),
+            "resumes": r["resumes"], "vs_oracle": vs_oracle(r, "tanh_2d_1024_eps5e-3.json"),
             "workload": "1024 x 1024 tanh mesh (beta 2.5), 4-component 2D GMM masses, "
                         "eps=5e-3, tol=1e-6"}
 
@@ -283,6 +321,7 @@ def bench_other_configs(precision):
         return {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
                 "iters": r["iters"], "w1": r["w1"], "marginal_err": r["marginal_err"],
                 "converged": r["converged"], "scan_mantissa": "fp32" if prec == 1 else "fp64",
+                "state": state_repr(r), "resumes": r["resumes"],
                 "resident": r["fast"] == 2, "loop_ms": r["loop_ms"]}
 
     # the headline workload on the streaming sweeps (the path taken by
@@ -310,8 +349,10 @@ def bench_other_configs(precision):
     p = wl.config_small_1d()
     out["small_1d_n512"] = run1d(p, 0)
     out["small_1d_n512"]["workload"] = "n=m=512 sorted U(0,1), masses U(0.1,1), eps=0.01, tol=1e-9, cap 2000"
+    out["small_1d_n512"]["vs_oracle"] = vs_oracle(out["small_1d_n512"], "small_1d_n512.json")
     p = wl.config_graded_1d(1 << 20, 1e-2)
     out["graded_1d_eps1e-2"] = run1d(p, precision)
+    out["graded_1d_eps1e-2"]["vs_oracle"] = vs_oracle(out["graded_1d_eps1e-2"], "graded_1d_2p20_eps1e-2.json")
     out["tanh_2d_1024"] = bench_tanh_2d(precision)
     out["random_3d_128"] = bench_random_3d(precision)
     return out
@@ -452,14 +493,29 @@ def bench_serving(precision, full):
 
 
 def _cpu_model():
+    """The host CPU as lscpu names it (model, sockets, cores, threads), else
+    /proc/cpuinfo's model name."""
+    import subprocess
+    info = {}
     try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "CPU(s)", "Vendor ID"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    if "Model name" not in info:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        info["Model name"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return info or {"Model name": "unknown"}
 
 
 def main():
@@ -566,9 +622,24 @@ def main():
         r64 = solve(0 if prec == 1 else 1)
         dt = time.perf_counter() - t0
         key = "fp64_scans" if prec == 1 else "fp32_scans"
-        extra[key] = {"value": pts * r64["iters"] / dt, "iters": r64["iters"],
-                      "w1": r64["w1"], "marginal_err": r64["marginal_err"],
+        extra[key] = {"value": pts * r64["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
+                      "iters": r64["iters"], "w1": r64["w1"], "marginal_err": r64["marginal_err"],
+                      "state": state_repr(r64), "resident": r64["fast"] == 2,
                       "w1_rel_diff_vs_headline": abs(r64["w1"] - last["w1"]) / r64["w1"]}
+        if key == "fp64_scans":
+            # the FP64 loop runs the streaming general sweeps (k_sweep with
+            # FP64 mantissas): the HBM roofline of the same 88 B per grid point
+            # per iteration, from the loop's HIP events over its sweeps
+            sw_s = r64["loop_ms"] * 1e-3 / max(1, r64["sweeps"])
+            gbs64 = per_sweep_bytes / sw_s / 1e9
+            extra[key]["roofline"] = {
+                "bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs64 / HBM_PEAK_GBS,
+                "traffic": measured_traffic(TRAFFIC_FP64, STREAM_SOURCES, args.n),
+                "kernel": "k_sweep<double, 256, 8, IN_LOG2, EPI_UPDATE_CHECK / EPI_UPDATE, NEXT_AGG>",
+                "avg_sweep_us": sw_s * 1e6, "algorithmic_bytes_per_sweep": per_sweep_bytes}
+        if args.n == 1 << 20 and args.tol == 1e-6:
+            extra[key]["vs_oracle"] = vs_oracle(r64, f"graded_1d_2p20_eps{args.eps:g}.json")
     if not args.no_dense:
         gin = torch.as_tensor(prob.eps * np.log(prob.v), dtype=torch.float64, device="cuda")
         out = torch.empty_like(x)
@@ -625,8 +696,13 @@ def main():
         "config": {"workload": f"1D W1 graded meshes n=m={args.n} (x=t^2, y=Chebyshev), "
                                f"3-GMM masses, eps={args.eps:g}, tol={args.tol:g}",
                    "n": args.n, "m": args.n, "eps": args.eps, "tol": args.tol,
-                   "scan_mantissa": args.precision, "state": "f64"},
+                   "scan_mantissa": args.precision, "state": state_repr(last),
+                   "stop_test": ("FP32-sum estimate, each stop confirmed by an FP64 check of the returned pair"
+                                 if prec == 1 else "FP64")},
         "iters_per_solve": its[-1], "w1": last["w1"], "marginal_err": last["marginal_err"],
+        "resumes": last["resumes"],
+        "vs_oracle": (vs_oracle(last, f"graded_1d_2p20_eps{args.eps:g}.json")
+                      if args.n == 1 << 20 and args.tol == 1e-6 else None),
         "p50_latency_ms": float(np.percentile(lat_ms, 50)),
         "p99_latency_ms": float(np.percentile(lat_ms, 99)),
         "roofline": roofline, "cpu_baseline": cpu, **extra,

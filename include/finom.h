@@ -52,8 +52,25 @@ typedef enum {
 
 /* Options. A NULL pointer means all defaults (zero-initialised struct). */
 typedef struct {
-    int32_t precision;  /* 0 = FP64 scans; 1 = FP32-mantissa scans. State, convergence
-                           check and cost are FP64 in both modes.                        */
+    int32_t precision;  /* 0 = FP64 scans, FP64 log potentials as state.
+                           1 = FP32-mantissa scans. The state is FP64 log potentials on
+                           the general sweeps (result fast = 0, 2D, d >= 3) and the
+                           scalings U = w 2^(-c/(eps ln 2)) as FP32 mantissa + int32
+                           exponent on the fast and resident sweeps (fast = 1, 2, 3).
+                           The loop head's stop test uses the loop's own FP32-sum
+                           estimate; every stop is then confirmed by an FP64 check of
+                           the returned pair (K^T phi with FP64 scans), which is the
+                           reported marginal_err and decides convergence (a rejected
+                           stop resumes the loop). The cost is FP64 in both modes.
+                        2 = the linear domain with the stored vector representation
+                           of section 2.2 (r_i per row, each column's lower- and
+                           upper-block entries), eq. p-DP / q-DP as FP64 scans of
+                           affine maps: no exponential or logarithm per iteration.
+                           sinkhorn_w1_1d and finom_matvec (domain 0) only; the
+                           scalings must fit FP64, so sinkhorn_w1_1d refuses
+                           (FINOM_E_ARG) meshes with (max - min coordinate) / eps >
+                           600, and a scaling that overflows or underflows on the
+                           way ends the loop with FINOM_E_NUMERIC.                   */
     int32_t domain;     /* matvec entry points only: 0 = linear (out = K in, in >= 0);
                            1 = log (in = eps ln psi, out = eps ln K psi).               */
     int32_t skip_checks;/* 1 = trust the inputs: no device-side sortedness / mass checks
@@ -64,7 +81,7 @@ typedef struct {
 typedef struct {
     double w1;            /* <C, Gamma> of the returned pair, FP64                       */
     double marginal_err;  /* ||diag(psi) K^T phi - v||_1 of the returned pair (loop-head
-                             check of Algorithm 1), FP64                                 */
+                             check of Algorithm 1), with FP64 scans in both modes        */
     int64_t iters;        /* completed iterations l                                      */
     int32_t converged;    /* marginal_err <= tol                                         */
     int32_t status;       /* the value the call returned                                 */
@@ -80,7 +97,9 @@ typedef struct {
                              else 0 (the streaming general sweeps). 0 for precision 0, 2D
                              and d >= 3 (sinkhorn_w1_nd with one axis reports as
                              sinkhorn_w1_1d); the server runs 0 or 1.                    */
-    int32_t reserved;
+    int32_t resumes;      /* precision 1: stops of the FP32 loop that the FP64 check of
+                             the returned pair rejected (the loop then went on); 0 for
+                             precision 0                                               */
 } finom_result;
 
 /*
@@ -96,6 +115,10 @@ typedef struct {
 int finom_matvec(const double* x_rows, int64_t n, const double* y_cols, int64_t m,
                  double eps, const double* in, double* out, const finom_opts* opts,
                  void* stream);
+/* (finom_matvec with opts->precision 2 evaluates the linear-domain product
+ * from the stored representation; domain must be 0, else FINOM_E_ARG.
+ * dense_matvec, finom_matvec_noalloc, sinkhorn_w1_2d, sinkhorn_w1_nd,
+ * finom_batch and the server accept precision 0 and 1 only.) */
 
 /*
  * The same product evaluated densely, O(n*m) kernel entries generated on the

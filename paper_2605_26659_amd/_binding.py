@@ -6,10 +6,12 @@ given. If the library is not built, importing the entry points raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import math
 import os
 import re
+import weakref
 from pathlib import Path
 
 _PKG = Path(__file__).resolve().parent
@@ -47,12 +49,13 @@ class Opts(C.Structure):
 class Result(C.Structure):
     _fields_ = [("w1", C.c_double), ("marginal_err", C.c_double), ("iters", C.c_int64),
                 ("converged", C.c_int32), ("status", C.c_int32), ("loop_ms", C.c_double),
-                ("sweeps", C.c_int64), ("fast", C.c_int32), ("reserved", C.c_int32)]
+                ("sweeps", C.c_int64), ("fast", C.c_int32), ("resumes", C.c_int32)]
 
     def as_dict(self):
         return {"w1": self.w1, "marginal_err": self.marginal_err, "iters": int(self.iters),
                 "converged": bool(self.converged), "status": int(self.status),
-                "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps), "fast": int(self.fast)}
+                "loop_ms": float(self.loop_ms), "sweeps": int(self.sweeps), "fast": int(self.fast),
+                "resumes": int(self.resumes)}
 
 
 class Problem(C.Structure):
@@ -146,7 +149,32 @@ def load(path: os.PathLike | None = None):
     L.finom_tile_config.argtypes = [C.c_int32, _i64]
     if path is None:
         _lib = L
+        atexit.register(_release_at_exit)
     return L
+
+
+_servers = weakref.WeakSet()
+
+
+def _release_at_exit():
+    """Before the interpreter and the HIP runtime shut down: stop live
+    servers, wait for the device, and free the library's cached device and
+    pinned workspace (finom_release), so nothing of the library is left for
+    the runtime's own teardown."""
+    if _lib is None:
+        return
+    for srv in list(_servers):
+        try:
+            srv.close()
+        except Exception:
+            pass
+    try:
+        torch = _torch()
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+        _lib.finom_release()
+    except Exception:
+        pass
 
 
 def strerror(status: int) -> str:
@@ -468,6 +496,7 @@ class FinomServer:
         _check(st, "finom_server_create")
         self._h = h
         self._keep = {}
+        _servers.add(self)
 
     def submit(self, d, sync=True) -> int:
         """Queues a problem; returns its ticket. With sync, torch's current

@@ -414,6 +414,7 @@ Engine::~Engine()
     arena_free(&ar_loop_);
     arena_free(&ar_cost_);
     arena_free(&ar_res_);
+    arena_free(&ar_chk_);
     if (ev0_) hipEventDestroy(ev0_);
     if (ev1_) hipEventDestroy(ev1_);
     if (cs_) hipStreamDestroy(cs_);
@@ -657,21 +658,23 @@ void Engine::solve_resident()
     }
 }
 
-void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen)
+void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen, bool resume)
 {
     std::vector<Job*> rj = jobs;
     // larger problems first: the tiles are handed out in this order
     std::stable_sort(rj.begin(), rj.end(), [](const Job* a, const Job* b) { return a->pk[0].ntiles > b->pk[0].ntiles; });
-    std::vector<Job*> rest;
-    for (Job* j : pending_init_)
-        if (std::find(rj.begin(), rj.end(), j) == rj.end()) rest.push_back(j);
-    pending_init_.swap(rest);
+    if (!resume) {
+        std::vector<Job*> rest;
+        for (Job* j : pending_init_)
+            if (std::find(rj.begin(), rj.end(), j) == rj.end()) rest.push_back(j);
+        pending_init_.swap(rest);
+    }
 
     Alloc al(&ar_res_, s_);
     std::vector<StateInit> ini;
     std::vector<int> first(1, 0);
     for (Job* j : rj) {
-        ini.push_back(StateInit{j->slot, 0, j->d.itr_max, j->d.tol});
+        if (!resume) ini.push_back(StateInit{j->slot, 0, j->d.itr_max, j->d.tol});
         first.push_back(first.back() + j->pk[0].ntiles);
     }
     const int total = first.back();
@@ -706,8 +709,9 @@ void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen)
     const ResidentArgs* d_args = upload_vec(al, args);
     const int* d_first = upload_vec(al, first);
     al.uploaded();
-    hipLaunchKernelGGL(k_init_states, dim3(blocks_for((long long)ini.size())), dim3(kBlock), 0, s_, d_ini,
-                       (int)ini.size(), ps_);
+    if (!ini.empty())
+        hipLaunchKernelGGL(k_init_states, dim3(blocks_for((long long)ini.size())), dim3(kBlock), 0, s_, d_ini,
+                           (int)ini.size(), ps_);
     HIPCHK(hipGetLastError());
     // records start at zero (tag 0: written 0 times)
     HIPCHK(hipMemsetAsync(rec, 0, 5 * (size_t)total * sizeof(unsigned long long), s_));
@@ -732,7 +736,7 @@ void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen)
     for (Job* j : rj) {
         j->resident = true;
         j->started = true;
-        j->loop_ms = ms;
+        j->loop_ms += ms;
     }
     if (*hfail) {
         set_last_error("resident solver: a grid wait exceeded its bound");
@@ -748,6 +752,11 @@ bool Engine::add(Job* j)
     max_slot_ = std::max(max_slot_, j->slot);
     j->loop_ms = 0.0;
     j->started = false;
+    j->shift = 0;
+    j->resumes = 0;
+    j->last_resume_l = -1;
+    j->resume_k = 0;
+    j->err64 = 0.0;
     active_.push_back(j);
     pending_init_.push_back(j);
     dirty_ = true;
@@ -1012,12 +1021,143 @@ void Engine::read_states()
     HIPCHK(hipStreamSynchronize(s_));
 }
 
+void Engine::confirm_stops(std::vector<Job*>& fin)
+{
+    std::vector<Job*> todo;
+    todo.swap(fin);
+    while (!todo.empty()) {
+        Alloc al(&ar_chk_, s_);
+        const int dummy = cap_;
+        // the returned pairs in FP64 log form (jobs on the fast state: phi, the
+        // checked psi and log2 v, in place)
+        std::vector<int> bo(todo.size());
+        std::vector<FastStateTask> ft;
+        for (size_t q = 0; q < todo.size(); ++q) {
+            Job* j = todo[q];
+            bo[q] = j->resident ? 0 : psi_slot(hps_[j->slot].iters, j->shift);
+            if (!j->fast && !j->gen) continue;
+            const double kappa = 1.0 / (j->d.eps * kLn2);
+            FastStateTask t;
+            memset(&t, 0, sizeof(t));
+            t.mode = 2;
+            t.b = kappa;
+            t.out = j->F; t.mesh = j->d.x1; t.n = j->p.na; ft.push_back(t);
+            t.out = j->G[bo[q]]; t.mesh = j->d.x2; t.n = j->p.nb; ft.push_back(t);
+            memset(&t, 0, sizeof(t));
+            t.mode = 3;
+            t.out = j->lv; t.in = j->d.v; t.n = j->p.nb; ft.push_back(t);
+        }
+        enqueue_fast_state(al, ft, s_);
+        // K^T phi with FP64 scans and the check: 1D lines and 2D y-lines by
+        // tile shape, after the 2D x-lines; each job's partials contiguous
+        std::map<int, Sweep> x2d, chk1d, chk2d;
+        std::vector<SegTask> segs;
+        double* err_d = al.dev<double>(todo.size());
+        int P = 0;
+        for (size_t q = 0; q < todo.size(); ++q) {
+            Job* j = todo[q];
+            const JobDesc& d = j->d;
+            const int b = bo[q];
+            const int base = P;
+            if (d.dim == 1) {
+                Sweep& sw = chk1d[j->p.cfg[0]];
+                LineDesc a = make_line(d.x2, d.n2, d.x1, d.n1, j->pkt[0].zeta, j->pkt[0].trs, j->pkt[0].T, d.eps);
+                a.gin = j->F; a.out = j->G[1 - b]; a.a0 = j->lv; a.a1 = d.v; a.a2 = j->G[b];
+                a.prob = dummy;
+                a.dec_part_off = -1;
+                a.part_base = P;
+                P += a.ntiles;
+                sw.lines.push_back(a);
+            } else {
+                add_2d_kt_x_lines(x2d[j->p.cfg[0]], j->pkt[0], d.eps, j->F, d.n1, j->S, d.m1, dummy);
+                Sweep& sw = chk2d[j->p.cfg[1]];
+                const size_t q0 = sw.lines.size();
+                add_2d_kt_y_lines(sw, j->pkt[1], d.eps, j->S, d.m1, j->G[1 - b], d.m2, j->lvr, j->vr, j->G[b], d.n2,
+                                  dummy);
+                for (size_t k = q0; k < sw.lines.size(); ++k) {
+                    sw.lines[k].part_base = P;
+                    P += sw.lines[k].ntiles;
+                }
+            }
+            segs.push_back(SegTask{base, P - base, err_d + q});
+        }
+        double* partial = al.dev<double>(std::max(P, 1));
+        for (auto* m : {&x2d, &chk1d, &chk2d})
+            for (auto& kv : *m) {
+                kv.second.cfg = kv.first;
+                kv.second.epi = (m == &x2d) ? EPI_STORE_LOG2 : EPI_UPDATE_CHECK;
+                upload_sweep(al, kv.second, sizeof(Ext<double>));
+            }
+        const SegTask* d_segs = upload_vec(al, segs);
+        double* err_h = al.host<double>(todo.size());
+        al.uploaded();
+        for (auto& kv : x2d) launch_sweep(0, IN_LOG2, kv.second, ps_, nullptr, nullptr, 0, s_);
+        for (auto* m : {&chk1d, &chk2d})
+            for (auto& kv : *m) launch_sweep(0, IN_LOG2, kv.second, ps_, partial, nullptr, 0, s_);
+        hipLaunchKernelGGL(k_segment_sums, dim3((unsigned)segs.size()), dim3(kBlock), 0, s_, partial, d_segs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(err_h, err_d, sizeof(double) * todo.size(), hipMemcpyDeviceToHost, s_));
+        HIPCHK(hipStreamSynchronize(s_));
+
+        // confirmed stops, and the jobs that resume from the same pair (back
+        // in their own representation)
+        std::vector<Job*> again[2];   // resident, by variant
+        ft.clear();
+        for (size_t q = 0; q < todo.size(); ++q) {
+            Job* j = todo[q];
+            const ProbState& st = hps_[j->slot];
+            j->err64 = err_h[q];
+            const long long l = st.iters;
+            if (!(j->err64 > j->d.tol) || l >= j->d.itr_max || !std::isfinite(j->err64) || st.status ||
+                !may_resume(l, j->last_resume_l)) {
+                fin.push_back(j);
+                continue;
+            }
+            if (j->fast || j->gen) {
+                const double kappa = 1.0 / (j->d.eps * kLn2);
+                FastStateTask t;
+                memset(&t, 0, sizeof(t));
+                t.mode = 4;
+                t.b = kappa;
+                t.out = j->F; t.mesh = j->d.x1; t.n = j->p.na; ft.push_back(t);
+                t.out = j->G[bo[q]]; t.mesh = j->d.x2; t.n = j->p.nb; ft.push_back(t);
+                memset(&t, 0, sizeof(t));
+                t.mode = 1;
+                t.out = j->lv; t.in = j->d.v; t.n = j->p.nb; ft.push_back(t);
+            }
+            if (bo[q] == 1)
+                HIPCHK(hipMemcpyAsync(j->G[0], j->G[1], sizeof(double) * j->p.nb, hipMemcpyDeviceToDevice, s_));
+            j->shift = (int)(l & 1);
+            j->resume_k = resume_step(j->resume_k);
+            enqueue_rearm(ps_ + j->slot, l, resume_until(l, j->resume_k, j->d.itr_max), s_);
+            j->last_resume_l = l;
+            ++j->resumes;
+            if (j->resident) again[j->gen ? 1 : 0].push_back(j);
+            // streaming jobs go on in the next rounds: their lines are still
+            // listed, and the aggregates of their phi are those of the last
+            // update, which no later sweep has touched
+        }
+        enqueue_fast_state(al, ft, s_);
+        al.uploaded();
+        todo.clear();
+        for (int gen = 0; gen < 2; ++gen)
+            if (!again[gen].empty()) {
+                run_resident_batch(again[gen], gen != 0, true);
+                todo.insert(todo.end(), again[gen].begin(), again[gen].end());
+            }
+    }
+}
+
 std::vector<Job*> Engine::harvest()
 {
     std::vector<Job*> fin;
     for (Job* j : active_)
         if (j->started && hps_[j->slot].done) fin.push_back(j);
     if (fin.empty()) return fin;
+    if (precision_ == 1) {
+        confirm_stops(fin);
+        if (fin.empty()) return fin;
+    }
 
     Alloc al(&ar_cost_, s_);
     const int dummy = cap_;
@@ -1035,25 +1175,13 @@ std::vector<Job*> Engine::harvest()
     std::vector<SegTask> segs;
     std::vector<ScaleTask> sc;
     std::vector<long long> sc_n;
-    // the fast sweeps' state back to log potentials, in place, before the costs
-    std::vector<FastStateTask> ft;
-    for (Job* j : fin) {
-        if (!j->fast && !j->gen) continue;
-        const double kappa = 1.0 / (j->d.eps * kLn2);
-        FastStateTask t;
-        memset(&t, 0, sizeof(t));
-        t.mode = 2;
-        t.b = kappa;
-        t.out = j->F; t.mesh = j->d.x1; t.n = j->p.na; ft.push_back(t);
-        t.out = j->resident ? j->G[0] : j->G[hps_[j->slot].iters & 1]; t.mesh = j->d.x2; t.n = j->p.nb;
-        ft.push_back(t);
-    }
-    enqueue_fast_state(al, ft, s_);
+    // the fast sweeps' state is in log form already: only FP32 jobs run on
+    // it, and the FP64 check of their stop converted the returned pair
     int P = 0;
     for (Job* j : fin) {
         const JobDesc& d = j->d;
         const ProbState& st = hps_[j->slot];
-        double* Gf = j->resident ? j->G[0] : j->G[st.iters & 1];
+        double* Gf = j->resident ? j->G[0] : j->G[psi_slot(st.iters, j->shift)];
         const double eps = d.eps;
         const int base = P;
         if (d.dim == 1) {
@@ -1118,9 +1246,16 @@ std::vector<Job*> Engine::harvest()
         r.marginal_err = st.err;
         r.iters = st.iters;
         r.converged = st.converged;
-        r.sweeps = j->d.dim == 1 ? 2 * st.iters + 1 : 4 * st.iters + 2;
+        int bad = st.status;
+        if (precision_ == 1) {
+            r.marginal_err = j->err64;
+            r.converged = (j->err64 <= j->d.tol) ? 1 : 0;
+            if (!std::isfinite(j->err64)) bad = 1;
+        }
+        r.sweeps = j->d.dim == 1 ? 2 * st.iters + 1 + j->resumes : 4 * st.iters + 2 + 2 * j->resumes;
         r.loop_ms = j->loop_ms;
-        r.status = st.status ? FINOM_E_NUMERIC : (st.converged ? FINOM_OK : FINOM_NOT_CONVERGED);
+        r.resumes = j->resumes;
+        r.status = bad ? FINOM_E_NUMERIC : (r.converged ? FINOM_OK : FINOM_NOT_CONVERGED);
         r.fast = j->fast ? (j->resident ? 2 : 1) : (j->gen ? 3 : 0);
         free_slots_.push(j->slot);
         j->slot = -1;

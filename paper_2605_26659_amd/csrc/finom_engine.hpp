@@ -66,6 +66,12 @@ struct Job {
                                 // variant (state as for the fast sweeps); only when the engine solves resident
     bool resident = false;      // solved by the resident batch kernel (final psi in G[0])
     bool started = false;       // its iteration state has been set (harvest looks at it only then)
+    int shift = 0;              // streaming loop resumed after a rejected stop: psi of iteration l in
+                                // G[(l & 1) ^ shift]
+    int resumes = 0;            // stops the FP64 check rejected
+    long long last_resume_l = -1;   // iteration of the last rejected stop
+    long long resume_k = 0;         // iterations run after it
+    double err64 = 0.0;         // FP32 mode: the FP64 check of the returned pair
     Part pk[2], pkt[2], pc[2];   // per axis: K, K^T, cost partition of K
     void bind();
     double points() const { return 0.5 * (double)(p.na + p.nb); }
@@ -107,7 +113,13 @@ public:
 
 private:
     void rebuild();
-    void run_resident_batch(const std::vector<Job*>& rj, bool gen);
+    // resume: the jobs' states are already armed (a stop the FP64 check
+    // rejected); otherwise they are initialised
+    void run_resident_batch(const std::vector<Job*>& rj, bool gen, bool resume = false);
+    // FP32 mode: the FP64 check of every stopped job's returned pair; jobs
+    // that fail it before their cap resume (the resident ones are solved on
+    // here, the streaming ones go on in the next rounds) and leave `fin`
+    void confirm_stops(std::vector<Job*>& fin);
     void launch_iterations(int k, hipStream_t s);
     void read_states();
 
@@ -123,7 +135,7 @@ private:
     std::vector<Job*> active_;      // live jobs, in join order
     std::vector<Job*> pending_init_;   // joined since the last rebuild
     std::vector<Job*> listed_;      // jobs in the current launch lists
-    Arena ar_setup_, ar_loop_, ar_cost_, ar_res_;
+    Arena ar_setup_, ar_loop_, ar_cost_, ar_res_, ar_chk_;
     std::vector<std::unique_ptr<Sweep>> sweeps_;
     std::vector<Sweep*> seq_[2];
     std::vector<bool> dec_[2];

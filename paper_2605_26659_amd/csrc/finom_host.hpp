@@ -11,6 +11,7 @@
 #include <new>
 #include <vector>
 
+#include "../../include/finom.h"
 #include "finom_fast.hpp"
 #include "finom_kernels.hpp"
 
@@ -298,7 +299,9 @@ bool resident_fits(long long n, long long m, int T, bool gen);
 // Conversions for the fast sweeps' state, one thread per element:
 //   mode 0: out = 2^{a + b in_k} as Ext<float> (B = 2^{2 c kappa}, the initial state);
 //   mode 1: out = in_k as Ext<float> (masses);
-//   mode 2: out = log2(state_k) + b mesh_k as double, in place over the Ext<float> state.
+//   mode 2: out = log2(state_k) + b mesh_k as double, in place over the Ext<float> state;
+//   mode 3: out = log2(in_k) as double (masses back to FP64 log masses, in place over mode 1's output);
+//   mode 4: the inverse of mode 2, in place: the Ext<float> state 2^(out_k - b mesh_k).
 struct FastStateTask {
     void* out;
     const double* in;
@@ -321,6 +324,50 @@ bool setup_fast_1d(Alloc& al, const Part& pk, const Part& pkt, double* lu, doubl
                    bool convert_always = false);
 
 constexpr double kCoordLimit = 33554432.0;   // 2^25: bound on |coordinate| / (eps ln 2)
+
+// ---------------------------------------------------------------------------
+// FP32 mode: the stop of Algorithm 1's loop head confirmed in FP64.
+// The FP32 loops decide with their own estimate of the marginal error (FP32
+// sums, a few units of 2^-24 per entry of K^T phi). When one stops, the
+// returned pair is checked again with FP64 scans (the general sweep with FP64
+// mantissas): ||diag(psi_old) K^T phi - v||_1 in FP64. That value is the
+// reported error and decides convergence; if it exceeds tol before the cap,
+// the loop resumes from the same pair with a lower threshold for its estimate
+// (resume_threshold) and stops again later, to be checked again.
+// ---------------------------------------------------------------------------
+// Where a loop whose stop the FP64 check rejected at iteration l stops next:
+// it runs k more iterations with its own estimate's stop switched off and is
+// checked again; k doubles from 1 at each rejection of the same solve (at most
+// 64), never past the cap. The FP64 error of an FP32 pair carries the FP32
+// rounding of its states (about 1e-7 on unit mass), so its decrease over one
+// iteration near tol is no guide to how many more are needed; doubling reaches
+// any count in a logarithmic number of checks and overshoots it at most 2x.
+inline long long resume_step(long long k_prev) { return k_prev < 1 ? 1 : std::min<long long>(64, 2 * k_prev); }
+inline long long resume_until(long long l, long long k, long long cap) { return std::min(cap, l + k); }
+// ---------------------------------------------------------------------------
+// Precision 2: the linear domain with the stored vector representation of
+// section 2.2 (finom_linear.hip)
+// ---------------------------------------------------------------------------
+// Whether the mode's scalings fit FP64 for a mesh spanning [lo, hi].
+bool linear_span_ok(double lo, double hi, double eps);
+// K w for the product of partition p (rows p.xr, columns p.yc), linear.
+void linear_matvec(Alloc& al, const Part& p, double eps, const double* w, double* out, int cfg, hipStream_t s);
+// Algorithm 1 with the linear-domain products: phi (n), psi[2] (m) scalings;
+// *ret_psi is the psi buffer of the returned pair.
+int linear_loop(Alloc& al, const Part& pk, const Part& pkt, int cfg, const double* u, const double* v, double eps,
+                long long itr_max, int k, double* phi, double* psi[2], ProbState* ps, ProbState* hps,
+                hipStream_t s, finom_result* res, int* ret_psi);
+
+// A rejected stop resumes only if the loop has advanced since the last resume
+// (a guard: every resume runs at least one iteration).
+inline bool may_resume(long long l, long long last_resume_l) { return l > last_resume_l; }
+// A streaming loop resumed at a graph's first iteration (parity 0): psi of
+// iteration l sits in G[(l & 1) ^ shift], shift = (l_resume & 1).
+inline int psi_slot(long long l, int shift) { return (int)((l & 1) ^ shift); }
+// Re-arms a stopped state for a resumed loop: not done, the estimate's stop
+// off (threshold -1), stop at iteration itr_stop, iteration l in both
+// counter slots (iters keeps l: the resident solver starts from it).
+void enqueue_rearm(ProbState* ps, long long l, long long itr_stop, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Line builders shared by the single-problem solvers and the batch engine

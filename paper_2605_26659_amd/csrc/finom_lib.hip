@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <cstdio>
+#include <functional>
 #include <mutex>
 
 #include "../../include/finom.h"
@@ -558,10 +559,24 @@ __global__ __launch_bounds__(kBlock) void k_fast_state(const FastStateTask* __re
         int e = 0;
         const double fr = frexp(t.in[k], &e);
         ((Ext<float>*)t.out)[k] = Ext<float>{(float)fr, e};
-    } else {
+    } else if (t.mode == 2) {
         const Ext<float> u = ((const Ext<float>*)t.out)[k];
         ((double*)t.out)[k] =
             (u.m > 0.f) ? log2((double)u.m) + (double)u.e + t.b * t.mesh[k] : -__builtin_inf();
+    } else if (t.mode == 3) {
+        ((double*)t.out)[k] = log2(t.in[k]);
+    } else {
+        // the inverse of mode 2 in FP64: 2^(s - floor s) in [1, 2) rounded to
+        // FP32 and normalised. A state that mode 2 converted comes back with
+        // the same bits: the log form is off by at most 2^-27 in absolute
+        // terms (|c kappa| < 2^25), well inside half an FP32 unit.
+        const double s = ((const double*)t.out)[k] - t.b * t.mesh[k];
+        Ext<float> u = ext_zero<float>();
+        if (s > -__builtin_inf()) {
+            const double fl = floor(s);
+            u = ext_norm(Ext<float>{(float)exp2(s - fl), (int)fl});
+        }
+        ((Ext<float>*)t.out)[k] = u;
     }
 }
 
@@ -581,6 +596,25 @@ void enqueue_fast_state(Alloc& al, const std::vector<FastStateTask>& tasks, hipS
     HIPCHK(hipMemcpyAsync(dt, ht, sizeof(FastStateTask) * nt, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(df, hf, sizeof(int) * (nt + 1), hipMemcpyHostToDevice, s));
     if (hf[nt] > 0) hipLaunchKernelGGL(k_fast_state, dim3(hf[nt]), dim3(kBlock), 0, s, dt, df, nt);
+    HIPCHK(hipGetLastError());
+}
+
+__global__ void k_rearm(ProbState* __restrict__ p, long long l, long long itr_stop)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p->done = 0;
+        p->converged = 0;
+        p->tol = -1.0;
+        p->itr_max = itr_stop;
+        p->cnt[0] = l;
+        p->cnt[1] = l;
+        p->iters = l;
+    }
+}
+
+void enqueue_rearm(ProbState* ps, long long l, long long itr_stop, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, s, ps, l, itr_stop);
     HIPCHK(hipGetLastError());
 }
 
@@ -674,8 +708,12 @@ struct LoopSpec {
     std::vector<bool> decides[2];      // sweep takes the stop decision
 };
 
+// on_stop (optional) runs when the state reports a stop; it returns true
+// after re-arming the state for more iterations (a stop that the FP64 check
+// rejected), and the replays go on.
 static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* partial,
-                    long long itr_max, int k, hipStream_t s, ProbState* hps, finom_result* res)
+                    long long itr_max, int k, hipStream_t s, ProbState* hps, finom_result* res,
+                    const std::function<bool()>& on_stop = {})
 {
     k += (k & 1);   // even, so every replay starts on parity 0
     hipStream_t cs = nullptr;
@@ -697,14 +735,20 @@ static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* pa
         HIPCHK(hipEventCreate(&ev0));
         HIPCHK(hipEventCreate(&ev1));
         HIPCHK(hipEventRecord(ev0, s));
-        const long long max_launches = itr_max / k + 2;
+        long long max_launches = itr_max / k + 2;
         long long launches = 0;
         for (;;) {
             HIPCHK(hipGraphLaunch(exec, s));
             ++launches;
             HIPCHK(hipMemcpyAsync(hps, ps, sizeof(ProbState), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            if (hps->done) break;
+            if (hps->done) {
+                if (on_stop && on_stop()) {
+                    ++max_launches;   // the resumed iteration may start a replay of its own
+                    continue;
+                }
+                break;
+            }
             if (launches > max_launches) {   // only if the device state were corrupt
                 st = FINOM_E_HIP;
                 break;
@@ -840,8 +884,9 @@ static int matvec_impl(bool dense, const double* x, int64_t n, const double* y, 
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (!x || !y || !in || !out || n < 1 || m < 1 || !finite_pos(eps)) return FINOM_E_ARG;
-    if (o.precision != 0 && o.precision != 1) return FINOM_E_ARG;
+    if (o.precision < 0 || o.precision > 2) return FINOM_E_ARG;
     if (o.domain != 0 && o.domain != 1) return FINOM_E_ARG;
+    if (o.precision == 2 && (dense || o.domain != 0)) return FINOM_E_ARG;   // the linear mode is linear
     if (n + m > (int64_t)INT32_MAX) return FINOM_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     try {
@@ -874,6 +919,13 @@ static int matvec_impl(bool dense, const double* x, int64_t n, const double* y, 
             }
 #undef DK
             HIPCHK(hipGetLastError());
+            return FINOM_OK;
+        }
+        if (o.precision == 2) {
+            const int cfg = tuned_cfg(0, n + m);
+            const Part p = make_part(al, x, n, y, m, kCfgs[cfg].T(), s);
+            linear_matvec(al, p, eps, in, out, cfg, s);
+            al.uploaded();
             return FINOM_OK;
         }
         const int cfg = tuned_cfg(o.precision, n + m);
@@ -995,14 +1047,16 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
     };
     if (!x || !y || !u || !v || n < 1 || m < 1 || !finite_pos(eps)) return fail(FINOM_E_ARG);
     if (!(tol >= 0.0) || !std::isfinite(tol) || itr_max < 0) return fail(FINOM_E_ARG);
-    if (o.precision != 0 && o.precision != 1) return fail(FINOM_E_ARG);
+    if (o.precision < 0 || o.precision > 2) return fail(FINOM_E_ARG);
     if (n + m > (int64_t)INT32_MAX) return fail(FINOM_E_ARG);
     hipStream_t s = (hipStream_t)stream;
+    const bool linear = o.precision == 2;
     try {
         Alloc al(stream);
         // the tile shape does not depend on the kernel that runs the tiles,
-        // so a problem gets the same tiles alone and in a batch
-        const int cfg = tuned_cfg(o.precision, n + m);
+        // so a problem gets the same tiles alone and in a batch (the linear
+        // mode takes the FP64 table's shapes)
+        const int cfg = tuned_cfg(linear ? 0 : o.precision, n + m);
         const int T = kCfgs[cfg].T();
         const bool try_resident = o.precision == 1 && fast_allowed() && resident_fits(n, m, T, false);
         const bool try_gen = o.precision == 1 && fast_allowed() && resident_fits(n, m, T, true);
@@ -1031,6 +1085,19 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             }
             if (st != FINOM_OK) return fail(st);
         }
+        if (linear) {
+            // the linear mode's scalings fit FP64 only for diam / eps <= 600
+            double* h = al.host<double>(4);
+            HIPCHK(hipMemcpyAsync(h, x, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h + 1, x + n - 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h + 2, y, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(h + 3, y + m - 1, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (!linear_span_ok(std::min(h[0], h[2]), std::max(h[1], h[3]), eps)) {
+                set_last_error("linear mode (precision 2): diam / eps exceeds 600");
+                return fail(FINOM_E_ARG);
+            }
+        }
 
         // dividing indices (Algorithm 1, first step) on one merge-path
         // partition shared by both products
@@ -1057,7 +1124,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             ft[0].out = F; ft[0].in = x; ft[0].n = n; ft[0].a = -log2((double)n); ft[0].b = -kappa;
             ft[1].out = G[0]; ft[1].in = y; ft[1].n = m; ft[1].a = -log2((double)m); ft[1].b = -kappa;
             enqueue_fast_state(al, ft, s);
-        } else {
+        } else if (!linear) {
             enqueue_fill(F, n, -log2((double)n), s);
             enqueue_fill(G[0], m, -log2((double)m), s);
         }
@@ -1065,21 +1132,98 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
         const bool resident = (try_resident && fast) || gen;
-        if (resident) {
-            al.uploaded();
-            const int st = run_resident(al, pk, pkt, (Ext<float>*)F, (Ext<float>*)G[0], (const Ext<float>*)lu,
-                                        (const Ext<float>*)lv, Bx, By, ps, hps, s, res, gen);
-            if (st != FINOM_OK) return fail(st);
-        }
         const int nparts = std::max(pkt.ntiles, pc.ntiles);
         double* partial = al.dev<double>(nparts);
+
+        // FP32 mode: every stop is confirmed by the FP64 check of the pair it
+        // returns (K^T phi with FP64 scans), with the state in log form
+        const bool confirm = o.precision == 1;
+        double* part64 = confirm ? al.dev<double>(pkt.ntiles) : nullptr;
+        double* err64_d = confirm ? al.dev<double>(1) : nullptr;
+        double* err64_h = confirm ? al.host<double>(1) : nullptr;
+        Sweep chk64[2];   // by the buffer holding the checked psi
+        for (int bo = 0; bo < 2 && confirm; ++bo) {
+            chk64[bo].epi = EPI_UPDATE_CHECK;
+            chk64[bo].cfg = cfg;
+            LineDesc a = make_line(y, m, x, n, pkt.zeta, pkt.trs, T, eps);
+            a.gin = F; a.out = G[1 - bo]; a.a0 = lv; a.a1 = v; a.a2 = G[bo];
+            a.prob = 1;
+            a.dec_part_off = -1;
+            chk64[bo].lines.push_back(a);
+            assign_parts(chk64[bo], 0);
+            upload_sweep(al, chk64[bo], sizeof(Ext<double>));
+        }
+        int shift = 0;          // psi of iteration l in G[(l & 1) ^ shift] (streaming loop)
+        int resumes = 0;
+        long long last_l = -1;   // iteration of the last rejected stop
+        long long step = 0;      // iterations run after it
+        double err64 = 0.0;
+        // the pair in (F, G[bo]) to FP64 log form (and log2 v beside it) or back
+        auto ext_convert = [&](int bo, bool to_log) {
+            std::vector<FastStateTask> ft(3);
+            memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
+            ft[0].out = F; ft[0].mesh = x; ft[0].n = n; ft[0].b = kappa; ft[0].mode = to_log ? 2 : 4;
+            ft[1].out = G[bo]; ft[1].mesh = y; ft[1].n = m; ft[1].b = kappa; ft[1].mode = to_log ? 2 : 4;
+            ft[2].out = lv; ft[2].in = v; ft[2].n = m; ft[2].mode = to_log ? 3 : 1;
+            enqueue_fast_state(al, ft, s);
+        };
+        // Called at a stop (hps[0] read): true when the loop is re-armed
+        auto on_stop = [&]() -> bool {
+            const long long l = hps[0].iters;
+            const int bo = resident ? 0 : psi_slot(l, shift);
+            if (ext_state) ext_convert(bo, true);
+            launch_sweep(0, IN_LOG2, chk64[bo], ps, part64, nullptr, 0, s);
+            hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, part64, 0, pkt.ntiles,
+                               err64_d);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(err64_h, err64_d, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            err64 = *err64_h;
+            if (!(err64 > tol) || l >= itr_max || !std::isfinite(err64) || hps[0].status ||
+                !may_resume(l, last_l))
+                return false;
+            // resume from the same pair, in its own representation
+            if (ext_state) ext_convert(bo, false);
+            if (bo == 1) HIPCHK(hipMemcpyAsync(G[0], G[1], sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+            shift = (int)(l & 1);
+            step = resume_step(step);
+            enqueue_rearm(ps, l, resume_until(l, step, itr_max), s);
+            last_l = l;
+            ++resumes;
+            return true;
+        };
+        if (resident) {
+            al.uploaded();
+            double ms_total = 0.0;
+            for (;;) {
+                const int st = run_resident(al, pk, pkt, (Ext<float>*)F, (Ext<float>*)G[0], (const Ext<float>*)lu,
+                                            (const Ext<float>*)lv, Bx, By, ps, hps, s, res, gen);
+                if (st != FINOM_OK) return fail(st);
+                ms_total += res->loop_ms;
+                if (!on_stop()) break;
+            }
+            res->loop_ms = ms_total;
+        }
+        int lin_psi = 0;
+        if (linear) {
+            al.uploaded();
+            const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((n + m) / 2);
+            const int st = linear_loop(al, pk, pkt, cfg, u, v, eps, itr_max, kit, F, G, ps, hps, s, res, &lin_psi);
+            if (st != FINOM_OK) return fail(st);
+            // the returned pair to log2 potentials for the cost and the outputs
+            std::vector<FastStateTask> ft(2);
+            memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
+            ft[0].out = F; ft[0].in = F; ft[0].n = n; ft[0].mode = 3;
+            ft[1].out = G[lin_psi]; ft[1].in = G[lin_psi]; ft[1].n = m; ft[1].mode = 3;
+            enqueue_fast_state(al, ft, s);
+        }
         // tile aggregates: each product's epilogue writes the other's
         const bool multi = pk.ntiles > 1;
         void* agg_k = multi ? (void*)al.dev<char>((size_t)pk.ntiles * 2 * eb) : nullptr;
         void* agg_kt = multi ? (void*)al.dev<char>((size_t)pk.ntiles * 2 * eb) : nullptr;
 
         Sweep kt[2], kk[2];
-        for (int b = 0; b < 2 && !resident; ++b) {
+        for (int b = 0; b < 2 && !resident && !linear; ++b) {
             kt[b].epi = EPI_UPDATE_CHECK;
             kt[b].cfg = cfg;
             kt[b].agg_from_prev = multi;
@@ -1105,7 +1249,7 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
             upload_sweep(al, kt[b], eb);
             upload_sweep(al, kk[b], eb);
         }
-        if (!resident) {
+        if (!resident && !linear) {
             al.uploaded();
             // aggregates of the initial phi for the first K^T phi
             launch_aggregate(o.precision, IN_LOG2, kt[0], ps, s);
@@ -1116,14 +1260,16 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
                 lp.decides[b] = {false, true};
             }
             const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((n + m) / 2);
-            const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
+            const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res,
+                                    confirm ? std::function<bool()>(on_stop) : std::function<bool()>());
             if (st != FINOM_OK) return fail(st);
         }
 
-        // returned pair (F, G[l % 2]) (the resident solver leaves it in
-        // (F, G[0])); <C, Gamma> from the FP64 moment sums
-        double* Gf = resident ? G[0] : G[hps[0].iters & 1];
-        if (ext_state) {
+        // returned pair (F, G[psi_slot]) (the resident solver leaves it in
+        // (F, G[0])), in log form (the FP64 check has converted it already);
+        // <C, Gamma> from the FP64 moment sums
+        double* Gf = linear ? G[lin_psi] : resident ? G[0] : G[psi_slot(hps[0].iters, shift)];
+        if (ext_state && !confirm) {
             std::vector<FastStateTask> ft(2);
             memset(ft.data(), 0, ft.size() * sizeof(FastStateTask));
             ft[0].out = F; ft[0].mesh = x; ft[0].n = n; ft[0].b = kappa; ft[0].mode = 2;
@@ -1147,7 +1293,14 @@ int sinkhorn_w1_1d(const double* x, int64_t n, const double* y, int64_t m, const
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (confirm) {
+            hps[0].err = err64;
+            hps[0].converged = (err64 <= tol) ? 1 : 0;
+            if (!std::isfinite(err64)) hps[0].status = 1;
+        }
         finish_result(res, hps[0], hps[1].w1);
+        res->sweeps += resumes;
+        res->resumes = resumes;
         res->fast = fast ? (resident ? 2 : 1) : (gen ? 3 : 0);
         if (hps[0].status) return fail(FINOM_E_NUMERIC);
         return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
@@ -1262,7 +1415,54 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         }
         const long long ncost = 2LL * m1 * pxc.ntiles;
         double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
+
+        // FP32 mode: every stop is confirmed by the FP64 check of the pair it
+        // returns (K^T phi along x then y with FP64 scans)
+        const bool confirm = o.precision == 1;
+        Sweep ktx64, kty64[2];   // kty64 by the buffer holding the checked psi
+        double* part64 = confirm ? al.dev<double>(nchk) : nullptr;
+        double* err64_d = confirm ? al.dev<double>(1) : nullptr;
+        double* err64_h = confirm ? al.host<double>(1) : nullptr;
+        if (confirm) {
+            ktx64.cfg = cfg_x;
+            ktx64.epi = EPI_STORE_LOG2;
+            add_2d_kt_x_lines(ktx64, px_t, eps, F, n1, S, m1, 1);
+            upload_sweep(al, ktx64, sizeof(Ext<double>));
+            for (int bo = 0; bo < 2; ++bo) {
+                kty64[bo].cfg = cfg_y;
+                kty64[bo].epi = EPI_UPDATE_CHECK;
+                add_2d_kt_y_lines(kty64[bo], py_t, eps, S, m1, G[1 - bo], m2, lvr, vr, G[bo], n2, 1);
+                assign_parts(kty64[bo], 0);
+                upload_sweep(al, kty64[bo], sizeof(Ext<double>));
+            }
+        }
         al.uploaded();
+        int shift = 0;          // psi of iteration l in G[(l & 1) ^ shift]
+        int resumes = 0;
+        long long last_l = -1;   // iteration of the last rejected stop
+        long long step = 0;      // iterations run after it
+        double err64 = 0.0;
+        auto on_stop = [&]() -> bool {
+            const long long l = hps[0].iters;
+            const int bo = psi_slot(l, shift);
+            launch_sweep(0, IN_LOG2, ktx64, ps, nullptr, nullptr, 0, s);
+            launch_sweep(0, IN_LOG2, kty64[bo], ps, part64, nullptr, 0, s);
+            hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, part64, 0, nchk, err64_d);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(err64_h, err64_d, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            err64 = *err64_h;
+            if (!(err64 > tol) || l >= itr_max || !std::isfinite(err64) || hps[0].status ||
+                !may_resume(l, last_l))
+                return false;
+            if (bo == 1) HIPCHK(hipMemcpyAsync(G[0], G[1], sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
+            shift = (int)(l & 1);
+            step = resume_step(step);
+            enqueue_rearm(ps, l, resume_until(l, step, itr_max), s);
+            last_l = l;
+            ++resumes;
+            return true;
+        };
 
         LoopSpec lp;
         for (int b = 0; b < 2; ++b) {
@@ -1270,12 +1470,13 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
             lp.decides[b] = {false, false, true, false};
         }
         const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((na + nb) / 2);
-        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
+        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res,
+                                confirm ? std::function<bool()>(on_stop) : std::function<bool()>());
         if (st != FINOM_OK) return fail(st);
 
         // <C, Gamma> = sum Phi o (M_x Psi K_y^T) + sum Phi o (K_x Psi M_y^T), M = C o K,
         // each product along y first, as in the loop
-        double* Gf = G[hps[0].iters & 1];
+        double* Gf = G[psi_slot(hps[0].iters, shift)];
         Sweep cy_p, cx_m, cy_m, cx_p;
         cy_p.kind = 1; cy_p.epi = EPI_STORE_LOG2;
         add_2d_k_y_lines(cy_p, pyc, eps, Gf, m2, S, m1, n2);
@@ -1302,8 +1503,14 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (confirm) {
+            hps[0].err = err64;
+            hps[0].converged = (err64 <= tol) ? 1 : 0;
+            if (!std::isfinite(err64)) hps[0].status = 1;
+        }
         finish_result(res, hps[0], hps[1].w1);
-        res->sweeps = 4 * hps[0].iters + 2;
+        res->sweeps = 4 * hps[0].iters + 2 + 2 * resumes;
+        res->resumes = resumes;
         if (hps[0].status) return fail(FINOM_E_NUMERIC);
         return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
     } catch (...) {
@@ -1515,7 +1722,51 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         }
         const long long ncost = (long long)d * (na / n_src[0]) * pc[0].ntiles;
         double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
+
+        // FP32 mode: every stop is confirmed by the FP64 check of the pair it
+        // returns (K^T phi along every axis with FP64 scans)
+        const bool confirm = o.precision == 1;
+        std::vector<Sweep> kt64[2];   // by the buffer holding the checked psi
+        double* part64 = confirm ? al.dev<double>(nchk) : nullptr;
+        double* err64_d = confirm ? al.dev<double>(1) : nullptr;
+        double* err64_h = confirm ? al.host<double>(1) : nullptr;
+        for (int bo = 0; bo < 2 && confirm; ++bo) {
+            kt64[bo].resize(d);
+            for (int k = 0; k < d; ++k) {
+                kt64[bo][k].cfg = cfg[k];
+                kt64[bo][k].epi = k == d - 1 ? EPI_UPDATE_CHECK : EPI_STORE_LOG2;
+            }
+            add_product(kt64[bo].data(), true, pkt, F, G[1 - bo], lvr, vr, G[bo], 1);
+            assign_parts(kt64[bo][d - 1], 0);
+            for (int k = 0; k < d; ++k) upload_sweep(al, kt64[bo][k], sizeof(Ext<double>));
+        }
         al.uploaded();
+        int shift = 0;          // psi of iteration l in G[(l & 1) ^ shift]
+        int resumes = 0;
+        long long last_l = -1;   // iteration of the last rejected stop
+        long long step = 0;      // iterations run after it
+        double err64 = 0.0;
+        auto on_stop = [&]() -> bool {
+            const long long l = hps[0].iters;
+            const int bo = psi_slot(l, shift);
+            for (int k = 0; k < d; ++k)
+                launch_sweep(0, IN_LOG2, kt64[bo][k], ps, k == d - 1 ? part64 : nullptr, nullptr, 0, s);
+            hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, part64, 0, nchk, err64_d);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(err64_h, err64_d, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            err64 = *err64_h;
+            if (!(err64 > tol) || l >= itr_max || !std::isfinite(err64) || hps[0].status ||
+                !may_resume(l, last_l))
+                return false;
+            if (bo == 1) HIPCHK(hipMemcpyAsync(G[0], G[1], sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
+            shift = (int)(l & 1);
+            step = resume_step(step);
+            enqueue_rearm(ps, l, resume_until(l, step, itr_max), s);
+            last_l = l;
+            ++resumes;
+            return true;
+        };
 
         LoopSpec lp;
         for (int b = 0; b < 2; ++b) {
@@ -1529,12 +1780,13 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
             }
         }
         const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((na + nb) / 2);
-        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res);
+        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res,
+                                confirm ? std::function<bool()>(on_stop) : std::function<bool()>());
         if (st != FINOM_OK) return fail(st);
 
         // <C, Gamma> with C = sum_c |x_c - y_c|: pass c is the product K psi
         // with the moment kernel C_c o K_c along axis c, summed against phi
-        double* Gf = G[hps[0].iters & 1];
+        double* Gf = G[psi_slot(hps[0].iters, shift)];
         std::vector<Sweep> cs((size_t)d * d);
         int nparts = 0;
         for (int c = 0; c < d; ++c) {
@@ -1556,8 +1808,14 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(hps, ps, 2 * sizeof(ProbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (confirm) {
+            hps[0].err = err64;
+            hps[0].converged = (err64 <= tol) ? 1 : 0;
+            if (!std::isfinite(err64)) hps[0].status = 1;
+        }
         finish_result(res, hps[0], hps[1].w1);
-        res->sweeps = 2LL * d * hps[0].iters + d;
+        res->sweeps = 2LL * d * hps[0].iters + d + (long long)d * resumes;
+        res->resumes = resumes;
         if (hps[0].status) return fail(FINOM_E_NUMERIC);
         return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
     } catch (...) {

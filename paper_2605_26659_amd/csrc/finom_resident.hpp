@@ -493,6 +493,12 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
     int& s_flag = L.flag;
     const int T = a.T;
     const int nt = a.ntiles;
+    // the loop's bounds and its first iteration (0, or where a stop that the
+    // FP64 check rejected left it), read before this block publishes anything,
+    // so before tile 0 can record the stop
+    const long long itr_max = a.ps->itr_max;
+    const double tol = a.ps->tol;
+    long long l = a.ps->iters;
     unsigned long long* rec_x = a.rec;                       // totals of the x points' column terms
     unsigned long long* rec_y = a.rec + 2 * (size_t)nt;      // totals of the y points' column terms
     unsigned long long* rec_p = a.rec + 4 * (size_t)nt;      // partial errors of the checking sweep
@@ -560,9 +566,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
                              nullptr, 0);
     }
 
-    const long long itr_max = a.ps->itr_max;
-    const double tol = a.ps->tol;
-    long long l = 0;
+    long long it = 0;   // iterations of this launch: the records' tags count from the launch
     double err = 0.0;
     bool ok = true;
     ResidentIn in;
@@ -571,8 +575,8 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         // ---- K^T phi with the marginal check: columns x, rows y
         resident_columns<BLOCK, IPT, GEN>(nc, nr, own_l.e, own_u.e, U, B, s_l, s_u, s_f, s_tmp);
         const int rxl = own_l.e, rxu = own_u.e;
-        // records of this iteration's sweeps: write l + 1 of their buffers
-        const unsigned tag = (unsigned)((l + 1) & 1);
+        // records of this iteration's sweeps: write it + 1 of their buffers
+        const unsigned tag = (unsigned)((it + 1) & 1);
         __builtin_amdgcn_s_setprio(2);
         resident_read<false>(a, tile, rec_x, nullptr, tag, &s_flag, 0.0, in);
         block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.0, s_f + 2 * NW,
@@ -623,6 +627,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
                              rec_of(own_u, tag ^ 1u), nullptr, 0);
         __builtin_amdgcn_s_setprio(0);
         ++l;
+        ++it;
     }
     // the returned pair: the current phi (and the psi the loop head checked,
     // written above)

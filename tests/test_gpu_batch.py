@@ -18,7 +18,7 @@ import pytest
 from oracle import clib, dense
 from paper_2605_26659_amd import workloads as wl
 
-from gpuhelp import dev, host
+from gpuhelp import check_slack, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -222,12 +222,17 @@ def test_uneven_4096_problem_workload():
         assert abs(r["iters"] - ito) <= max(3, 0.01 * ito), (i, r["iters"], ito)
         assert r["converged"] == (erro <= p.tol)
         if not r["converged"]:
-            # the loop head's error in FP32: each term |psi_old (K^T phi) - v|
-            # carries a few 2^-24 v, so the sum (mass 1) is good to ~3e-7
+            # at the cap: the FP64 check of the FP32 pair against the oracle's
+            # pair, off by the FP32 iterates' rounding (mass 1: ~3e-7)
             assert abs(r["marginal_err"] - erro) <= 3e-7 + 1e-4 * erro, (i, r["marginal_err"], erro)
-        # marginals of the returned pair, recomputed by the oracle
+        # marginals of the returned pair, recomputed by the oracle: the
+        # reported error is their FP64 check, within tol when converged
         f, g = host(d["f_out"]), host(d["g_out"])
         s = dense.logmatvec(p.x, p.y, g, p.eps)
         t = dense.logmatvec(p.y, p.x, f, p.eps)
         assert np.sum(np.abs(np.exp((f + s) / p.eps) - p.u)) <= 1e-6
-        assert np.sum(np.abs(np.exp((g + t) / p.eps) - p.v)) <= max(2e-6, 1.01 * erro)
+        err_r = np.sum(np.abs(np.exp((g + t) / p.eps) - p.v))
+        slack = check_slack(g, t, p.eps, p.v)
+        assert abs(r["marginal_err"] - err_r) <= slack, (i, r["marginal_err"], err_r)
+        if r["converged"]:
+            assert err_r <= p.tol + slack, (i, err_r)

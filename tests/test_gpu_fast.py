@@ -80,10 +80,18 @@ def test_fast_and_general_converge_to_the_same_plan(monkeypatch):
     r1, f1, g1 = _solve(p, tol=1e-6, itr_max=20000)
     monkeypatch.setenv("FINOM_FAST", "0")
     r0, f0, g0 = _solve(p, tol=1e-6, itr_max=20000)
+    r64, f64, g64 = _solve(p, tol=1e-6, itr_max=20000, precision=0)
     assert r1["fast"] == 1 and not r0["fast"]
     assert r1["converged"] and r0["converged"]
     assert abs(r1["w1"] - r0["w1"]) <= 1e-6 * r0["w1"]
-    assert abs(r1["iters"] - r0["iters"]) <= max(3, 0.01 * r0["iters"])
+    # each FP32 path stops where the FP64 check of its own pair passes. The
+    # fast sweeps' pairs track the FP64 loop's error to a few %: within
+    # max(3, 1 %) of its count. The general sweeps' FP32-mantissa exp2 / log2
+    # leave an error floor of about 2.5e-7 on unit mass, so their FP64 error
+    # reaches tol = 1e-6 when the FP64 loop's is near 0.75e-6: ln(1/0.75) / the
+    # asymptotic rate more iterations (~5 at eps = 1e-2), within max(8, 3 %).
+    assert abs(r1["iters"] - r64["iters"]) <= max(3, 0.01 * r64["iters"]), (r1["iters"], r64["iters"])
+    assert abs(r0["iters"] - r64["iters"]) <= max(8, 0.03 * r64["iters"]), (r0["iters"], r64["iters"])
     assert np.max(np.abs(f1 - f0)) / p.eps <= 1e-4
 
 

@@ -21,7 +21,7 @@ import pytest
 from oracle import clib
 from paper_2605_26659_amd import workloads as wl
 
-from gpuhelp import dev, host
+from gpuhelp import check_slack, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -41,9 +41,12 @@ def _against_oracle(p, iters):
     assert res["iters"] == iters
     assert np.max(np.abs(f - fo)) / p.eps <= TOL_ITER
     assert np.max(np.abs(g - go)) / p.eps <= TOL_ITER
-    # the check runs in FP32: each term |psi_old (K^T phi) - v| carries an
-    # absolute error of a few 2^-24 v (the states themselves are FP32-accurate),
-    # so the sum (total mass 1) is good to ~3e-7 absolute
+    # the reported error is the FP64 check of the returned FP32 pair: equal to
+    # the oracle's recomputation from (f, g), and off the oracle's own pair by
+    # the FP32 iterates' rounding (a few 2^-24 per term, mass 1: ~3e-7)
+    t = clib.finom_logmatvec(p.y, p.x, f, p.eps)
+    err_r = np.sum(np.abs(np.exp((g + t) / p.eps) - p.v))
+    assert abs(res["marginal_err"] - err_r) <= check_slack(g, t, p.eps, p.v)
     assert abs(res["marginal_err"] - erro) <= 3e-7 + 1e-4 * erro
     return res
 
@@ -91,10 +94,16 @@ def test_extended_variant_and_general_sweeps_converge_to_the_same_plan(monkeypat
     rr, fr, gr = _solve(p, 1e-6, 20000)
     monkeypatch.setenv("FINOM_RESIDENT", "0")
     rs, fs, gs = _solve(p, 1e-6, 20000)
+    r64, _, _ = _solve(p, 1e-6, 20000, precision=0)
     assert rr["fast"] == 3 and rs["fast"] == 0
     assert rr["converged"] and rs["converged"]
     assert abs(rr["w1"] - rs["w1"]) <= 1e-6 * rs["w1"]
-    assert abs(rr["iters"] - rs["iters"]) <= max(3, 0.01 * rs["iters"])
+    # each stops where the FP64 check of its own pair passes: the resident
+    # variant within max(3, 1 %) of the FP64 loop's count, the general sweeps
+    # (FP32-mantissa exp2 / log2, an error floor of about 2.5e-7 on unit mass)
+    # within max(8, 3 %)
+    assert abs(rr["iters"] - r64["iters"]) <= max(3, 0.01 * r64["iters"]), (rr["iters"], r64["iters"])
+    assert abs(rs["iters"] - r64["iters"]) <= max(8, 0.03 * r64["iters"]), (rs["iters"], r64["iters"])
     assert np.max(np.abs(fr - fs)) / p.eps <= 1e-4
 
 
