@@ -57,7 +57,8 @@ TRAFFIC_RESIDENT = {"sources_sha256": "a8c0e16cbe0f876b096e625f9e19f5c9fe428c987
 TRAFFIC_STREAM = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
                   "fetch_kib": (22818.1 + 18715.2) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
 # the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
-TRAFFIC_FP64 = {"sources_sha256": None, "fetch_kib": 0.0, "write_kib": 0.0, "n": 1 << 20}
+TRAFFIC_FP64 = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
+                "fetch_kib": (19660.5 + 28045.7) / 2, "write_kib": (8279.98 + 8346.41) / 2, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
@@ -94,6 +95,11 @@ def vs_oracle(res, name):
             "iters_oracle": gd["iters"], "iters_diff": int(res["iters"]) - int(gd["iters"]),
             "marginal_err": res["marginal_err"], "marginal_err_oracle": gd["err"],
             "golden": f"tests/golden/{name}"}
+
+
+def graded_golden(eps):
+    """The reference file of the graded 2^20 workload at this eps, if any."""
+    return {1e-2: "graded_1d_2p20_eps1e-2.json", 1e-3: "graded_1d_2p20_eps1e-3.json"}.get(eps, "none.json")
 
 
 def state_repr(res):
@@ -355,6 +361,43 @@ def bench_other_configs(precision):
     out["graded_1d_eps1e-2"]["vs_oracle"] = vs_oracle(out["graded_1d_eps1e-2"], "graded_1d_2p20_eps1e-2.json")
     out["tanh_2d_1024"] = bench_tanh_2d(precision)
     out["random_3d_128"] = bench_random_3d(precision)
+    out.update(bench_linear())
+    return out
+
+
+def bench_linear():
+    """The linear-domain mode (precision 2: the stored vector representation,
+    FP64 affine-map scans, no exponential per iteration) on the small 1D case
+    and on the graded 2^20 workload at eps = 1e-2 (diam / eps = 100; at
+    eps = 1e-3 the mode refuses the mesh). One timed solve after a warm-up."""
+    import torch
+    from paper_2605_26659_amd import sinkhorn_w1_1d, workloads as wl
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    out = {}
+    for key, p, gold in (("small_1d_n512_linear", wl.config_small_1d(), "small_1d_n512.json"),
+                         ("graded_1d_eps1e-2_linear", wl.config_graded_1d(1 << 20, 1e-2),
+                          "graded_1d_2p20_eps1e-2.json")):
+        x, y, u, v = dev(p.x), dev(p.y), dev(p.u), dev(p.v)
+        sinkhorn_w1_1d(x, y, u, v, p.eps, p.tol, p.itr_max, precision=2, want_potentials=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, _, _ = sinkhorn_w1_1d(x, y, u, v, p.eps, p.tol, p.itr_max, precision=2, want_potentials=False)
+        dt = time.perf_counter() - t0
+        n, m = len(p.x), len(p.y)
+        # per iteration: K^T phi reads phi, eta, eta' (columns x) and r, v,
+        # psi_old (rows y) and writes psi; K psi reads psi, eta, eta'
+        # (columns y) and r, u (rows x) and writes phi: 48 n + 56 m bytes
+        per_sweep = (48.0 * n + 56.0 * m) / 2.0
+        sw_s = r["loop_ms"] * 1e-3 / max(1, r["sweeps"])
+        gbs = per_sweep / sw_s / 1e9
+        out[key] = {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
+                    "iters": r["iters"], "w1": r["w1"], "marginal_err": r["marginal_err"],
+                    "converged": r["converged"], "mode": "linear domain, stored representation, FP64",
+                    "loop_ms": r["loop_ms"], "vs_oracle": vs_oracle(r, gold),
+                    "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                                 "kernel": "k_lin_aggregate + k_lin_sweep per half-iteration",
+                                 "avg_sweep_us": sw_s * 1e6, "algorithmic_bytes_per_sweep": per_sweep}}
     return out
 
 
@@ -487,8 +530,10 @@ def bench_serving(precision, full):
     for i, fr in enumerate(fracs):
         out["runs"].append(_serve(descs, work, fr * cap_rate, 3.0 if full else 2.0, precision,
                                   budget, 100 + i))
-    if full:
-        out["runs"].append(_serve(descs, work, 2000.0, 1.0, precision, budget, 200, drain_s=120.0))
+    # the configuration's nominal rate (Poisson, 2000 requests/s): a short
+    # window by default, offered and served load side by side
+    out["runs"].append(_serve(descs, work, 2000.0, 1.0 if full else 0.5, precision, budget, 200,
+                              drain_s=120.0 if full else 30.0))
     return out
 
 
@@ -636,10 +681,10 @@ def main():
                 "bound": "hbm", "achieved": gbs64, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs64 / HBM_PEAK_GBS,
                 "traffic": measured_traffic(TRAFFIC_FP64, STREAM_SOURCES, args.n),
-                "kernel": "k_sweep<double, 256, 8, IN_LOG2, EPI_UPDATE_CHECK / EPI_UPDATE, NEXT_AGG>",
+                "kernel": "k_sweep<double, 256, 4, IN_LOG2, EPI_UPDATE_CHECK / EPI_UPDATE, NEXT_AGG>",
                 "avg_sweep_us": sw_s * 1e6, "algorithmic_bytes_per_sweep": per_sweep_bytes}
         if args.n == 1 << 20 and args.tol == 1e-6:
-            extra[key]["vs_oracle"] = vs_oracle(r64, f"graded_1d_2p20_eps{args.eps:g}.json")
+            extra[key]["vs_oracle"] = vs_oracle(r64, graded_golden(args.eps))
     if not args.no_dense:
         gin = torch.as_tensor(prob.eps * np.log(prob.v), dtype=torch.float64, device="cuda")
         out = torch.empty_like(x)
@@ -701,7 +746,7 @@ def main():
                                  if prec == 1 else "FP64")},
         "iters_per_solve": its[-1], "w1": last["w1"], "marginal_err": last["marginal_err"],
         "resumes": last["resumes"],
-        "vs_oracle": (vs_oracle(last, f"graded_1d_2p20_eps{args.eps:g}.json")
+        "vs_oracle": (vs_oracle(last, graded_golden(args.eps))
                       if args.n == 1 << 20 and args.tol == 1e-6 else None),
         "p50_latency_ms": float(np.percentile(lat_ms, 50)),
         "p99_latency_ms": float(np.percentile(lat_ms, 99)),
