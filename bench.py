@@ -56,6 +56,8 @@ TRAFFIC_RESIDENT = {"sources_sha256": "a8c0e16cbe0f876b096e625f9e19f5c9fe428c987
                     "fetch_kib": 419616.0, "write_kib": 201081.0, "n": 1 << 20}
 TRAFFIC_STREAM = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
                   "fetch_kib": (22818.1 + 18715.2) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
+# the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per sweep
+TRAFFIC_STREAM_2P24 = {"sources_sha256": None, "fetch_kib": 0.0, "write_kib": 0.0, "n": 1 << 24}
 # the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
 TRAFFIC_FP64 = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
                 "fetch_kib": (19660.5 + 28045.7) / 2, "write_kib": (8279.98 + 8346.41) / 2, "n": 1 << 20}
@@ -148,6 +150,8 @@ def parse():
                     help="only the 3D 128^3 record (two warm-ups and one timed solve)")
     ap.add_argument("--tanh-2d-only", action="store_true",
                     help="only the 2D 1024 x 1024 tanh-mesh record (one warm-up and one timed solve)")
+    ap.add_argument("--stream-2p24-only", action="store_true",
+                    help="only the 2^24 streaming record (a warm-up and one timed 100-iteration solve)")
     ap.add_argument("--plan-only", action="store_true",
                     help="only the plan export / plan difference record (--steps launches each)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2605_26659_amd", "tune_gfx950.txt"),
@@ -271,14 +275,55 @@ def bench_tanh_2d(precision):
     t0 = time.perf_counter()
     r, _, _ = sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
     dt = time.perf_counter() - t0
+    dense2d = bench_dense_2d(p, r["iters"], p.points * r["iters"] / dt)
     return {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s",
             "solve_ms": dt * 1e3, "iters": r["iters"], "w1": r["w1"],
-            "marginal_err": r["marginal_err"], "converged": r["converged"],
+            "marginal_err": r["marginal_err"], "converged": r["converged"], "dense_2d": dense2d,
             "loop_ms": r["loop_ms"], "iteration_us": r["loop_ms"] * 1e3 / max(1, r["iters"]),
             "scan_mantissa": "fp32" if precision == 1 else "fp64", "state": state_repr(r),
             "resumes": r["resumes"], "vs_oracle": vs_oracle(r, "tanh_2d_1024_eps5e-3.json"),
             "workload": "1024 x 1024 tanh mesh (beta 2.5), 4-component 2D GMM masses, "
                         "eps=5e-3, tol=1e-6"}
+
+
+def bench_dense_2d(p, iters, finom_rate):
+    """The 2D dense baselines on the same workload: one product timed with HIP
+    events on the stream it runs on; an iteration is two products, and the
+    iterates equal FINOM's, so time to tolerance = 2 x product x FINOM's
+    iteration count. Per axis: two FP64 matrix products on the matrix cores
+    (roofline against the FP64 matrix peak); full: the (NM)^2 product with
+    one exponential per kernel entry."""
+    import torch
+    from paper_2605_26659_amd import dense_matvec_2d
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    x1, y1, x2, y2 = dev(p.x1), dev(p.y1), dev(p.x2), dev(p.y2)
+    g = dev((p.eps * np.log(p.v)).ravel(order="F"))
+    out = torch.empty(p.u.size, dtype=torch.float64, device="cuda")
+    n1, m1 = p.u.shape
+    n2, m2 = p.v.shape
+    res = {}
+    for full, reps in ((False, 5), (True, 1)):
+        dense_matvec_2d(x1, y1, x2, y2, p.eps, g, out, full=full)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            dense_matvec_2d(x1, y1, x2, y2, p.eps, g, out, full=full)
+        e1.record(s)
+        torch.cuda.synchronize()
+        prod_s = e0.elapsed_time(e1) * 1e-3 / reps
+        rate = p.points / (2.0 * prod_s)
+        rec = {"product_s": prod_s, "per_iteration_s": 2 * prod_s, "time_to_tol_s": 2 * prod_s * iters,
+               "value": rate, "unit": "grid-pt*iters/s", "finom_speedup": finom_rate / rate}
+        if not full:
+            flops = 2.0 * (n1 * n2 * m2 + n1 * m2 * m1)
+            tf = flops / prod_s / 1e12
+            rec["roofline"] = {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
+                               "frac": tf / 78.6, "kernel": "k_dense2d_gemm (FP64 MFMA 16x16x4) x 2 "
+                                                            "+ the shift kernels", "flops_per_product": flops}
+        res["full_on_the_fly" if full else "per_axis_mfma"] = rec
+    return res
 
 
 def bench_random_3d(precision):
@@ -361,8 +406,42 @@ def bench_other_configs(precision):
     out["graded_1d_eps1e-2"]["vs_oracle"] = vs_oracle(out["graded_1d_eps1e-2"], "graded_1d_2p20_eps1e-2.json")
     out["tanh_2d_1024"] = bench_tanh_2d(precision)
     out["random_3d_128"] = bench_random_3d(precision)
+    out["graded_1d_2p24_streaming"] = bench_stream_2p24(precision)
     out.update(bench_linear())
     return out
+
+
+def bench_stream_2p24(precision, iters=100):
+    """The graded 1D workload at n = m = 2^24 (eps = 1e-3): too large for the
+    resident solver, so it runs the streaming sweeps, with a working set of
+    about 1.5 GB, far beyond the 256 MB Infinity Cache. A fixed count of
+    iterations (tol 0) after a warm-up solve; the HBM roofline of its sweeps
+    from the loop's HIP events."""
+    import torch
+    from paper_2605_26659_amd import sinkhorn_w1_1d, workloads as wl
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    n = 1 << 24
+    p = wl.config_graded_1d(n, 1e-3, tol=0.0, itr_max=iters)
+    x, y, u, v = dev(p.x), dev(p.y), dev(p.u), dev(p.v)
+    del p
+    sinkhorn_w1_1d(x, y, u, v, 1e-3, 0.0, 4, precision=precision, want_potentials=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, _, _ = sinkhorn_w1_1d(x, y, u, v, 1e-3, 0.0, iters, precision=precision, want_potentials=False)
+    dt = time.perf_counter() - t0
+    per_sweep = ((BYTES_KT[0] + BYTES_K[0]) * n + (BYTES_KT[1] + BYTES_K[1]) * n) / 2.0
+    sw_s = r["loop_ms"] * 1e-3 / max(1, r["sweeps"])
+    gbs = per_sweep / sw_s / 1e9
+    return {"value": n * r["iters"] / dt, "unit": "grid-pt*iters/s", "solve_ms": dt * 1e3,
+            "iters": r["iters"], "w1": r["w1"], "marginal_err": r["marginal_err"], "state": state_repr(r),
+            "fast": r["fast"], "loop_ms": r["loop_ms"],
+            "workload": "graded 1D n=m=2^24 (x=t^2, y=Chebyshev), 3-GMM masses, eps=1e-3, "
+                        f"{iters} iterations (tol 0)",
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(TRAFFIC_STREAM_2P24, STREAM_SOURCES, n),
+                         "kernel": "k_sweep_fast, both half-iteration variants, averaged over the loop",
+                         "avg_sweep_us": sw_s * 1e6, "algorithmic_bytes_per_sweep": per_sweep}}
 
 
 def bench_linear():
@@ -589,6 +668,9 @@ def main():
         return
     if args.tanh_2d_only:
         print(json.dumps(bench_tanh_2d(1 if args.precision == "fp32" else 0)), flush=True)
+        return
+    if args.stream_2p24_only:
+        print(json.dumps(bench_stream_2p24(1 if args.precision == "fp32" else 0)), flush=True)
         return
     if args.random_3d_only:
         print(json.dumps(bench_random_3d(1 if args.precision == "fp32" else 0)), flush=True)

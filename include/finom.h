@@ -129,6 +129,27 @@ int dense_matvec(const double* x_rows, int64_t n, const double* y_cols, int64_t 
                  double eps, const double* in, double* out, const finom_opts* opts,
                  void* stream);
 
+/*
+ * The 2D dense baselines (section 4's standard Sinkhorn on tensor meshes,
+ * eq. 2d-kron), log domain: out = eps ln (K e^{in/eps}) for the kernel
+ * K((k,i),(l,j)) = exp(-(|x1_k - x2_l| + |y1_i - y2_j|)/eps) from the target
+ * grid x2 (n2) x y2 (m2) to the source grid x1 (n1) x y1 (m1). in: n2*m2 and
+ * out: n1*m1 column-major (element (l, j) at l + j*n2). K^T is the same call
+ * with the grids swapped.
+ *   full = 0: per axis, vec(K_x E K_y^T) as two dense FP64 matrix products on
+ *     the matrix cores, every kernel entry generated as its tile is loaded;
+ *     each operand is shifted by its column (row) maximum so that the linear
+ *     values stay in FP64 while exp(-diam/eps) does not underflow.
+ *   full = 1: the (n1 m1) x (n2 m2) product with one exponential per kernel
+ *     entry and a running maximum per output (vector units).
+ * Meshes need not be sorted. Asynchronous on `stream`; full = 0 uses the
+ * per-stream workspace (16 (n1 + n2) m2 bytes). Errors: FINOM_E_ARG,
+ * FINOM_E_NOMEM, FINOM_E_HIP.
+ */
+int dense_matvec_2d(const double* x1, int64_t n1, const double* y1, int64_t m1,
+                    const double* x2, int64_t n2, const double* y2, int64_t m2,
+                    double eps, const double* in, double* out, int32_t full, void* stream);
+
 /* Largest n + m that finom_matvec_noalloc accepts (2^22 merged points). */
 #define FINOM_NOALLOC_MAX_POINTS 4194304
 
@@ -346,7 +367,7 @@ void finom_server_destroy(finom_server* srv);
  * 2^9 .. 2^21 elements (batches that fill the GPU, update sweeps) and keeps the
  * fastest per size class for all later calls in the process. With cache_path,
  * results are read from that file if it exists and written to it otherwise.
- * The environment variable FINOM_TILE_CFG (0..2) overrides every choice.
+ * The environment variable FINOM_TILE_CFG (0..4) overrides every choice.
  */
 int finom_autotune(int32_t precision, const char* cache_path, void* stream);
 /* The tile-shape index used for a line of `merged` = rows + columns elements. */

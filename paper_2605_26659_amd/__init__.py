@@ -7,7 +7,7 @@ generates seeded synthetic workloads.
 from ._binding import (  # noqa: F401
     FINOM_E_ADMIT, FINOM_E_ARG, FINOM_E_HIP, FINOM_E_MASS, FINOM_E_NOMEM,
     FINOM_E_NUMERIC, FINOM_E_UNSORTED, FINOM_NOT_CONVERGED, FINOM_OK, FinomError,
-    LIB_PATH, declared_functions, dense_matvec, finom_matvec, finom_matvec_noalloc, finom_release,
+    LIB_PATH, declared_functions, dense_matvec, dense_matvec_2d, finom_matvec, finom_matvec_noalloc, finom_release,
     finom_version, load, sinkhorn_w1_1d, sinkhorn_w1_2d, strerror,
     FinomServer, finom_autotune, finom_batch, finom_footprint, finom_tile_config,
     problem_1d, problem_2d, with_outputs,

@@ -117,6 +117,7 @@ def load(path: os.PathLike | None = None):
     L.finom_matvec.argtypes = [_vp, _i64, _vp, _i64, _d, _vp, _vp, C.POINTER(Opts), _vp]
     L.dense_matvec.argtypes = L.finom_matvec.argtypes
     L.finom_matvec_noalloc.argtypes = L.finom_matvec.argtypes
+    L.dense_matvec_2d.argtypes = [_vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _d, _vp, _vp, C.c_int32, _vp]
     L.sinkhorn_w1_1d.argtypes = [_vp, _i64, _vp, _i64, _vp, _vp, _d, _d, _i64, C.POINTER(Opts),
                                  _vp, _vp, C.POINTER(Result), _vp]
     L.finom_strerror.restype = C.c_char_p
@@ -255,6 +256,23 @@ def dense_matvec(x_rows, y_cols, eps, inp, out=None, *, precision=0, domain=0,
                              y_cols.numel(), float(eps), _dev(inp, "in"), _dev(out, "out"),
                              C.byref(_opts(precision, domain, skip_checks)), _stream_ptr(stream))
     _check(st, "dense_matvec")
+    return out
+
+
+def dense_matvec_2d(x1, y1, x2, y2, eps, inp, out=None, *, full=False, stream=None):
+    """eps ln (K e^{in/eps}) on tensor meshes, densely: the per-axis matrix
+    products on the matrix cores (full=False) or the full (n1 m1) x (n2 m2)
+    product (full=True). in: n2*m2, out: n1*m1, flat column-major."""
+    torch = _torch()
+    n1, m1, n2, m2 = x1.numel(), y1.numel(), x2.numel(), y2.numel()
+    if inp.numel() != n2 * m2:
+        raise ValueError("in holds n2 * m2 values")
+    if out is None:
+        out = torch.empty(n1 * m1, dtype=torch.float64, device=x1.device)
+    st = load().dense_matvec_2d(_dev(x1, "x1"), n1, _dev(y1, "y1"), m1, _dev(x2, "x2"), n2, _dev(y2, "y2"), m2,
+                                float(eps), _dev(inp, "in"), _dev(out, "out"), int(bool(full)),
+                                _stream_ptr(stream))
+    _check(st, "dense_matvec_2d")
     return out
 
 

@@ -1,8 +1,10 @@
 // Tile-shape autotuner. For each length class of merged lines (2^9 .. 2^21
 // elements) it times the update sweep of a batch of lines that fills the GPU
 // (2^22 merged elements in all, distinct meshes and potentials per line) with
-// every tile shape, and keeps the fastest shape for the class. The choice only
-// changes how the work is tiled, never what is computed.
+// every tile shape, and keeps the fastest shape for the class. In FP32, where
+// some shape lets a line of the class run on the resident solver, only such
+// shapes compete. The choice only changes how the work is tiled, never what is
+// computed.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -223,11 +225,22 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
             hipLaunchKernelGGL(k_tune_exp, dim3(blocks_for(count * n)), dim3(kBlock), 0, s, A.Y, count * n,
                                2.0 / kLn2, A.EY);
             HIPCHK(hipGetLastError());
-            double tbest = 0.0;
-            best[c] = 0;
+            // FP32 problems whose tiles fit the resident solver at once run
+            // there (one launch per solve): where some shape lets a line of this
+            // class fit, only such shapes are candidates, so that tuning never
+            // moves a problem off the resident solver
+            bool allowed[kNumCfg];
+            bool any_resident = false;
             for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+                allowed[cfg] = precision == 1 && fast_allowed() && resident_fits(n, n, kCfgs[cfg].T(), false);
+                any_resident = any_resident || allowed[cfg];
+            }
+            double tbest = 0.0;
+            best[c] = -1;
+            for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+                if (any_resident && !allowed[cfg]) continue;
                 const double t = time_pair(al, precision, cfg, n, count, A, s);
-                if (cfg == 0 || t < tbest) {
+                if (best[c] < 0 || t < tbest) {
                     tbest = t;
                     best[c] = cfg;
                 }

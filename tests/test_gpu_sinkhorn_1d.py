@@ -130,6 +130,22 @@ def test_full_size_graded_iterates(eps, precision):
     assert abs(res["marginal_err"] - err_r) <= check_slack(g, t, eps, p.v)
 
 
+def test_streaming_beyond_the_llc_iterates():
+    """n = m = 2^24 graded meshes (a working set of about 1.5 GB, beyond the
+    256 MB Infinity Cache; too large for the resident solver, so the streaming
+    fast sweeps): 4 iterations against Algorithm 1 on the CPU."""
+    p = wl.config_graded_1d(1 << 24, 1e-3)
+    L = 4
+    print("graded 1D n=2^24 eps=1e-3, 4 iterations", flush=True)
+    res, f, g = _solve(p, precision=1, tol=0.0, itr_max=L)
+    assert res["fast"] == 1 and res["iters"] == L
+    fo, go, ito, erro = clib.sinkhorn_1d(p.x, p.y, p.u, p.v, p.eps, 0.0, L)
+    df = np.max(np.abs(f - fo)) / p.eps
+    dg = np.max(np.abs(g - go)) / p.eps
+    assert df <= 2e-5 and dg <= 2e-5, (df, dg)
+    assert abs(res["marginal_err"] - erro) <= 1e-5 * max(erro, 1e-3)
+
+
 def test_full_size_converged_cost_within_closed_form_bounds():
     p = wl.config_graded_1d(1 << 20, 1e-2)
     res, f, g = _solve(p, precision=1, tol=1e-6, itr_max=20000)
