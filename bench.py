@@ -52,8 +52,15 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # recorded beside them; after any change to those sources the traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
-TRAFFIC_RESIDENT = {"sources_sha256": "a8c0e16cbe0f876b096e625f9e19f5c9fe428c9874cf505c2ffc245d18be7948",
-                    "fetch_kib": 419616.0, "write_kib": 201081.0, "n": 1 << 20}
+TRAFFIC_RESIDENT = {"sources_sha256": "2dc6ef27f1cc1f45772691da50b69210751ab5198347c5c5787aec6b6f7d0827",
+                    "fetch_kib": 452241.0, "write_kib": 188600.0, "n": 1 << 20}
+# The resident kernel's instruction counters (rocprofv3 --pmc SQ_INSTS_VALU,
+# SQ_WAVES, per launch, same workload and sources as TRAFFIC_RESIDENT) and the
+# average launch of that run: VALU wave instructions issued, against one per
+# SIMD per 4 clocks (a wave64 instruction occupies a 16-lane SIMD for 4).
+RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.2907e10,
+                 "waves": 4096, "launch_us": 27967.01, "iters": 3117, "n": 1 << 20}
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4     # wave instructions per second
 TRAFFIC_STREAM = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
                   "fetch_kib": (22818.1 + 18715.2) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
 # the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per sweep
@@ -730,6 +737,13 @@ def main():
                     "unit_note": "lane operations (each add, multiply, fma, ldexp, reciprocal counts once) "
                                  "against 256 CUs x 64 lanes x 2.4 GHz",
                     "streaming_equivalent_GBs": per_sweep_bytes / (sweep_ms * 1e-3) / 1e9}
+        rv = RESIDENT_VALU
+        if args.n == rv["n"] and sources_digest(RESIDENT_SOURCES) == rv["sources_sha256"]:
+            roofline["valu_counters"] = {
+                "issued_lane_ops_per_grid_pt_iter": rv["valu_insts"] * 64 / (rv["n"] * rv["iters"]),
+                "valu_issue_frac": rv["valu_insts"] / (rv["launch_us"] * 1e-6 * VALU_ISSUE_PEAK),
+                "note": "rocprofv3 SQ_INSTS_VALU per launch of the same workload: VALU wave instructions "
+                        "issued against one per SIMD per 4 clocks (profiles/k_resident_1d_graded_1d_n2p20.md)"}
     else:
         # dominant kernels: the half-iteration sweeps; average launch duration
         # from the loop's HIP events divided by the sweeps executed

@@ -630,7 +630,7 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
 // ---------------------------------------------------------------------------
 static const void* resident_batch_kernel(bool gen)
 {
-    return gen ? (const void*)k_resident_batch<kResidentBlock, kResidentIpt, kResidentWavesGen, true>
+    return gen ? (const void*)k_resident_batch<kResidentBlockGen, kResidentIptGen, kResidentWavesGen, true>
                : (const void*)k_resident_batch<kResidentBlock, kResidentIpt, kResidentWaves, false>;
 }
 
@@ -640,7 +640,7 @@ int resident_batch_capacity(bool gen)
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_batch_kernel(gen), kResidentBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_batch_kernel(gen), resident_block(gen), 0) !=
         hipSuccess)
         return 0;
     return cus * per_cu;
@@ -725,7 +725,8 @@ void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen, bool re
     const int grid = std::min(total, resident_capacity(gen));
     void* kargs[] = {&b};
     HIPCHK(hipEventRecord(ev0_, s_));
-    HIPCHK(hipLaunchCooperativeKernel(resident_batch_kernel(gen), dim3(grid), dim3(kResidentBlock), kargs, 0, s_));
+    HIPCHK(hipLaunchCooperativeKernel(resident_batch_kernel(gen), dim3(grid), dim3(resident_block(gen)), kargs, 0,
+                                      s_));
     HIPCHK(hipEventRecord(ev1_, s_));
     int* hfail = al.host<int>(1);
     HIPCHK(hipMemcpyAsync(hfail, flags, sizeof(int), hipMemcpyDeviceToHost, s_));

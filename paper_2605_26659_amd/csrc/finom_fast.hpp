@@ -43,6 +43,16 @@ __device__ __forceinline__ float dpp_f(float v)
     return __int_as_float(dpp_i<CTRL, RM>(0, __float_as_int(v)));
 }
 
+// Row broadcast for a reduction whose result is read in the wave's last lane:
+// the rows the broadcast does not write are left undefined (no identity to
+// materialise first), and none of them feeds the last lane.
+template <int CTRL, int RM>
+__device__ __forceinline__ float dpp_bc_f(float v)
+{
+    static_assert(CTRL == 0x142 || CTRL == 0x143, "row broadcasts only");
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, RM, 0xF, false));
+}
+
 __device__ __forceinline__ float readlane_f(float v, int lane)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -59,6 +69,30 @@ __device__ __forceinline__ float wave_incl_prefix_f(float v)
     return v;
 }
 
+// Sum over the wave (every lane gets it), in the order of the prefix above.
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+    v += dpp_f<0x111>(v);
+    v += dpp_f<0x112>(v);
+    v += dpp_f<0x114>(v);
+    v += dpp_f<0x118>(v);
+    v += dpp_bc_f<0x142, 0xA>(v);
+    v += dpp_bc_f<0x143, 0xC>(v);
+    return readlane_f(v, kWave - 1);
+}
+
+// Sum of lanes [0, N) (N <= 16, a power of two), read from lane N - 1.
+template <int N>
+__device__ __forceinline__ float first_lanes_sum_f(float v)
+{
+    static_assert(N >= 1 && N <= 16 && (N & (N - 1)) == 0, "one row, power of two");
+    if (N > 1) v += dpp_f<0x111>(v);
+    if (N > 2) v += dpp_f<0x112>(v);
+    if (N > 4) v += dpp_f<0x114>(v);
+    if (N > 8) v += dpp_f<0x118>(v);
+    return readlane_f(v, N - 1);
+}
+
 __device__ __forceinline__ float wave_incl_suffix_f(float v)
 {
     v += dpp_f<0x101>(v);          // row_shl:1
@@ -73,15 +107,36 @@ __device__ __forceinline__ float wave_incl_suffix_f(float v)
     return v + add;
 }
 
+// Maxima take INT_MIN, the identity of max, where the DPP source is missing,
+// so that each step folds into a single max with a DPP operand.
+constexpr int kMaxIdentity = -2147483647 - 1;
+
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ int dpp_max_i(int v)
+{
+    return max(v, dpp_i<CTRL, RM>(kMaxIdentity, v));
+}
+
 __device__ __forceinline__ int wave_max_i(int v)
 {
-    v = max(v, dpp_i<0x111, 0xF>(kZeroExp, v));
-    v = max(v, dpp_i<0x112, 0xF>(kZeroExp, v));
-    v = max(v, dpp_i<0x114, 0xF>(kZeroExp, v));
-    v = max(v, dpp_i<0x118, 0xF>(kZeroExp, v));
-    v = max(v, dpp_i<0x142, 0xA>(kZeroExp, v));
-    v = max(v, dpp_i<0x143, 0xC>(kZeroExp, v));
+    v = dpp_max_i<0x111>(v);
+    v = dpp_max_i<0x112>(v);
+    v = dpp_max_i<0x114>(v);
+    v = dpp_max_i<0x118>(v);
+    v = dpp_max_i<0x142, 0xA>(v);
+    v = dpp_max_i<0x143, 0xC>(v);
     return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
+template <int N>
+__device__ __forceinline__ int first_lanes_max_i(int v)
+{
+    static_assert(N >= 1 && N <= 16 && (N & (N - 1)) == 0, "one row, power of two");
+    if (N > 1) v = dpp_max_i<0x111>(v);
+    if (N > 2) v = dpp_max_i<0x112>(v);
+    if (N > 4) v = dpp_max_i<0x114>(v);
+    if (N > 8) v = dpp_max_i<0x118>(v);
+    return __builtin_amdgcn_readlane(v, N - 1);
 }
 
 // Block maxima of two integers; s_i holds 2 * (BLOCK / 64) entries.
@@ -115,8 +170,8 @@ __device__ __forceinline__ void block_sum2_f(float& a, float& b, float* s_f)
     constexpr int NW = BLOCK / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    const float wa = readlane_f(wave_incl_prefix_f(a), kWave - 1);
-    const float wb = readlane_f(wave_incl_prefix_f(b), kWave - 1);
+    const float wa = wave_sum_f(a);
+    const float wb = wave_sum_f(b);
     __syncthreads();
     if (lane == 0) {
         s_f[wid] = wa;
@@ -192,7 +247,7 @@ __device__ __forceinline__ Ext<float> wave_total_ref(RefAcc a)
 {
     const int r = wave_max_i(a.r);
     const float v = ldexp_m(a.s, a.r - r);
-    return Ext<float>{readlane_f(wave_incl_prefix_f(v), kWave - 1), r};
+    return Ext<float>{wave_sum_f(v), r};
 }
 
 // Per-wave results of two totals go to LDS (slot wid of s_f / s_i and
@@ -349,7 +404,9 @@ __device__ __forceinline__ void fast_tile_columns(const FastTileIn<IPT>& t, floa
 // Exclusive prefix (s_l) and inclusive suffix (s_u) of the tile's columns in
 // place, thread t owning columns [t IPT, t IPT + IPT); the caller has passed a
 // barrier since the columns were written. s_f holds 2 * (BLOCK / 64) entries.
-template <int BLOCK, int IPT>
+// With SYNC the results are visible to the block on return; without, the
+// caller passes a barrier before reading them.
+template <int BLOCK, int IPT, bool SYNC = true>
 __device__ __forceinline__ void fast_tile_scan(float* s_l, float* s_u, int nc, float* s_f)
 {
     constexpr int NW = BLOCK / kWave;
@@ -357,19 +414,31 @@ __device__ __forceinline__ void fast_tile_scan(float* s_l, float* s_u, int nc, f
     const int wid = threadIdx.x / kWave;
     float vl[IPT], vu[IPT];
     const int base = threadIdx.x * IPT;
+    // chunks wholly inside or wholly past the columns need no per-entry mask
+    // (only one thread has a chunk that straddles the end)
+    if (base >= nc) {
 #pragma unroll
-    for (int q = 0; q < IPT; q += 4) {
-        const float4 a = *reinterpret_cast<const float4*>(s_l + base + q);
-        const float4 b = *reinterpret_cast<const float4*>(s_u + base + q);
-        vl[q] = a.x; vl[q + 1] = a.y; vl[q + 2] = a.z; vl[q + 3] = a.w;
-        vu[q] = b.x; vu[q + 1] = b.y; vu[q + 2] = b.z; vu[q + 3] = b.w;
+        for (int q = 0; q < IPT; ++q) vl[q] = vu[q] = 0.f;
+    } else {
+#pragma unroll
+        for (int q = 0; q < IPT; q += 4) {
+            const float4 a = *reinterpret_cast<const float4*>(s_l + base + q);
+            const float4 b = *reinterpret_cast<const float4*>(s_u + base + q);
+            vl[q] = a.x; vl[q + 1] = a.y; vl[q + 2] = a.z; vl[q + 3] = a.w;
+            vu[q] = b.x; vu[q + 1] = b.y; vu[q + 2] = b.z; vu[q + 3] = b.w;
+        }
+        if (base + IPT > nc) {
+#pragma unroll
+            for (int q = 0; q < IPT; ++q) {
+                const bool live = base + q < nc;
+                vl[q] = live ? vl[q] : 0.f;
+                vu[q] = live ? vu[q] : 0.f;
+            }
+        }
     }
     float sl = 0.f, su = 0.f;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
-        const bool live = base + q < nc;
-        vl[q] = live ? vl[q] : 0.f;
-        vu[q] = live ? vu[q] : 0.f;
         sl += vl[q];
         su += vu[q];
     }
@@ -378,15 +447,15 @@ __device__ __forceinline__ void fast_tile_scan(float* s_l, float* s_u, int nc, f
     if (lane == kWave - 1) s_f[wid] = il;
     if (lane == 0) s_f[NW + wid] = iu;
     __syncthreads();
-    // the other waves' totals, read at once (adding the zeros of the other
-    // side leaves the sums exact)
-    float pre = 0.f, suf = 0.f;
-#pragma unroll
-    for (int v = 0; v < NW; ++v) {
-        const float f = s_f[v], g = s_f[NW + v];
-        pre += v < wid ? f : 0.f;
-        suf += v > wid ? g : 0.f;
-    }
+    // the other waves' totals: lane j < NW reads wave j's, and the lanes of the
+    // waves before (prefix) / after (suffix) this one are summed across lanes
+    const int j = lane & (NW - 1);
+    const bool head = lane < NW;
+    float a = s_f[j], b = s_f[NW + j];
+    a = (head && j < wid) ? a : 0.f;
+    b = (head && j > wid) ? b : 0.f;
+    const float pre = first_lanes_sum_f<NW>(a);
+    const float suf = first_lanes_sum_f<NW>(b);
     float run = pre + dpp_f<0x138>(il);    // wave_shr:1 -> exclusive prefix
     float runu = dpp_f<0x130>(iu) + suf;   // wave_shl:1 -> exclusive suffix
 #pragma unroll
@@ -411,7 +480,7 @@ __device__ __forceinline__ void fast_tile_scan(float* s_l, float* s_u, int nc, f
         s_l[BLOCK * IPT] = run;      // z = nc = T: everything before
         s_u[BLOCK * IPT] = 0.f;
     }
-    __syncthreads();
+    if (SYNC) __syncthreads();
 }
 
 // Rows of a scanned tile. With the carries, the row's sums are

@@ -837,6 +837,12 @@ bool resident_allowed()
     return !(e && e[0] == '0');
 }
 
+const void* resident_kernel(bool gen)
+{
+    return gen ? (const void*)k_resident_1d<kResidentBlockGen, kResidentIptGen, kResidentWavesGen, true>
+               : (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves, false>;
+}
+
 // The smaller of the two kernels' capacities, so that a problem is resident
 // alone exactly when it is resident in a batch. Computed once per process on
 // the device current at the first call.
@@ -849,12 +855,11 @@ int resident_capacity(bool gen)
     if (c < 0) {
         int dev = 0, coop = 0, cus = 0, per_cu = 0;
         c = 0;
-        const void* k = gen ? (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWavesGen, true>
-                            : (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves, false>;
+        const void* k = resident_kernel(gen);
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kResidentBlock, 0) == hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, resident_block(gen), 0) == hipSuccess)
             c = std::min(cus * per_cu, resident_batch_capacity(gen));
     }
     return c;
@@ -1006,9 +1011,8 @@ static int run_resident(Alloc& al, const Part& pk, const Part& pkt, Ext<float>* 
         HIPCHK(hipEventCreate(&ev1));
         HIPCHK(hipEventRecord(ev0, s));
         void* args[] = {&a};
-        const void* k = gen ? (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWavesGen, true>
-                            : (const void*)k_resident_1d<kResidentBlock, kResidentIpt, kResidentWaves, false>;
-        HIPCHK(hipLaunchCooperativeKernel(k, dim3(pk.ntiles), dim3(kResidentBlock), args, 0, s));
+        HIPCHK(hipLaunchCooperativeKernel(resident_kernel(gen), dim3(pk.ntiles), dim3(resident_block(gen)), args, 0,
+                                          s));
         HIPCHK(hipEventRecord(ev1, s));
         int* hfail = al.host<int>(1);
         HIPCHK(hipMemcpyAsync(hfail, a.fail, sizeof(int), hipMemcpyDeviceToHost, s));

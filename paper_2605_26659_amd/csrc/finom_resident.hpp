@@ -17,7 +17,10 @@
 // elements as [its nc y points, its nr x points]. In the checking sweep
 // (K^T phi) the x slots are columns and the y slots rows; in K psi the other
 // way round. The arithmetic per element is that of k_sweep_fast; the tile
-// reference exponents come from the tile's own totals.
+// reference exponents come from the tile's own totals. The checking sweep's
+// error terms are summed in FP32 (each term capped at 2^100, far above any
+// tolerance): the sum only decides when the loop stops, and the library
+// confirms a stop with an FP64 check of the returned pair.
 #pragma once
 #include <type_traits>
 
@@ -66,13 +69,19 @@ struct ResidentArgs {
 // the high half and its exponent in the low half; a partial error is a
 // non-negative double. Both are restored exactly.
 constexpr unsigned kResidentSpin = 1u << 22;   // default bound of a wait, in polls (~seconds)
-constexpr int kResidentMaxTiles = 512;         // tiles of one problem (one record per thread)
-// The kernels' shape: 512 threads of 8 slots (tiles of up to 4096 merged
-// points). The fast variant runs two blocks per CU (four waves per SIMD, at
-// most 128 registers); the variant with extended-number scans needs twice the
-// LDS for them and runs one (two waves per SIMD).
-constexpr int kResidentBlock = 512, kResidentIpt = 8, kResidentWaves = 4, kResidentWavesGen = 2;
+constexpr int kResidentMaxTiles = 512;         // tiles of one problem
+// The kernels' shapes, both with tiles of up to 4096 merged points. The fast
+// variant runs 512 threads of 8 slots and two blocks per CU (four waves per
+// SIMD, at most 128 registers). With 256 threads of 16 slots the block-wide
+// steps of a sweep cost half as much per point, but two waves per SIMD leave
+// too little to issue while a wave waits: measured slower. The variant with
+// extended-number scans needs twice the LDS for them and runs one block of
+// 512 threads per CU.
+constexpr int kResidentBlock = 512, kResidentIpt = 8, kResidentWaves = 4;
+constexpr int kResidentBlockGen = 512, kResidentIptGen = 8, kResidentWavesGen = 2;
 constexpr int kResidentSlots = kResidentBlock * kResidentIpt;
+static_assert(kResidentSlots == kResidentBlockGen * kResidentIptGen, "both variants take the same tiles");
+constexpr int kResidentErrCap = 100;           // binary exponent cap of one error term
 
 __device__ __forceinline__ unsigned long long rec_of(Ext<float> v, unsigned tag)
 {
@@ -106,15 +115,14 @@ __device__ __forceinline__ void resident_fail(const ResidentArgs& a, int* s_flag
     *s_flag = 0;
 }
 
-// Reads a record until it carries the expected tag. The wait is bounded: it
-// fails after a.spin_limit polls, or when another block's failure shows in
-// the fail flag (checked every 64 polls); a failure clears the block's flag,
-// so the block leaves its loop and publishes no more, and every block waiting
-// for it fails in turn.
-__device__ __forceinline__ unsigned long long rec_read(const ResidentArgs& a, const unsigned long long* p,
-                                                       unsigned tag, int* s_flag)
+// Reads a record until it carries the expected tag, starting from a first
+// read w already made. The wait is bounded: it fails after a.spin_limit polls,
+// or when another block's failure shows in the fail flag (checked every 64
+// polls); a failure clears the block's flag, so the block leaves its loop and
+// publishes no more, and every block waiting for it fails in turn.
+__device__ __forceinline__ unsigned long long rec_wait(const ResidentArgs& a, const unsigned long long* p,
+                                                       unsigned long long w, unsigned tag, int* s_flag)
 {
-    unsigned long long w = rec_load(p);
     unsigned polls = 0;
     while ((unsigned)(w >> 63) != tag) {
         ++polls;
@@ -144,64 +152,70 @@ __device__ __forceinline__ void resident_publish(int n, unsigned long long* p0, 
 }
 
 // A block's share of the carries from one buffer of records: thread t holds
-// tile t's lower total when t < tile, its upper total when t > tile, and with
-// PART tile t's partial error.
+// the lower totals of tiles t + r BLOCK before the block's tile, the upper
+// totals of those after it, and with PART the partial errors of all of them.
 struct ResidentIn {
     Ext<float> cl, cu;
-    double part;
+    float part;
 };
 
 // own_part: this tile's partial error, which its thread takes from the
 // block rather than from its record (the same value: records keep it exactly).
-template <bool PART>
+// A thread waits for its totals record before it requests the partial error
+// published beside it (requesting both first measured slower).
+template <int BLOCK, bool PART>
 __device__ __forceinline__ void resident_read(const ResidentArgs& a, int tile, const unsigned long long* tot,
                                               const unsigned long long* part, unsigned tag, int* s_flag,
-                                              double own_part, ResidentIn& in)
+                                              float own_part, ResidentIn& in)
 {
-    const int t = threadIdx.x, nt = a.ntiles;
+    constexpr int RPT = (kResidentMaxTiles + BLOCK - 1) / BLOCK;
+    const int nt = a.ntiles;
     in.cl = in.cu = ext_zero<float>();
-    in.part = 0.0;
-    if (t < nt && t != tile) {
-        const Ext<float> v = ext_of_rec(rec_read(a, tot + 2 * t + (t > tile ? 1 : 0), tag, s_flag));
-        if (t < tile) in.cl = v;
-        else in.cu = v;
-        if (PART) in.part = double_of_rec(rec_read(a, part + t, tag, s_flag));
+    in.part = 0.f;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int t = threadIdx.x + r * BLOCK;
+        if (t < nt && t != tile) {
+            const unsigned long long* pt = tot + 2 * t + (t > tile ? 1 : 0);
+            const Ext<float> v = ext_of_rec(rec_wait(a, pt, rec_load(pt), tag, s_flag));
+            if (t < tile) in.cl = ext_add(in.cl, v);
+            else in.cu = ext_add(in.cu, v);
+            if (PART) in.part += (float)double_of_rec(rec_wait(a, part + t, rec_load(part + t), tag, s_flag));
+        }
+        if (PART && t == tile) in.part += own_part;
     }
-    if (PART && t == tile) in.part = own_part;
 }
 
 // ---- block totals
-// The per-wave parts of a block's two extended totals (each against the
-// wave's largest exponent) and, with D, of a double sum, as one interleaved
-// sequence of DPP steps so that the independent reductions fill each other's
-// wait states; lane 0 of each wave leaves them in LDS for block_total_read /
-// block_read_sum after a barrier. The order of every sum is fixed.
+// The per-wave parts of a block's two extended totals and, with D, of an FP32
+// sum, as one interleaved sequence of DPP steps so that the independent
+// reductions fill each other's wait states; lane 0 of each wave leaves them in
+// LDS (each extended part normalised) for block_totals_read / block_refs_read
+// after a barrier. The order of every sum is fixed.
 template <int C, int R>
-__device__ __forceinline__ double dpp_d(double v)
+__device__ __forceinline__ float dpp_sum_src(float v)
 {
-    const long long b = __double_as_longlong(v);
-    const int lo = dpp_i<C, R>(0, (int)(b & 0xffffffffLL));
-    const int hi = dpp_i<C, R>(0, (int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    if constexpr (C == 0x142 || C == 0x143) return dpp_bc_f<C, R>(v);
+    else return dpp_f<C, R>(v);
 }
 
 template <int C, int R, bool D>
-__device__ __forceinline__ void tot_step1(int& ra, int& rb, double& d)
+__device__ __forceinline__ void tot_step1(int& ra, int& rb, float& d)
 {
-    ra = max(ra, dpp_i<C, R>(kZeroExp, ra));
-    rb = max(rb, dpp_i<C, R>(kZeroExp, rb));
-    if (D) d += dpp_d<C, R>(d);
+    ra = dpp_max_i<C, R>(ra);
+    rb = dpp_max_i<C, R>(rb);
+    if (D) d += dpp_sum_src<C, R>(d);
 }
 
 template <int C, int R>
 __device__ __forceinline__ void tot_step2(float& sa, float& sb)
 {
-    sa += dpp_f<C, R>(sa);
-    sb += dpp_f<C, R>(sb);
+    sa += dpp_sum_src<C, R>(sa);
+    sb += dpp_sum_src<C, R>(sb);
 }
 
 template <int BLOCK, bool D>
-__device__ __forceinline__ void block_totals_write(RefAcc a, RefAcc b, double d, float* s_f, int* s_i, double* s_d)
+__device__ __forceinline__ void block_totals_write(RefAcc a, RefAcc b, float d, float* s_f, int* s_i, float* s_e)
 {
     constexpr int NW = BLOCK / kWave;
     int ra = a.r, rb = b.r;
@@ -222,19 +236,14 @@ __device__ __forceinline__ void block_totals_write(RefAcc a, RefAcc b, double d,
     tot_step2<0x143, 0xC>(sa, sb);
     sa = readlane_f(sa, kWave - 1);
     sb = readlane_f(sb, kWave - 1);
-    if (D) {
-        const long long db = __double_as_longlong(d);
-        const int lo = __builtin_amdgcn_readlane((int)(db & 0xffffffffLL), kWave - 1);
-        const int hi = __builtin_amdgcn_readlane((int)(db >> 32), kWave - 1);
-        d = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-    }
+    if (D) d = readlane_f(d, kWave - 1);
     if ((threadIdx.x & (kWave - 1)) == 0) {
         const int wid = threadIdx.x / kWave;
-        s_f[wid] = sa;
-        s_i[wid] = ra;
-        s_f[NW + wid] = sb;
-        s_i[NW + wid] = rb;
-        if (D) s_d[wid] = d;
+        s_f[wid] = __builtin_amdgcn_frexp_mantf(sa);
+        s_i[wid] = sa > 0.f ? ra + __builtin_amdgcn_frexp_expf(sa) : kZeroExp;
+        s_f[NW + wid] = __builtin_amdgcn_frexp_mantf(sb);
+        s_i[NW + wid] = sb > 0.f ? rb + __builtin_amdgcn_frexp_expf(sb) : kZeroExp;
+        if (D) s_e[wid] = d;
     }
 }
 
@@ -243,35 +252,36 @@ __device__ __forceinline__ void block_totals_write(RefAcc a, RefAcc b, double d,
 // combined across lanes (largest exponent, then the sum in a fixed order), so
 // every thread gets the same results.
 template <int BLOCK, bool D>
-__device__ __forceinline__ void block_totals_read(const float* s_f, const int* s_i, const double* s_d, Ext<float>& ta,
-                                                  Ext<float>& tb, double& td)
+__device__ __forceinline__ void block_totals_read(const float* s_f, const int* s_i, const float* s_e, Ext<float>& ta,
+                                                  Ext<float>& tb, float& td)
 {
     constexpr int NW = BLOCK / kWave;
-    static_assert(NW == 8, "three DPP steps combine eight waves");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = lane & (NW - 1);
     const bool mine = lane < NW;
     const float fa = s_f[w], fb = s_f[NW + w];
     const int ea = mine ? s_i[w] : kZeroExp, eb = mine ? s_i[NW + w] : kZeroExp;
-    double d = D && mine ? s_d[w] : 0.0;
-    int ra = ea, rb = eb;
-    tot_step1<0x111, 0xF, D>(ra, rb, d);   // row_shr:1
-    tot_step1<0x112, 0xF, D>(ra, rb, d);   // row_shr:2
-    tot_step1<0x114, 0xF, D>(ra, rb, d);   // row_shr:4
-    ra = __builtin_amdgcn_readlane(ra, NW - 1);
-    rb = __builtin_amdgcn_readlane(rb, NW - 1);
-    float sa = mine ? ldexp_m(fa, ea - ra) : 0.f, sb = mine ? ldexp_m(fb, eb - rb) : 0.f;
-    tot_step2<0x111, 0xF>(sa, sb);
-    tot_step2<0x112, 0xF>(sa, sb);
-    tot_step2<0x114, 0xF>(sa, sb);
-    ta = ext_norm(Ext<float>{readlane_f(sa, NW - 1), ra});
-    tb = ext_norm(Ext<float>{readlane_f(sb, NW - 1), rb});
-    if (D) {
-        const long long db = __double_as_longlong(d);
-        const int lo = __builtin_amdgcn_readlane((int)(db & 0xffffffffLL), NW - 1);
-        const int hi = __builtin_amdgcn_readlane((int)(db >> 32), NW - 1);
-        td = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-    }
+    const float d = D && mine ? s_e[w] : 0.f;
+    const int ra = first_lanes_max_i<NW>(ea), rb = first_lanes_max_i<NW>(eb);
+    const float sa = first_lanes_sum_f<NW>(mine ? ldexp_m(fa, ea - ra) : 0.f);
+    const float sb = first_lanes_sum_f<NW>(mine ? ldexp_m(fb, eb - rb) : 0.f);
+    ta = ext_norm(Ext<float>{sa, ra});
+    tb = ext_norm(Ext<float>{sb, rb});
+    if (D) td = first_lanes_sum_f<NW>(d);
+}
+
+// Only the references of the next sweep's column terms: the largest exponent
+// of the waves' (normalised) parts of the two totals. Every term of the tile
+// is below 2^ref and the tile's total below 2^(ref + 3).
+template <int BLOCK>
+__device__ __forceinline__ void block_refs_read(const int* s_i, int& ra, int& rb)
+{
+    constexpr int NW = BLOCK / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = lane & (NW - 1);
+    const bool mine = lane < NW;
+    ra = first_lanes_max_i<NW>(mine ? s_i[w] : kZeroExp);
+    rb = first_lanes_max_i<NW>(mine ? s_i[NW + w] : kZeroExp);
 }
 
 // Exclusive prefix and exclusive suffix (thread order) of extended values over
@@ -307,7 +317,8 @@ __device__ __forceinline__ void block_scan_ext(Ext<float> vl, Ext<float> vu, Ext
 // Exclusive prefix (s_l) and inclusive suffix (s_u) of a tile's extended
 // column terms in place, thread t owning columns [t IPT, t IPT + IPT), and the
 // total before the end at s_l[BLOCK IPT]; the caller has passed a barrier
-// since the columns were written. Terms past ncol count as zero.
+// since the columns were written, and passes another before the results are
+// read. Terms past ncol count as zero.
 template <int BLOCK, int IPT>
 __device__ __forceinline__ void resident_scan_ext(Ext<float>* s_l, Ext<float>* s_u, int nc, Ext<float>* s_tmp)
 {
@@ -345,14 +356,14 @@ __device__ __forceinline__ void resident_scan_ext(Ext<float>* s_l, Ext<float>* s
         s_l[BLOCK * IPT] = run;
         s_u[BLOCK * IPT] = ext_zero<float>();
     }
-    __syncthreads();
 }
 
 // The local half of a sweep: the column terms (slots [c_first, c_first +
 // ncol), column index k - c_first) to LDS, and their in-tile scan. Needs
 // nothing from other blocks. On the fast sweeps' tiles the terms are plain
-// FP32 against the tile's own totals (r0l, r0u); with GEN they are extended
-// numbers, for tiles whose terms span more than FP32's range.
+// FP32 against the references r0l, r0u (no term above 2^r); with GEN they are
+// extended numbers, for tiles whose terms span more than FP32's range. The
+// scan's results are visible after the caller's next barrier.
 template <int BLOCK, int IPT, bool GEN, typename Term>
 __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l, int r0u, const Ext<float>* U,
                                                  const Ext<float>* B, Term* s_l, Term* s_u, float* s_f,
@@ -360,14 +371,15 @@ __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l,
 {
     // Opaque copies of the slot bounds and the thread index: without them the
     // compiler hoists every slot's masks and LDS offsets of both sweeps out of
-    // the solver loop and runs out of registers.
+    // the solver loop and runs out of registers. (Per-lane tests: a
+    // wave-uniform test per slot runs more scalar instructions than it saves.)
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     asm volatile("" : "+s"(c_first), "+s"(ncol));
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int k = tid + q * BLOCK - c_first;
-        if (k >= 0 && k < ncol) {
+        if ((unsigned)k < (unsigned)ncol) {
             if constexpr (GEN) {
                 s_l[k] = Ext<float>{U[q].m * B[q].m, U[q].e + B[q].e};
                 s_u[k] = U[q];
@@ -379,19 +391,20 @@ __device__ __forceinline__ void resident_columns(int c_first, int ncol, int r0l,
     }
     __syncthreads();
     if constexpr (GEN) resident_scan_ext<BLOCK, IPT>(s_l, s_u, ncol, s_tmp);
-    else fast_tile_scan<BLOCK, IPT>(s_l, s_u, ncol, s_f);
+    else fast_tile_scan<BLOCK, IPT, false>(s_l, s_u, ncol, s_f);
 }
 
 // The rows of a sweep (slots [r_first, r_first + nrow), dividing index Z as a
 // column index of this tile) once the carries are known: replaces the rows'
-// states and leaves the next sweep's tile totals (and for CHECK the tile's
-// partial error) in the block's LDS slots. CHECK also keeps the rows' old
-// states in `old` (the pair the loop head returns when it stops).
+// states and leaves the per-wave parts of the next sweep's tile totals (and
+// for CHECK of the tile's partial error) in the block's LDS slots, visible on
+// return. CHECK also keeps the rows' old states in `old` (the pair the loop
+// head returns when it stops).
 template <int BLOCK, int IPT, bool CHECK, bool GEN, typename Term>
 __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<float> CU, int ncol, int r_first,
                                               int nrow, int r0l, int r0u, Ext<float>* U, const Ext<float>* s_a,
                                               const Ext<float>* B, const unsigned short* s_z, Ext<float>* old,
-                                              const Term* s_l, const Term* s_u, float* s_f, int* s_i, double* s_d)
+                                              const Term* s_l, const Term* s_u, float* s_f, int* s_i, float* s_e)
 {
     constexpr int NW = BLOCK / kWave;
     int tid = threadIdx.x;
@@ -400,7 +413,12 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
     const int rl = max(r0l, CL.e), ru = max(r0u, CU.e);
     const float cl_rel = ldexp_m(CL.m, CL.e - rl), cu_rel = ldexp_m(CU.m, CU.e - ru);
     const int shl = r0l - rl, shu = r0u - ru;
-    double red = 0.0;
+    // the in-tile sums rescaled by 2^shl <= 1 in the same fused operation as
+    // the carry's addition (exact products; where 2^shl is below FP32's normal
+    // range the in-tile part is below 2^-126 of the carry, which is >= 1/2)
+    const float scl = shl < -126 ? 0.f : ldexp_m(1.f, shl);
+    const float scu = shu < -126 ? 0.f : ldexp_m(1.f, shu);
+    float red = 0.f;
     RefAcc n1{0.f, kZeroExp}, n2{0.f, kZeroExp};
     // every slot's scan values first (unconditional: each slot's dividing
     // index is within the scans), so that no row waits on its own LDS reads
@@ -413,43 +431,42 @@ __device__ __forceinline__ void resident_rows(const Ext<float> CL, const Ext<flo
         su[q] = s_u[z];
         A[q] = s_a[tid + q * BLOCK];
     }
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-        const int k = tid + q * BLOCK - r_first;
-        if (k >= 0 && k < nrow) {
-            const Ext<float> Aq = A[q];
-            Ext<float> W;
-            if constexpr (GEN) {
-                const Ext<float> L = ext_add(CL, sl[q]);
-                const Ext<float> R = ext_add(su[q], CU);
-                W = ext_add(L, Ext<float>{R.m * B[q].m, R.e + B[q].e});
-            } else {
-                const float pm = cl_rel + ldexp_m(sl[q], shl);
-                const float qm = ldexp_m(su[q], shu) + cu_rel;
-                W = ext_add(Ext<float>{pm, rl}, Ext<float>{qm * B[q].m, ru + B[q].e});
-            }
-            const Ext<float> Un = ext_norm(Ext<float>{Aq.m * __builtin_amdgcn_rcpf(W.m), Aq.e - W.e});
-            if (CHECK) {
-                const int ep = U[q].e + W.e;
-                const int re = max(ep, Aq.e);
-                const float d = __builtin_fmaf(ldexp_m(U[q].m, ep - re), W.m, -ldexp_m(Aq.m, Aq.e - re));
-                red += __builtin_amdgcn_ldexp((double)fabsf(d), re);
-                old[q] = U[q];
-            }
-            U[q] = Un;
-            if constexpr (GEN) {
-                // totals of terms of any range: against the largest so far
-                const Ext<float> t1 = ext_add(Ext<float>{n1.s, n1.r}, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
-                const Ext<float> t2 = ext_add(Ext<float>{n2.s, n2.r}, Un);
-                n1 = RefAcc{t1.m, t1.e};
-                n2 = RefAcc{t2.m, t2.e};
-            } else {
-                ref_add(n1, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
-                ref_add(n2, Un);
-            }
+    auto row = [&](int q) {
+        const Ext<float> Aq = A[q];
+        Ext<float> W;
+        if constexpr (GEN) {
+            const Ext<float> L = ext_add(CL, sl[q]);
+            const Ext<float> R = ext_add(su[q], CU);
+            W = ext_add(L, Ext<float>{R.m * B[q].m, R.e + B[q].e});
+        } else {
+            const float pm = __builtin_fmaf(sl[q], scl, cl_rel);
+            const float qm = __builtin_fmaf(su[q], scu, cu_rel);
+            W = ext_add(Ext<float>{pm, rl}, Ext<float>{qm * B[q].m, ru + B[q].e});
         }
-    }
-    block_totals_write<BLOCK, CHECK>(n1, n2, red, s_f + 4 * NW, s_i + 4 * NW, s_d);
+        const Ext<float> Un = ext_norm(Ext<float>{Aq.m * __builtin_amdgcn_rcpf(W.m), Aq.e - W.e});
+        if (CHECK) {
+            const int ep = U[q].e + W.e;
+            const int re = max(ep, Aq.e);
+            const float d = __builtin_fmaf(ldexp_m(U[q].m, ep - re), W.m, -ldexp_m(Aq.m, Aq.e - re));
+            red += ldexp_m(fabsf(d), min(re, kResidentErrCap));
+            old[q] = U[q];
+        }
+        U[q] = Un;
+        if constexpr (GEN) {
+            // totals of terms of any range: against the largest so far
+            const Ext<float> t1 = ext_add(Ext<float>{n1.s, n1.r}, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
+            const Ext<float> t2 = ext_add(Ext<float>{n2.s, n2.r}, Un);
+            n1 = RefAcc{t1.m, t1.e};
+            n2 = RefAcc{t2.m, t2.e};
+        } else {
+            ref_add(n1, Ext<float>{Un.m * B[q].m, Un.e + B[q].e});
+            ref_add(n2, Un);
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < IPT; ++q)
+        if ((unsigned)(tid + q * BLOCK - r_first) < (unsigned)nrow) row(q);
+    block_totals_write<BLOCK, CHECK>(n1, n2, red, s_f + 4 * NW, s_i + 4 * NW, s_e + NW);
     __syncthreads();
 }
 
@@ -467,9 +484,10 @@ struct ResidentLds {
     Ext<float> tmp[GEN ? 2 * NW : 1];
     float f[6 * NW];
     int i[6 * NW];
-    double d[NW];
+    float e[2 * NW];   // per-wave error parts: [0, NW) of the carries, [NW, 2 NW) of the rows
     Ext<float> a[T];
     unsigned short z[T];
+    float pe;   // the tile's partial error of the last checking sweep
     int flag;   // 0 once a wait of this block has failed
 };
 
@@ -487,7 +505,7 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
     Ext<float>* const s_tmp = L.tmp;
     float* const s_f = L.f;
     int* const s_i = L.i;
-    double* const s_d = L.d;
+    float* const s_e = L.e;
     Ext<float>* const s_a = L.a;
     unsigned short* const s_z = L.z;
     int& s_flag = L.flag;
@@ -537,9 +555,13 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
     // SIMDs favour the older block's waves: a block raises its waves' issue
     // priority from its records to its publication, so that a block on the
     // critical path is not held back by its neighbour's column work.
+    // Per sweep the block passes four barriers: columns written, scan's wave
+    // totals, scan and carry parts written, rows' parts written. Every thread
+    // takes the next sweep's column references from the rows' parts; wave 0
+    // alone forms the tile's totals and partial error and publishes them.
     if (threadIdx.x == 0) s_flag = 1;
     // the first sweep's column totals (x points) from the initial state
-    Ext<float> own_l, own_u;
+    int refl, refu;
     {
         RefAcc n1{0.f, kZeroExp}, n2{0.f, kZeroExp};
 #pragma unroll
@@ -557,41 +579,47 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
                 }
             }
         }
-        block_total2_write<BLOCK>(n1, n2, s_f + 4 * NW, s_i + 4 * NW);
+        block_totals_write<BLOCK, false>(n1, n2, 0.f, s_f + 4 * NW, s_i + 4 * NW, s_e);
         __syncthreads();
-        own_l = block_total_read<BLOCK>(s_f + 4 * NW, s_i + 4 * NW);
-        own_u = block_total_read<BLOCK>(s_f + 5 * NW, s_i + 5 * NW);
-        if (threadIdx.x < kWave)
+        block_refs_read<BLOCK>(s_i + 4 * NW, refl, refu);
+        if (threadIdx.x < kWave) {
+            Ext<float> own_l, own_u;
+            float unused;
+            block_totals_read<BLOCK, false>(s_f + 4 * NW, s_i + 4 * NW, s_e, own_l, own_u, unused);
             resident_publish(2, rec_x + 2 * tile, rec_of(own_l, 1u), rec_x + 2 * tile + 1, rec_of(own_u, 1u),
                              nullptr, 0);
+        }
     }
 
     long long it = 0;   // iterations of this launch: the records' tags count from the launch
-    double err = 0.0;
+    float err = 0.f;
     bool ok = true;
     ResidentIn in;
     Ext<float> uold[IPT];   // the y points' states the loop head checks
     for (;;) {
         // ---- K^T phi with the marginal check: columns x, rows y
-        resident_columns<BLOCK, IPT, GEN>(nc, nr, own_l.e, own_u.e, U, B, s_l, s_u, s_f, s_tmp);
-        const int rxl = own_l.e, rxu = own_u.e;
+        resident_columns<BLOCK, IPT, GEN>(nc, nr, refl, refu, U, B, s_l, s_u, s_f, s_tmp);
+        const int rxl = refl, rxu = refu;
         // records of this iteration's sweeps: write it + 1 of their buffers
         const unsigned tag = (unsigned)((it + 1) & 1);
         __builtin_amdgcn_s_setprio(2);
-        resident_read<false>(a, tile, rec_x, nullptr, tag, &s_flag, 0.0, in);
-        block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.0, s_f + 2 * NW,
-                                         s_i + 2 * NW, s_d);
+        resident_read<BLOCK, false>(a, tile, rec_x, nullptr, tag, &s_flag, 0.f, in);
+        block_totals_write<BLOCK, false>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, 0.f, s_f + 2 * NW,
+                                         s_i + 2 * NW, s_e);
         __syncthreads();
         ok = s_flag != 0;
         if (!ok) break;
         Ext<float> CL, CU;
-        double pe;
-        block_totals_read<BLOCK, false>(s_f + 2 * NW, s_i + 2 * NW, s_d, CL, CU, pe);
-        resident_rows<BLOCK, IPT, true, GEN>(CL, CU, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_d);
-        block_totals_read<BLOCK, true>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
+        float pe;
+        block_totals_read<BLOCK, false>(s_f + 2 * NW, s_i + 2 * NW, s_e, CL, CU, pe);
+        resident_rows<BLOCK, IPT, true, GEN>(CL, CU, nr, 0, nc, rxl, rxu, U, s_a, B, s_z, uold, s_l, s_u, s_f, s_i, s_e);
+        block_refs_read<BLOCK>(s_i + 4 * NW, refl, refu);
         if (threadIdx.x < kWave) {
+            Ext<float> own_l, own_u;
+            block_totals_read<BLOCK, true>(s_f + 4 * NW, s_i + 4 * NW, s_e + NW, own_l, own_u, pe);
             resident_publish(3, rec_y + 2 * tile, rec_of(own_l, tag), rec_y + 2 * tile + 1, rec_of(own_u, tag),
-                             rec_p + tile, rec_of(pe, tag));
+                             rec_p + tile, rec_of((double)pe, tag));
+            if (threadIdx.x == 0) L.pe = pe;   // read by thread `tile` after the next barriers
         }
         __builtin_amdgcn_s_setprio(0);
         // ---- K psi: its columns (y) while the others finish, then the loop
@@ -599,17 +627,17 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         // is needed before the columns: the scans were last read before the
         // rows' barrier, and the LDS read since then is written again only
         // after the column phase's barriers.
-        resident_columns<BLOCK, IPT, GEN>(0, nc, own_l.e, own_u.e, U, B, s_l, s_u, s_f, s_tmp);
-        const int ryl = own_l.e, ryu = own_u.e;
+        resident_columns<BLOCK, IPT, GEN>(0, nc, refl, refu, U, B, s_l, s_u, s_f, s_tmp);
+        const int ryl = refl, ryu = refu;
         __builtin_amdgcn_s_setprio(2);
-        resident_read<true>(a, tile, rec_y, rec_p, tag, &s_flag, pe, in);
+        resident_read<BLOCK, true>(a, tile, rec_y, rec_p, tag, &s_flag, L.pe, in);
         block_totals_write<BLOCK, true>(RefAcc{in.cl.m, in.cl.e}, RefAcc{in.cu.m, in.cu.e}, in.part, s_f + 2 * NW,
-                                        s_i + 2 * NW, s_d);
+                                        s_i + 2 * NW, s_e);
         __syncthreads();
         ok = s_flag != 0;
         if (!ok) break;
-        block_totals_read<BLOCK, true>(s_f + 2 * NW, s_i + 2 * NW, s_d, CL, CU, err);
-        if (l >= itr_max || !(err > tol)) {
+        block_totals_read<BLOCK, true>(s_f + 2 * NW, s_i + 2 * NW, s_e, CL, CU, err);
+        if (l >= itr_max || !((double)err > tol)) {
             // the returned psi: the states the loop head checked
 #pragma unroll
             for (int q = 0; q < IPT; ++q) {
@@ -620,11 +648,14 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
         }
         // ---- K psi: rows x
         resident_rows<BLOCK, IPT, false, GEN>(CL, CU, nc, nc, nr, ryl, ryu, U, s_a, B, s_z, nullptr, s_l, s_u, s_f, s_i,
-                                         s_d);
-        block_totals_read<BLOCK, false>(s_f + 4 * NW, s_i + 4 * NW, s_d, own_l, own_u, pe);
-        if (threadIdx.x < kWave)
+                                         s_e);
+        block_refs_read<BLOCK>(s_i + 4 * NW, refl, refu);
+        if (threadIdx.x < kWave) {
+            Ext<float> own_l, own_u;
+            block_totals_read<BLOCK, false>(s_f + 4 * NW, s_i + 4 * NW, s_e, own_l, own_u, pe);
             resident_publish(2, rec_x + 2 * tile, rec_of(own_l, tag ^ 1u), rec_x + 2 * tile + 1,
                              rec_of(own_u, tag ^ 1u), nullptr, 0);
+        }
         __builtin_amdgcn_s_setprio(0);
         ++l;
         ++it;
@@ -638,10 +669,10 @@ __device__ __forceinline__ void resident_solve(const ResidentArgs& a, const int 
     }
     if (tile == 0 && threadIdx.x == 0) {
         ProbState* P = a.ps;
-        P->err = err;
+        P->err = (double)err;
         P->iters = l;
-        P->converged = (ok && err <= tol) ? 1 : 0;
-        P->status = (!(err == err) || err == __builtin_inf()) ? 1 : 0;
+        P->converged = (ok && (double)err <= tol) ? 1 : 0;
+        P->status = (!(err == err) || err == __builtin_inff()) ? 1 : 0;
         P->done = 1;
     }
 }
@@ -697,5 +728,12 @@ __global__ __launch_bounds__(BLOCK, MINW) void k_resident_batch(ResidentBatch b)
         resident_solve<BLOCK, IPT, GEN>(a, __builtin_amdgcn_readfirstlane(g - b.first[lo]), L);
     }
 }
+
+}  // namespace finom
+
+namespace finom {
+
+// Threads per block of the resident kernels (the fast and the extended variant).
+constexpr int resident_block(bool gen) { return gen ? kResidentBlockGen : kResidentBlock; }
 
 }  // namespace finom
