@@ -113,7 +113,7 @@ def graded_golden(eps):
 
 def state_repr(res):
     """What the loop kept as its iteration state (result field `fast`)."""
-    if res.get("fast", 0) in (1, 2, 3):
+    if res.get("fast", 0) in (1, 2, 3, 4):
         return "ext-f32 scalings (FP32 mantissa + int32 exponent)"
     return "f64 log potentials"
 

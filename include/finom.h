@@ -54,9 +54,12 @@ typedef enum {
 typedef struct {
     int32_t precision;  /* 0 = FP64 scans, FP64 log potentials as state.
                            1 = FP32-mantissa scans. The state is FP64 log potentials on
-                           the general sweeps (result fast = 0, 2D, d >= 3) and the
-                           scalings U = w 2^(-c/(eps ln 2)) as FP32 mantissa + int32
-                           exponent on the fast and resident sweeps (fast = 1, 2, 3).
+                           the general sweeps (result fast = 0: d >= 3, 2D with an axis
+                           mesh longer than 2048) and the scalings
+                           U = w 2^(-c/(eps ln 2)) as FP32 mantissa + int32 exponent on
+                           the fast and resident sweeps (fast = 1, 2, 3) and the 2D
+                           extended-state loop (fast = 4; c is the sum of the point's
+                           two coordinates).
                            The loop head's stop test uses the loop's own FP32-sum
                            estimate; every stop is then confirmed by an FP64 check of
                            the returned pair (K^T phi with FP64 scans), which is the
@@ -94,9 +97,12 @@ typedef struct {
                              state on chip; single calls and finom_batch members whose
                              tiles fit the GPU at once). Beyond that range: 3 for the
                              resident solver's extended-number variant (same condition),
-                             else 0 (the streaming general sweeps). 0 for precision 0, 2D
-                             and d >= 3 (sinkhorn_w1_nd with one axis reports as
-                             sinkhorn_w1_1d); the server runs 0 or 1.                    */
+                             else 0 (the streaming general sweeps). 2D, precision 1: 4 for
+                             the extended-state loop (every axis mesh of at most 2048
+                             points: one block per line holds the whole line, each pair
+                             of products along one axis in one launch), else 0. 0 for
+                             precision 0 and d >= 3 (sinkhorn_w1_nd with one or two axes
+                             reports as sinkhorn_w1_1d / _2d); the server runs 0, 1 or 4. */
     int32_t resumes;      /* precision 1: stops of the FP32 loop that the FP64 check of
                              the returned pair rejected (the loop then went on); 0 for
                              precision 0                                               */
@@ -368,6 +374,10 @@ void finom_server_destroy(finom_server* srv);
  * fastest per size class for all later calls in the process. With cache_path,
  * results are read from that file if it exists and written to it otherwise.
  * The environment variable FINOM_TILE_CFG (0..4) overrides every choice.
+ * The 2D extended-state loop takes its own line shape (threads per line x
+ * points per thread: 64x4, 256x4, 256x8 by the longest axis mesh, <= 256,
+ * <= 1024, <= 2048 points); FINOM_LINE_SHAPE (0..4: 64x4, 256x4, 256x8, 128x8,
+ * 64x16) picks another that holds the longest mesh.
  */
 int finom_autotune(int32_t precision, const char* cache_path, void* stream);
 /* The tile-shape index used for a line of `merged` = rows + columns elements. */

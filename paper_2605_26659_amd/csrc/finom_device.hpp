@@ -51,6 +51,20 @@ using gptr = T*;
 template <typename T>
 __device__ __forceinline__ gptr<T> gbl(T* p) { return (gptr<T>)p; }
 
+// Workgroups go to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8), and
+// each XCD has an L2 of its own. xcd_block renumbers a grid of G workgroups so
+// that every XCD takes one contiguous range of work items: neighbouring lines
+// of a sweep then meet in one L2 (the strided stores of a 2D sweep fill the
+// same cache lines there instead of reaching memory as partial lines).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    const int q = G / kXcds, r = G % kXcds;
+    const int x = b % kXcds, i = b / kXcds;
+    return x * q + min(x, r) + i;
+}
+
 __device__ __forceinline__ float ldexp_m(float m, int e) { return __builtin_amdgcn_ldexpf(m, e); }
 __device__ __forceinline__ double ldexp_m(double m, int e) { return __builtin_amdgcn_ldexp(m, e); }
 

@@ -338,6 +338,10 @@ JobPlan plan_job(const JobDesc& d, int precision)
         p.o_Bx = take(sizeof(Ext<float>) * p.na);
         p.o_By = take(sizeof(Ext<float>) * p.nb);
     }
+    if (d.dim == 2) {
+        p.lx_shape = ext2d_shape(d.n1, d.m1, d.n2, d.m2, precision);
+        if (p.lx_shape >= 0) p.o_lx = take(ext2d_bytes(d.n1, d.m1, d.n2, d.m2));
+    }
     for (int a = 0; a < d.dim; ++a) {
         p.cfg[a] = tuned_cfg(precision, p.R[a] + p.C[a]);
         const int T = kCfgs[p.cfg[a]].T();
@@ -365,6 +369,7 @@ void Job::bind()
     vr = d.dim == 2 ? (double*)(mem + p.o_vr) : nullptr;
     Bx = p.o_Bx ? (Ext<float>*)(mem + p.o_Bx) : nullptr;
     By = p.o_By ? (Ext<float>*)(mem + p.o_By) : nullptr;
+    if (p.lx_shape >= 0) ext2d_bind(lx, mem + p.o_lx, d.n1, d.m1, d.n2, d.m2, p.lx_shape);
     const int Tc = cost_tile_size();
     for (int a = 0; a < d.dim; ++a) {
         const double* xr = a == 0 ? d.x1 : d.y1;
@@ -536,6 +541,12 @@ void Engine::setup(const std::vector<Job*>& jobs, bool checks)
         const int* d_fr = upload_vec(al, fr);
         hipLaunchKernelGGL(k_scale_tasks, dim3(fr.back()), dim3(kBlock), 0, s_, d_tr, d_fr, (int)tr.size());
         HIPCHK(hipGetLastError());
+    }
+    // 2D FP32 jobs on the extended-state loop: their state and masses
+    for (Job* j : jobs) {
+        j->ext2d = j->p.lx_shape >= 0;
+        if (j->ext2d)
+            ext2d_init(j->lx, j->d.x1, j->d.x2, j->d.y1, j->d.y2, j->lu, j->lvr, 1.0 / (j->d.eps * kLn2), s_);
     }
     // fast-sweep eligibility of the 1D jobs (the static range bound of every tile)
     std::vector<BoundTask> bt;
@@ -808,6 +819,12 @@ void Engine::rebuild()
         hipLaunchKernelGGL(k_init_states, dim3(blocks_for((long long)ini.size())), dim3(kBlock), 0, s_, d_ini,
                            (int)ini.size(), ps_);
         HIPCHK(hipGetLastError());
+        // the extended-state loop's prologue (K_x^T phi of the initial phi)
+        for (Job* j : pending_init_)
+            if (j->ext2d) {
+                ext2d_setup(j->lx, j->pk[0], j->pkt[0], j->pk[1], j->pkt[1], j->slot);
+                ext2d_prologue(j->lx, ps_, s_);
+            }
         pending_init_.clear();
     }
 
@@ -849,10 +866,18 @@ void Engine::rebuild()
     };
 
     std::vector<LineRange> chk(listed_.size()), dcd(listed_.size());
+    lx_listed_.clear();
     for (size_t ji = 0; ji < listed_.size(); ++ji) {
         Job* j = listed_[ji];
         const JobDesc& d = j->d;
         const double eps = d.eps;
+        if (j->ext2d) {
+            // its own launches (ext2d_iteration), decision included
+            ext2d_setup(j->lx, j->pk[0], j->pkt[0], j->pk[1], j->pkt[1], j->slot);
+            lx_listed_.push_back(j);
+            chk[ji] = dcd[ji] = LineRange{-1, 0, 0};
+            continue;
+        }
         if (d.dim == 1) {
             const long long n = d.n1, m = d.n2;
             const int fs = j->fast ? 1 : 0;
@@ -922,6 +947,7 @@ void Engine::rebuild()
     // stop decisions: every line of a job's deciding stage reads the job's
     // partials; the first one records the state
     for (size_t ji = 0; ji < listed_.size(); ++ji) {
+        if (chk[ji].group < 0) continue;
         for (int b = 0; b < 2; ++b) {
             const Sweep& cs = *groups[chk[ji].group].sw[b];
             const int off = cs.lines[chk[ji].first].part_base;
@@ -980,6 +1006,7 @@ void Engine::launch_iterations(int k, hipStream_t s)
         const int b = it & 1;
         for (size_t q = 0; q < seq_[b].size(); ++q)
             launch_sweep(precision_, IN_LOG2, *seq_[b][q], ps_, partial_, dec_[b][q] ? partial_ : nullptr, b, s);
+        for (Job* j : lx_listed_) ext2d_iteration(j->lx, b, ps_, s);
     }
 }
 
@@ -1036,6 +1063,9 @@ void Engine::confirm_stops(std::vector<Job*>& fin)
         for (size_t q = 0; q < todo.size(); ++q) {
             Job* j = todo[q];
             bo[q] = j->resident ? 0 : psi_slot(hps_[j->slot].iters, j->shift);
+            if (j->ext2d)
+                ext2d_to_log2(j->lx, bo[q], j->F, j->G[bo[q]], j->d.x1, j->d.x2, j->d.y1, j->d.y2,
+                              1.0 / (j->d.eps * kLn2), s_);
             if (!j->fast && !j->gen) continue;
             const double kappa = 1.0 / (j->d.eps * kLn2);
             FastStateTask t;
@@ -1126,8 +1156,12 @@ void Engine::confirm_stops(std::vector<Job*>& fin)
                 t.mode = 1;
                 t.out = j->lv; t.in = j->d.v; t.n = j->p.nb; ft.push_back(t);
             }
-            if (bo[q] == 1)
+            if (bo[q] == 1) {
                 HIPCHK(hipMemcpyAsync(j->G[0], j->G[1], sizeof(double) * j->p.nb, hipMemcpyDeviceToDevice, s_));
+                if (j->ext2d)
+                    HIPCHK(hipMemcpyAsync(j->lx.UG[0], j->lx.UG[1], sizeof(Ext<float>) * j->p.nb,
+                                          hipMemcpyDeviceToDevice, s_));
+            }
             j->shift = (int)(l & 1);
             j->resume_k = resume_step(j->resume_k);
             enqueue_rearm(ps_ + j->slot, l, resume_until(l, j->resume_k, j->d.itr_max), s_);
@@ -1257,7 +1291,7 @@ std::vector<Job*> Engine::harvest()
         r.loop_ms = j->loop_ms;
         r.resumes = j->resumes;
         r.status = bad ? FINOM_E_NUMERIC : (r.converged ? FINOM_OK : FINOM_NOT_CONVERGED);
-        r.fast = j->fast ? (j->resident ? 2 : 1) : (j->gen ? 3 : 0);
+        r.fast = j->fast ? (j->resident ? 2 : 1) : (j->gen ? 3 : (j->ext2d ? 4 : 0));
         free_slots_.push(j->slot);
         j->slot = -1;
     }

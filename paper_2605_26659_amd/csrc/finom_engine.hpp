@@ -37,6 +37,8 @@ struct JobPlan {
     int ntiles[2] = {0, 0}, ntiles_c[2] = {0, 0};
     size_t o_lu = 0, o_lv = 0, o_F = 0, o_G0 = 0, o_G1 = 0, o_S = 0, o_Bx = 0, o_By = 0;
     size_t o_lvr = 0, o_vr = 0;   // 2D: log2 v and v row-major, as psi
+    int lx_shape = -1;            // 2D FP32 on the extended-state loop: its line shape
+    size_t o_lx = 0;              // and its arrays (ext2d_bind)
     size_t o_zeta[2] = {0, 0}, o_zeta_t[2] = {0, 0}, o_trs[2] = {0, 0}, o_trs_t[2] = {0, 0},
            o_trs_c[2] = {0, 0};
     size_t bytes = 0;
@@ -62,6 +64,9 @@ struct Job {
     Ext<float>* Bx = nullptr;   // 1D FP32: 2^{2 x kappa} and 2^{2 y kappa} for the fast sweeps
     Ext<float>* By = nullptr;
     bool fast = false;          // runs on the fast sweeps
+    bool ext2d = false;         // 2D FP32 on the extended-state loop (lx; F and G hold log2 potentials only
+                                // for its FP64 checks and the cost)
+    Ext2D lx;
     bool gen = false;           // 1D FP32 beyond the fast bound, for the resident solver's extended-number
                                 // variant (state as for the fast sweeps); only when the engine solves resident
     bool resident = false;      // solved by the resident batch kernel (final psi in G[0])
@@ -135,6 +140,7 @@ private:
     std::vector<Job*> active_;      // live jobs, in join order
     std::vector<Job*> pending_init_;   // joined since the last rebuild
     std::vector<Job*> listed_;      // jobs in the current launch lists
+    std::vector<Job*> lx_listed_;   // of them, the jobs on the extended-state 2D loop
     Arena ar_setup_, ar_loop_, ar_cost_, ar_res_, ar_chk_;
     std::vector<std::unique_ptr<Sweep>> sweeps_;
     std::vector<Sweep*> seq_[2];

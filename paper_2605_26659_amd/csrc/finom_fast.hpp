@@ -666,7 +666,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     __shared__ int s_i[4 * NW];
     __shared__ double s_d[NW];
 
-    const WorkItem w = work[blockIdx.x];
+    const WorkItem w = work[xcd_block(blockIdx.x, gridDim.x)];
     const LineDesc L = lines[w.line];
     ProbState* P = ps + L.prob;
     if (P->done) return;
@@ -740,7 +740,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_aggregate_fast(const WorkItem* _
     constexpr int NW = BLOCK / kWave;
     __shared__ float s_f[2 * NW];
     __shared__ int s_i[2 * NW];
-    const WorkItem w = work[blockIdx.x];
+    const WorkItem w = work[xcd_block(blockIdx.x, gridDim.x)];
     const LineDesc L = lines[w.line];
     if (ps[L.prob].done) return;
     const gptr<const int> TRS = gbl(L.trs);

@@ -14,6 +14,7 @@
 #include "../../include/finom.h"
 #include "finom_fast.hpp"
 #include "finom_kernels.hpp"
+#include "finom_line_ext.hpp"
 
 namespace finom {
 
@@ -368,6 +369,29 @@ inline int psi_slot(long long l, int shift) { return (int)((l & 1) ^ shift); }
 // off (threshold -1), stop at iteration itr_stop, iteration l in both
 // counter slots (iters keeps l: the resident solver starts from it).
 void enqueue_rearm(ProbState* ps, long long l, long long itr_stop, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// The 2D loop on extended-number state (FP32 mode, finom_line_ext.hpp),
+// shared by sinkhorn_w1_2d and the batch engine so that a problem runs the
+// same launches alone and in a batch
+// ---------------------------------------------------------------------------
+// Line shape for a 2D problem (-1: the general sweeps run it).
+int ext2d_shape(long long n1, long long m1, long long n2, long long m2, int precision);
+// Bytes of the arrays, and their carving from one block of that size.
+size_t ext2d_bytes(long long n1, long long m1, long long n2, long long m2);
+void ext2d_bind(Ext2D& e, char* mem, long long n1, long long m1, long long n2, long long m2, int shape);
+// Launch descriptors on the four partitions (px: rows x1, columns x2; py:
+// rows y1, columns y2; *_t transposed) for problem state `prob`.
+void ext2d_setup(Ext2D& e, const Part& px, const Part& px_t, const Part& py, const Part& py_t, int prob);
+// 2^{2 c kappa} per axis, phi = 1 / (n1 m1), psi = 1 / (n2 m2) and the masses
+// from their log2 (lu column-major, lvr row-major).
+void ext2d_init(const Ext2D& e, const double* x1, const double* x2, const double* y1, const double* y2,
+                const double* lu, const double* lvr, double kappa, hipStream_t s);
+void ext2d_prologue(const Ext2D& e, ProbState* ps, hipStream_t s);
+void ext2d_iteration(const Ext2D& e, int parity, ProbState* ps, hipStream_t s);
+// phi and psi (buffer bo) as log2 potentials into F (column-major) and G (row-major).
+void ext2d_to_log2(const Ext2D& e, int bo, double* F, double* G, const double* x1, const double* x2,
+                   const double* y1, const double* y2, double kappa, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Line builders shared by the single-problem solvers and the batch engine

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void k_tile_aggregate(const WorkItem* __rest
     constexpr int NS = MOMENT ? 4 : 2;
     __shared__ Ext<M> s_tmp[BLOCK / kWave];
     __shared__ double s_red[BLOCK / kWave];
-    const WorkItem w = work[blockIdx.x];
+    const WorkItem w = work[xcd_block(blockIdx.x, gridDim.x)];
     const LineDesc L = lines[w.line];
     ProbState* P = ps + L.prob;
     if (P->done) return;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
     __shared__ Ext<M> s_tmp[(NS + 2) * NW];
     __shared__ double s_red[NW];
 
-    const WorkItem w = work[blockIdx.x];
+    const WorkItem w = work[xcd_block(blockIdx.x, gridDim.x)];
     const LineDesc L = lines[w.line];
     ProbState* P = ps + L.prob;
     if (P->done) return;

@@ -711,9 +711,11 @@ struct LoopSpec {
 // on_stop (optional) runs when the state reports a stop; it returns true
 // after re-arming the state for more iterations (a stop that the FP64 check
 // rejected), and the replays go on.
-static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* partial,
-                    long long itr_max, int k, hipStream_t s, ProbState* hps, finom_result* res,
-                    const std::function<bool()>& on_stop = {})
+// The loop of Algorithm 1 / 2: k iterations (body(parity, stream) enqueues
+// one) captured in a HIP graph, replayed until the device state records a
+// stop; on_stop may veto a stop and re-arm the state (the loop then goes on).
+static int run_loop_fn(const std::function<void(int, hipStream_t)>& body, ProbState* ps, long long itr_max, int k,
+                       hipStream_t s, ProbState* hps, finom_result* res, const std::function<bool()>& on_stop = {})
 {
     k += (k & 1);   // even, so every replay starts on parity 0
     hipStream_t cs = nullptr;
@@ -724,12 +726,7 @@ static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* pa
     try {
         HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        for (int it = 0; it < k; ++it) {
-            const int b = it & 1;
-            for (size_t q = 0; q < lp.seq[b].size(); ++q)
-                launch_sweep(precision, IN_LOG2, *lp.seq[b][q], ps, partial,
-                             lp.decides[b][q] ? partial : nullptr, b, cs);
-        }
+        for (int it = 0; it < k; ++it) body(it & 1, cs);
         HIPCHK(hipStreamEndCapture(cs, &graph));
         HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         HIPCHK(hipEventCreate(&ev0));
@@ -776,6 +773,233 @@ static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* pa
     if (graph) hipGraphDestroy(graph);
     if (cs) hipStreamDestroy(cs);
     return st;
+}
+
+static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* partial,
+                    long long itr_max, int k, hipStream_t s, ProbState* hps, finom_result* res,
+                    const std::function<bool()>& on_stop = {})
+{
+    auto body = [&](int b, hipStream_t cs) {
+        for (size_t q = 0; q < lp.seq[b].size(); ++q)
+            launch_sweep(precision, IN_LOG2, *lp.seq[b][q], ps, partial, lp.decides[b][q] ? partial : nullptr, b, cs);
+    };
+    return run_loop_fn(body, ps, itr_max, k, s, hps, res, on_stop);
+}
+
+// ---- 2D loop on extended-number state (FP32 mode): line shapes (threads
+// per line x points per thread), one block per line and the whole line one
+// tile. By default the smallest shape that holds the longest axis mesh;
+// FINOM_LINE_SHAPE (0..4) picks another that holds it.
+struct LineShape {
+    int block, ipt;
+};
+constexpr int kNumLineShapes = 5;
+constexpr LineShape kLineShapes[kNumLineShapes] = {{64, 4}, {256, 4}, {256, 8}, {128, 8}, {64, 16}};
+
+static int line_ext_shape(long long longest)
+{
+    int sh = longest <= 256 ? 0 : longest <= 1024 ? 1 : longest <= 2048 ? 2 : -1;
+    if (sh < 0) return -1;
+    if (const char* e = getenv("FINOM_LINE_SHAPE")) {
+        const int v = atoi(e);
+        if (v >= 0 && v < kNumLineShapes && kLineShapes[v].block * kLineShapes[v].ipt >= longest) sh = v;
+    }
+    return sh;
+}
+
+template <int B, int I>
+static void launch_line_ext_t(const PassExt& d, int nlines, ProbState* ps, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_line_ext<B, I, LX_STORE>), dim3(nlines), dim3(B), 0, s, d, ps, 0);
+    HIPCHK(hipGetLastError());
+}
+
+template <int B, int I>
+static void launch_line_pair_t(const PairExt& pr, bool check, int nlines, ProbState* ps, int parity, hipStream_t s)
+{
+    if (check)
+        hipLaunchKernelGGL((k_line_pair_ext<B, I, true, false>), dim3(nlines), dim3(B), 0, s, pr, ps, parity);
+    else
+        hipLaunchKernelGGL((k_line_pair_ext<B, I, false, true>), dim3(nlines), dim3(B), 0, s, pr, ps, parity);
+    HIPCHK(hipGetLastError());
+}
+
+// One product storing W (the loop's prologue).
+static void launch_line_ext(int shape, const PassExt& d, int nlines, ProbState* ps, hipStream_t s)
+{
+    switch (shape) {
+        case 0: launch_line_ext_t<64, 4>(d, nlines, ps, s); break;
+        case 1: launch_line_ext_t<256, 4>(d, nlines, ps, s); break;
+        case 2: launch_line_ext_t<256, 8>(d, nlines, ps, s); break;
+        case 3: launch_line_ext_t<128, 8>(d, nlines, ps, s); break;
+        default: launch_line_ext_t<64, 16>(d, nlines, ps, s); break;
+    }
+}
+
+// A pair of products per line: the update with the check (psi rows), or the
+// update after the loop head's decision (phi columns).
+static void launch_line_pair(int shape, const PairExt& pr, bool check, int nlines, ProbState* ps, int parity,
+                             hipStream_t s)
+{
+    switch (shape) {
+        case 0: launch_line_pair_t<64, 4>(pr, check, nlines, ps, parity, s); break;
+        case 1: launch_line_pair_t<256, 4>(pr, check, nlines, ps, parity, s); break;
+        case 2: launch_line_pair_t<256, 8>(pr, check, nlines, ps, parity, s); break;
+        case 3: launch_line_pair_t<128, 8>(pr, check, nlines, ps, parity, s); break;
+        default: launch_line_pair_t<64, 16>(pr, check, nlines, ps, parity, s); break;
+    }
+}
+
+static void enqueue_grid_conv(const GridConv& c, hipStream_t s)
+{
+    const long long n = c.nx * c.ny;
+    const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>((n + kConvBlock - 1) / kConvBlock, 65536));
+    hipLaunchKernelGGL(k_grid_conv<0>, dim3(grid), dim3(kConvBlock), 0, s, c);
+    HIPCHK(hipGetLastError());
+}
+
+// log2 potentials g <-> the extended state of a grid (see GridConv)
+static void grid_to_ext(const double* g, double g0, Ext<float>* u, const double* X, const double* Y, long long nx,
+                        long long ny, bool row_major, double kappa, hipStream_t s)
+{
+    GridConv c{};
+    c.g = g;
+    c.u = u;
+    c.X = X;
+    c.Y = Y;
+    c.nx = nx;
+    c.ny = ny;
+    c.g0 = g0;
+    c.kappa = kappa;
+    c.row_major = row_major ? 1 : 0;
+    c.to_ext = 1;
+    enqueue_grid_conv(c, s);
+}
+
+static void grid_to_log2(const Ext<float>* u, double* g, const double* X, const double* Y, long long nx, long long ny,
+                         bool row_major, double kappa, hipStream_t s)
+{
+    GridConv c{};
+    c.gout = g;
+    c.uin = u;
+    c.X = X;
+    c.Y = Y;
+    c.nx = nx;
+    c.ny = ny;
+    c.kappa = kappa;
+    c.row_major = row_major ? 1 : 0;
+    c.to_ext = 0;
+    enqueue_grid_conv(c, s);
+}
+
+int ext2d_shape(long long n1, long long m1, long long n2, long long m2, int precision)
+{
+    if (precision != 1 || !fast_allowed()) return -1;
+    return line_ext_shape(std::max(std::max(n1, n2), std::max(m1, m2)));
+}
+
+size_t ext2d_bytes(long long n1, long long m1, long long n2, long long m2)
+{
+    const long long na = n1 * m1, nb = n2 * m2, ns = n2 * m1;
+    const long long ext = 2 * na + 3 * nb + 2 * ns + n1 + n2 + m1 + m2;
+    return sizeof(Ext<float>) * (size_t)ext + sizeof(double) * (size_t)n2 + 256 * 12;
+}
+
+void ext2d_bind(Ext2D& e, char* mem, long long n1, long long m1, long long n2, long long m2, int shape)
+{
+    e.shape = shape;
+    e.n1 = n1;
+    e.m1 = m1;
+    e.n2 = n2;
+    e.m2 = m2;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = (off + 255) / 256 * 256;
+        off = o + bytes;
+        return mem + o;
+    };
+    const size_t eb = sizeof(Ext<float>);
+    e.UF = (Ext<float>*)take(eb * n1 * m1);
+    e.UG[0] = (Ext<float>*)take(eb * n2 * m2);
+    e.UG[1] = (Ext<float>*)take(eb * n2 * m2);
+    e.SX = (Ext<float>*)take(eb * n2 * m1);
+    e.SY = (Ext<float>*)take(eb * n2 * m1);
+    e.Au = (Ext<float>*)take(eb * n1 * m1);
+    e.Av = (Ext<float>*)take(eb * n2 * m2);
+    e.B[0] = (Ext<float>*)take(eb * n1);
+    e.B[1] = (Ext<float>*)take(eb * n2);
+    e.B[2] = (Ext<float>*)take(eb * m1);
+    e.B[3] = (Ext<float>*)take(eb * m2);
+    e.part = (double*)take(sizeof(double) * n2);
+}
+
+void ext2d_setup(Ext2D& e, const Part& px, const Part& px_t, const Part& py, const Part& py_t, int prob)
+{
+    const long long n1 = e.n1, m1 = e.m1, n2 = e.n2, m2 = e.m2;
+    Ext<float>* const Bx1 = e.B[0];
+    Ext<float>* const Bx2 = e.B[1];
+    Ext<float>* const By1 = e.B[2];
+    Ext<float>* const By2 = e.B[3];
+    // prologue: SX = K_x^T phi along x (line b < m1: column b of phi) into
+    // the row-major intermediate
+    PassExt& t0 = e.pro;
+    t0 = PassExt{};
+    t0.uin = e.UF; t0.uin_line = n1; t0.bc = Bx1; t0.br = Bx2; t0.zeta = px_t.zeta;
+    t0.out = e.SX; t0.out_line = 1; t0.out_elem = m1; t0.R = (int)n2; t0.C = (int)n1; t0.prob = prob;
+    for (int b = 0; b < 2; ++b) {
+        // per psi row c < n2: psi = v / (row c of SX) K_y with the check, then
+        // row c of Psi K_y^T into the column-major SY
+        PairExt& y = e.y[b];
+        y = PairExt{};
+        PassExt& t = y.p1;
+        t.uin = e.SX; t.uin_line = m1; t.bc = By1; t.br = By2; t.zeta = py_t.zeta;
+        t.out = e.UG[1 - b]; t.out_line = m2; t.out_elem = 1; t.a = e.Av; t.a_line = m2; t.uold = e.UG[b];
+        t.partial = e.part; t.R = (int)m2; t.C = (int)m1; t.prob = prob;
+        y.br2 = By1; y.zeta2 = py.zeta; y.out2 = e.SY; y.out2_line = 1; y.out2_elem = n2; y.R2 = (int)m1;
+        // per phi column b < m1, after the loop head's decision: phi = u / K_x
+        // (column b of SY), then K_x^T phi into SX for the next pair
+        PairExt& x = e.x[b];
+        x = PairExt{};
+        PassExt& k = x.p1;
+        k.uin = e.SY; k.uin_line = n2; k.bc = Bx2; k.br = Bx1; k.zeta = px.zeta;
+        k.out = e.UF; k.out_line = n1; k.out_elem = 1; k.a = e.Au; k.a_line = n1; k.R = (int)n1; k.C = (int)n2;
+        k.dec = e.part; k.dec_n = (int)n2; k.prob = prob;
+        x.br2 = Bx2; x.zeta2 = px_t.zeta; x.out2 = e.SX; x.out2_line = 1; x.out2_elem = m1; x.R2 = (int)n2;
+    }
+}
+
+void ext2d_init(const Ext2D& e, const double* x1, const double* x2, const double* y1, const double* y2,
+                const double* lu, const double* lvr, double kappa, hipStream_t s)
+{
+    const double* axes[4] = {x1, x2, y1, y2};
+    const long long lens[4] = {e.n1, e.n2, e.m1, e.m2};
+    for (int a = 0; a < 4; ++a)
+        hipLaunchKernelGGL(k_axis_b<0>, dim3(std::max(1u, std::min(blocks_for(lens[a], kConvBlock), 65536u))),
+                           dim3(kConvBlock), 0, s, axes[a], lens[a], kappa, e.B[a]);
+    HIPCHK(hipGetLastError());
+    const long long na = e.n1 * e.m1, nb = e.n2 * e.m2;
+    grid_to_ext(nullptr, -log2((double)na), e.UF, x1, y1, e.n1, e.m1, false, kappa, s);
+    grid_to_ext(nullptr, -log2((double)nb), e.UG[0], x2, y2, e.n2, e.m2, true, kappa, s);
+    grid_to_ext(lu, 0.0, e.Au, nullptr, nullptr, e.n1, e.m1, false, 0.0, s);
+    grid_to_ext(lvr, 0.0, e.Av, nullptr, nullptr, e.n2, e.m2, true, 0.0, s);
+}
+
+void ext2d_prologue(const Ext2D& e, ProbState* ps, hipStream_t s)
+{
+    launch_line_ext(e.shape, e.pro, (int)e.m1, ps, s);
+}
+
+void ext2d_iteration(const Ext2D& e, int parity, ProbState* ps, hipStream_t s)
+{
+    launch_line_pair(e.shape, e.y[parity], true, (int)e.n2, ps, parity, s);
+    launch_line_pair(e.shape, e.x[parity], false, (int)e.m1, ps, parity, s);
+}
+
+void ext2d_to_log2(const Ext2D& e, int bo, double* F, double* G, const double* x1, const double* x2,
+                   const double* y1, const double* y2, double kappa, hipStream_t s)
+{
+    grid_to_log2(e.UF, F, x1, y1, e.n1, e.m1, false, kappa, s);
+    grid_to_log2(e.UG[bo], G, x2, y2, e.n2, e.m2, true, kappa, s);
 }
 
 static int default_graph_iters(long long points)
@@ -1393,40 +1617,44 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
 
+        // FP32 mode on lines of at most 2048 points: the loop keeps the
+        // grids' scalings as extended numbers (finom_line_ext.hpp), with no
+        // exponential or logarithm per point and iteration
+        const int lx_shape = ext2d_shape(n1, m1, n2, m2, o.precision);
+        const bool ext2d = lx_shape >= 0;
+        const double kappa = 1.0 / (eps * kLn2);
+
         Sweep ktx[2], kty[2], ky[2], kx[2];
         int nchk = 0;
-        for (int b = 0; b < 2; ++b) {
-            ktx[b].cfg = kx[b].cfg = cfg_x;
-            kty[b].cfg = ky[b].cfg = cfg_y;
-            // K^T phi = vec(K_x^T Phi K_y): S = K_x^T Phi (columns), then S K_y (rows of S into rows of psi)
-            ktx[b].epi = EPI_STORE_LOG2;
-            add_2d_kt_x_lines(ktx[b], px_t, eps, F, n1, S, m1);
-            kty[b].epi = EPI_UPDATE_CHECK;
-            add_2d_kt_y_lines(kty[b], py_t, eps, S, m1, G[1 - b], m2, lvr, vr, G[b], n2);
-            nchk = assign_parts(kty[b], 0);
-            // K psi = vec(K_x Psi K_y^T): S = Psi K_y^T (rows of psi), then K_x S (columns into phi)
-            ky[b].epi = EPI_STORE_LOG2;
-            add_2d_k_y_lines(ky[b], py, eps, G[1 - b], m2, S, m1, n2);
-            kx[b].epi = EPI_UPDATE;
-            add_2d_k_x_lines(kx[b], px, eps, S, n2, F, n1, lu, m1);
+        if (!ext2d) {
+            for (int b = 0; b < 2; ++b) {
+                ktx[b].cfg = kx[b].cfg = cfg_x;
+                kty[b].cfg = ky[b].cfg = cfg_y;
+                // K^T phi = vec(K_x^T Phi K_y): S = K_x^T Phi (columns), then S K_y (rows of S into rows of psi)
+                ktx[b].epi = EPI_STORE_LOG2;
+                add_2d_kt_x_lines(ktx[b], px_t, eps, F, n1, S, m1);
+                kty[b].epi = EPI_UPDATE_CHECK;
+                add_2d_kt_y_lines(kty[b], py_t, eps, S, m1, G[1 - b], m2, lvr, vr, G[b], n2);
+                nchk = assign_parts(kty[b], 0);
+                // K psi = vec(K_x Psi K_y^T): S = Psi K_y^T (rows of psi), then K_x S (columns into phi)
+                ky[b].epi = EPI_STORE_LOG2;
+                add_2d_k_y_lines(ky[b], py, eps, G[1 - b], m2, S, m1, n2);
+                kx[b].epi = EPI_UPDATE;
+                add_2d_k_x_lines(kx[b], px, eps, S, n2, F, n1, lu, m1);
+            }
+            for (int b = 0; b < 2; ++b) {
+                set_decision(ky[b], 0, nchk);
+                upload_sweep(al, ktx[b], eb);
+                upload_sweep(al, kty[b], eb);
+                upload_sweep(al, ky[b], eb);
+                upload_sweep(al, kx[b], eb);
+            }
         }
-        for (int b = 0; b < 2; ++b) {
-            set_decision(ky[b], 0, nchk);
-            upload_sweep(al, ktx[b], eb);
-            upload_sweep(al, kty[b], eb);
-            upload_sweep(al, ky[b], eb);
-            upload_sweep(al, kx[b], eb);
-        }
-        const long long ncost = 2LL * m1 * pxc.ntiles;
-        double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
 
         // FP32 mode: every stop is confirmed by the FP64 check of the pair it
         // returns (K^T phi along x then y with FP64 scans)
         const bool confirm = o.precision == 1;
         Sweep ktx64, kty64[2];   // kty64 by the buffer holding the checked psi
-        double* part64 = confirm ? al.dev<double>(nchk) : nullptr;
-        double* err64_d = confirm ? al.dev<double>(1) : nullptr;
-        double* err64_h = confirm ? al.host<double>(1) : nullptr;
         if (confirm) {
             ktx64.cfg = cfg_x;
             ktx64.epi = EPI_STORE_LOG2;
@@ -1436,9 +1664,22 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
                 kty64[bo].cfg = cfg_y;
                 kty64[bo].epi = EPI_UPDATE_CHECK;
                 add_2d_kt_y_lines(kty64[bo], py_t, eps, S, m1, G[1 - bo], m2, lvr, vr, G[bo], n2, 1);
-                assign_parts(kty64[bo], 0);
+                nchk = assign_parts(kty64[bo], 0);
                 upload_sweep(al, kty64[bo], sizeof(Ext<double>));
             }
+        }
+        const long long ncost = 2LL * m1 * pxc.ntiles;
+        double* partial = al.dev<double>(std::max<long long>(std::max<long long>(nchk, ncost), n2));
+        double* part64 = confirm ? al.dev<double>(nchk) : nullptr;
+        double* err64_d = confirm ? al.dev<double>(1) : nullptr;
+        double* err64_h = confirm ? al.host<double>(1) : nullptr;
+
+        // the extended-state loop's arrays and launches
+        Ext2D e;
+        if (ext2d) {
+            ext2d_bind(e, al.dev<char>(ext2d_bytes(n1, m1, n2, m2)), n1, m1, n2, m2, lx_shape);
+            ext2d_setup(e, px, px_t, py, py_t, 0);
+            ext2d_init(e, x1, x2, y1, y2, lu, lvr, kappa, s);
         }
         al.uploaded();
         int shift = 0;          // psi of iteration l in G[(l & 1) ^ shift]
@@ -1446,9 +1687,12 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         long long last_l = -1;   // iteration of the last rejected stop
         long long step = 0;      // iterations run after it
         double err64 = 0.0;
+        // the extended state as log2 potentials (F, and psi's slot bo of G)
+        auto ext_to_log2 = [&](int bo) { ext2d_to_log2(e, bo, F, G[bo], x1, x2, y1, y2, kappa, s); };
         auto on_stop = [&]() -> bool {
             const long long l = hps[0].iters;
             const int bo = psi_slot(l, shift);
+            if (ext2d) ext_to_log2(bo);
             launch_sweep(0, IN_LOG2, ktx64, ps, nullptr, nullptr, 0, s);
             launch_sweep(0, IN_LOG2, kty64[bo], ps, part64, nullptr, 0, s);
             hipLaunchKernelGGL((k_reduce_partials<kBlock>), dim3(1), dim3(kBlock), 0, s, part64, 0, nchk, err64_d);
@@ -1459,7 +1703,10 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
             if (!(err64 > tol) || l >= itr_max || !std::isfinite(err64) || hps[0].status ||
                 !may_resume(l, last_l))
                 return false;
-            if (bo == 1) HIPCHK(hipMemcpyAsync(G[0], G[1], sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
+            if (bo == 1) {
+                if (ext2d) HIPCHK(hipMemcpyAsync(e.UG[0], e.UG[1], sizeof(Ext<float>) * nb, hipMemcpyDeviceToDevice, s));
+                else HIPCHK(hipMemcpyAsync(G[0], G[1], sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
+            }
             shift = (int)(l & 1);
             step = resume_step(step);
             enqueue_rearm(ps, l, resume_until(l, step, itr_max), s);
@@ -1468,14 +1715,25 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
             return true;
         };
 
-        LoopSpec lp;
-        for (int b = 0; b < 2; ++b) {
-            lp.seq[b] = {&ktx[b], &kty[b], &ky[b], &kx[b]};
-            lp.decides[b] = {false, false, true, false};
-        }
         const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((na + nb) / 2);
-        const int st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res,
-                                confirm ? std::function<bool()>(on_stop) : std::function<bool()>());
+        int st;
+        if (ext2d) {
+            // the prologue's S holds K_x^T phi for the first pair; each phi pair
+            // leaves it for the next (a stop keeps phi and S as they were)
+            ext2d_prologue(e, ps, s);
+            auto body = [&](int b, hipStream_t cs) { ext2d_iteration(e, b, ps, cs); };
+            st = run_loop_fn(body, ps, itr_max, kit, s, hps, res,
+                             confirm ? std::function<bool()>(on_stop) : std::function<bool()>());
+            if (st == FINOM_OK) ext_to_log2(psi_slot(hps[0].iters, shift));
+        } else {
+            LoopSpec lp;
+            for (int b = 0; b < 2; ++b) {
+                lp.seq[b] = {&ktx[b], &kty[b], &ky[b], &kx[b]};
+                lp.decides[b] = {false, false, true, false};
+            }
+            st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res,
+                          confirm ? std::function<bool()>(on_stop) : std::function<bool()>());
+        }
         if (st != FINOM_OK) return fail(st);
 
         // <C, Gamma> = sum Phi o (M_x Psi K_y^T) + sum Phi o (K_x Psi M_y^T), M = C o K,
@@ -1515,6 +1773,7 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         finish_result(res, hps[0], hps[1].w1);
         res->sweeps = 4 * hps[0].iters + 2 + 2 * resumes;
         res->resumes = resumes;
+        res->fast = ext2d ? 4 : 0;
         if (hps[0].status) return fail(FINOM_E_NUMERIC);
         return fail(hps[0].converged ? FINOM_OK : FINOM_NOT_CONVERGED);
     } catch (...) {
