@@ -385,7 +385,8 @@ void ext2d_bind(Ext2D& e, char* mem, long long n1, long long m1, long long n2, l
 void ext2d_setup(Ext2D& e, const Part& px, const Part& px_t, const Part& py, const Part& py_t, int prob);
 // 2^{2 c kappa} per axis, phi = 1 / (n1 m1), psi = 1 / (n2 m2) and the masses
 // from their log2 (lu column-major, lvr row-major).
-void ext2d_init(const Ext2D& e, const double* x1, const double* x2, const double* y1, const double* y2,
+// Also decides the scan (Ext2D::s64; reads the axis meshes on the host).
+void ext2d_init(Ext2D& e, const double* x1, const double* x2, const double* y1, const double* y2,
                 const double* lu, const double* lvr, double kappa, hipStream_t s);
 void ext2d_prologue(const Ext2D& e, ProbState* ps, hipStream_t s);
 void ext2d_iteration(const Ext2D& e, int parity, ProbState* ps, hipStream_t s);

@@ -808,45 +808,54 @@ static int line_ext_shape(long long longest)
 }
 
 template <int B, int I>
-static void launch_line_ext_t(const PassExt& d, int nlines, ProbState* ps, hipStream_t s)
+static void launch_line_ext_t(const PassExt& d, bool s64, int nlines, ProbState* ps, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_line_ext<B, I, LX_STORE>), dim3(nlines), dim3(B), 0, s, d, ps, 0);
+    if (s64) hipLaunchKernelGGL((k_line_ext<B, I, LX_STORE, true>), dim3(nlines), dim3(B), 0, s, d, ps, 0);
+    else hipLaunchKernelGGL((k_line_ext<B, I, LX_STORE, false>), dim3(nlines), dim3(B), 0, s, d, ps, 0);
     HIPCHK(hipGetLastError());
 }
 
-template <int B, int I>
-static void launch_line_pair_t(const PairExt& pr, bool check, int nlines, ProbState* ps, int parity, hipStream_t s)
+template <int B, int I, bool S64>
+static void launch_line_pair_s(const PairExt& pr, bool check, int nlines, ProbState* ps, int parity, hipStream_t s)
 {
     if (check)
-        hipLaunchKernelGGL((k_line_pair_ext<B, I, true, false>), dim3(nlines), dim3(B), 0, s, pr, ps, parity);
+        hipLaunchKernelGGL((k_line_pair_ext<B, I, true, false, S64>), dim3(nlines), dim3(B), 0, s, pr, ps, parity);
     else
-        hipLaunchKernelGGL((k_line_pair_ext<B, I, false, true>), dim3(nlines), dim3(B), 0, s, pr, ps, parity);
+        hipLaunchKernelGGL((k_line_pair_ext<B, I, false, true, S64>), dim3(nlines), dim3(B), 0, s, pr, ps, parity);
+}
+
+template <int B, int I>
+static void launch_line_pair_t(const PairExt& pr, bool s64, bool check, int nlines, ProbState* ps, int parity,
+                               hipStream_t s)
+{
+    if (s64) launch_line_pair_s<B, I, true>(pr, check, nlines, ps, parity, s);
+    else launch_line_pair_s<B, I, false>(pr, check, nlines, ps, parity, s);
     HIPCHK(hipGetLastError());
 }
 
 // One product storing W (the loop's prologue).
-static void launch_line_ext(int shape, const PassExt& d, int nlines, ProbState* ps, hipStream_t s)
+static void launch_line_ext(int shape, bool s64, const PassExt& d, int nlines, ProbState* ps, hipStream_t s)
 {
     switch (shape) {
-        case 0: launch_line_ext_t<64, 4>(d, nlines, ps, s); break;
-        case 1: launch_line_ext_t<256, 4>(d, nlines, ps, s); break;
-        case 2: launch_line_ext_t<256, 8>(d, nlines, ps, s); break;
-        case 3: launch_line_ext_t<128, 8>(d, nlines, ps, s); break;
-        default: launch_line_ext_t<64, 16>(d, nlines, ps, s); break;
+        case 0: launch_line_ext_t<64, 4>(d, s64, nlines, ps, s); break;
+        case 1: launch_line_ext_t<256, 4>(d, s64, nlines, ps, s); break;
+        case 2: launch_line_ext_t<256, 8>(d, s64, nlines, ps, s); break;
+        case 3: launch_line_ext_t<128, 8>(d, s64, nlines, ps, s); break;
+        default: launch_line_ext_t<64, 16>(d, s64, nlines, ps, s); break;
     }
 }
 
 // A pair of products per line: the update with the check (psi rows), or the
 // update after the loop head's decision (phi columns).
-static void launch_line_pair(int shape, const PairExt& pr, bool check, int nlines, ProbState* ps, int parity,
-                             hipStream_t s)
+static void launch_line_pair(int shape, bool s64, const PairExt& pr, bool check, int nlines, ProbState* ps,
+                             int parity, hipStream_t s)
 {
     switch (shape) {
-        case 0: launch_line_pair_t<64, 4>(pr, check, nlines, ps, parity, s); break;
-        case 1: launch_line_pair_t<256, 4>(pr, check, nlines, ps, parity, s); break;
-        case 2: launch_line_pair_t<256, 8>(pr, check, nlines, ps, parity, s); break;
-        case 3: launch_line_pair_t<128, 8>(pr, check, nlines, ps, parity, s); break;
-        default: launch_line_pair_t<64, 16>(pr, check, nlines, ps, parity, s); break;
+        case 0: launch_line_pair_t<64, 4>(pr, s64, check, nlines, ps, parity, s); break;
+        case 1: launch_line_pair_t<256, 4>(pr, s64, check, nlines, ps, parity, s); break;
+        case 2: launch_line_pair_t<256, 8>(pr, s64, check, nlines, ps, parity, s); break;
+        case 3: launch_line_pair_t<128, 8>(pr, s64, check, nlines, ps, parity, s); break;
+        default: launch_line_pair_t<64, 16>(pr, s64, check, nlines, ps, parity, s); break;
     }
 }
 
@@ -968,11 +977,32 @@ void ext2d_setup(Ext2D& e, const Part& px, const Part& px_t, const Part& py, con
     }
 }
 
-void ext2d_init(const Ext2D& e, const double* x1, const double* x2, const double* y1, const double* y2,
+// Whether every chunk of every axis mesh (64 IPT consecutive columns of a
+// line, plus one neighbour on each side) spans at most kSpan64 binary orders
+// of kernel decay: 2 kappa (c_last - c_first) (FINOM_LINE_SCAN=ext turns
+// the FP64 scan off).
+static bool ext2d_scan64(const double* const* axes, const long long* lens, int chunk, double kappa)
+{
+    if (const char* e = getenv("FINOM_LINE_SCAN"))
+        if (strcmp(e, "ext") == 0) return false;
+    for (int a = 0; a < 4; ++a) {
+        std::vector<double> h((size_t)lens[a]);
+        HIPCHK(hipMemcpy(h.data(), axes[a], sizeof(double) * lens[a], hipMemcpyDeviceToHost));
+        for (long long c0 = 0; c0 < lens[a]; c0 += chunk) {
+            const long long lo = std::max(c0 - 1, 0LL), hi = std::min(c0 + chunk, lens[a] - 1);
+            if (!(2.0 * kappa * (h[hi] - h[lo]) <= kSpan64)) return false;
+        }
+    }
+    return true;
+}
+
+void ext2d_init(Ext2D& e, const double* x1, const double* x2, const double* y1, const double* y2,
                 const double* lu, const double* lvr, double kappa, hipStream_t s)
 {
     const double* axes[4] = {x1, x2, y1, y2};
     const long long lens[4] = {e.n1, e.n2, e.m1, e.m2};
+    HIPCHK(hipStreamSynchronize(s));   // the meshes are read on the host (they are inputs: nothing pending writes them)
+    e.s64 = ext2d_scan64(axes, lens, kWave * kLineShapes[e.shape].ipt, kappa) ? 1 : 0;
     for (int a = 0; a < 4; ++a)
         hipLaunchKernelGGL(k_axis_b<0>, dim3(std::max(1u, std::min(blocks_for(lens[a], kConvBlock), 65536u))),
                            dim3(kConvBlock), 0, s, axes[a], lens[a], kappa, e.B[a]);
@@ -986,14 +1016,16 @@ void ext2d_init(const Ext2D& e, const double* x1, const double* x2, const double
 
 void ext2d_prologue(const Ext2D& e, ProbState* ps, hipStream_t s)
 {
-    launch_line_ext(e.shape, e.pro, (int)e.m1, ps, s);
+    launch_line_ext(e.shape, e.s64 != 0, e.pro, (int)e.m1, ps, s);
 }
 
 void ext2d_iteration(const Ext2D& e, int parity, ProbState* ps, hipStream_t s)
 {
-    launch_line_pair(e.shape, e.y[parity], true, (int)e.n2, ps, parity, s);
-    launch_line_pair(e.shape, e.x[parity], false, (int)e.m1, ps, parity, s);
+    launch_line_pair(e.shape, e.s64 != 0, e.y[parity], true, (int)e.n2, ps, parity, s);
+    launch_line_pair(e.shape, e.s64 != 0, e.x[parity], false, (int)e.m1, ps, parity, s);
 }
+
+
 
 void ext2d_to_log2(const Ext2D& e, int bo, double* F, double* G, const double* x1, const double* x2,
                    const double* y1, const double* y2, double kappa, hipStream_t s)

@@ -134,7 +134,176 @@ __device__ __forceinline__ void line_scan_ext(Ext<float>* s_l, Ext<float>* s_u, 
     }
 }
 
-template <int BLOCK, int IPT, int EPI>
+// ---- the in-line scan with FP64 mantissas against one reference per wave
+//
+// Wave w of the block owns the chunk of columns [64 IPT w, 64 IPT (w + 1)).
+// Its terms are scaled to the chunk's largest exponent and summed in FP64;
+// chunks are chained by extended-number carries. A term more than 2^-1022
+// below its chunk's largest vanishes. For the prefix L at a row that can only
+// matter if the chunk's largest lower-block term comes after the row, and
+// then that term's upper-block twin enters B R at the row, damped by the
+// kernel over at most the chunk's extent plus one neighbouring column: when
+// 2 kappa times that extent is at most kSpan64 binary orders, B R exceeds the
+// vanished part of L by more than 2^53 (and the same with the two blocks
+// swapped). The host checks the extent per chunk of every axis mesh
+// (ext2d_scan64); otherwise the extended-number scan runs.
+constexpr double kSpan64 = 900.0;
+
+template <int CTRL, int RM = 0xF>
+__device__ __forceinline__ double dpp_f64(double v)   // lanes without a source read 0
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RM, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_incl_prefix_f64(double v)
+{
+    v += dpp_f64<0x111>(v);          // row_shr:1
+    v += dpp_f64<0x112>(v);          // row_shr:2
+    v += dpp_f64<0x114>(v);          // row_shr:4
+    v += dpp_f64<0x118>(v);          // row_shr:8
+    v += dpp_f64<0x142, 0xA>(v);     // row_bcast:15
+    v += dpp_f64<0x143, 0xC>(v);     // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ double wave_incl_suffix_f64(double v)
+{
+    v += dpp_f64<0x101>(v);          // row_shl:1
+    v += dpp_f64<0x102>(v);          // row_shl:2
+    v += dpp_f64<0x104>(v);          // row_shl:4
+    v += dpp_f64<0x108>(v);          // row_shl:8
+    const double t1 = readlane_f64(v, 16), t2 = readlane_f64(v, 32), t3 = readlane_f64(v, 48);
+    const double s1 = t2 + t3;
+    const double s0 = t1 + s1;
+    const int row = (threadIdx.x & (kWave - 1)) >> 4;
+    const double add = (row == 0) ? s0 : (row == 1) ? s1 : (row == 2) ? t3 : 0.0;
+    return v + add;
+}
+
+// Per-wave scan data: the waves' totals and reference exponents (for the
+// carries) and the final reference of every chunk's stored values.
+template <int NW>
+struct LxWaves {
+    double tot[2 * NW];
+    int ref[2 * NW];
+    int R[2 * NW];   // [w]: lower block, [NW + w]: upper block
+};
+
+// The scan of C terms in s_l / s_u (Ext<float>, entry e at lx_pad(e)) into
+// FP64 values in the same slots: entry e of the lower block holds the
+// exclusive prefix, of the upper block the inclusive suffix, each as the
+// mantissa against 2^{W.R[chunk of e]}; entry C gets the total and zero. The
+// caller has passed a barrier since the terms were written, and passes another
+// before reading.
+template <int BLOCK, int IPT>
+__device__ __forceinline__ void line_scan_f64(Ext<float>* s_l, Ext<float>* s_u, int C, LxWaves<BLOCK / kWave>& W)
+{
+    constexpr int NW = BLOCK / kWave;
+    double* const dl_out = reinterpret_cast<double*>(s_l);
+    double* const du_out = reinterpret_cast<double*>(s_u);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int base = threadIdx.x * IPT;
+    // the chunk's terms and their largest exponents (zero terms excluded)
+    Ext<float> vl[IPT], vu[IPT];
+    int ml = kZeroExp, mu = kZeroExp;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        vl[q] = vu[q] = ext_zero<float>();
+        if (base + q < C) {
+            vl[q] = s_l[lx_pad(base + q)];
+            vu[q] = s_u[lx_pad(base + q)];
+        }
+        ml = max(ml, vl[q].m != 0.f ? vl[q].e : kZeroExp);
+        mu = max(mu, vu[q].m != 0.f ? vu[q].e : kZeroExp);
+    }
+    ml = wave_max_i(ml);
+    mu = wave_max_i(mu);
+    double dl[IPT], du[IPT];
+    double sl = 0.0, su = 0.0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        dl[q] = __builtin_amdgcn_ldexp((double)vl[q].m, vl[q].e - ml);
+        du[q] = __builtin_amdgcn_ldexp((double)vu[q].m, vu[q].e - mu);
+        sl += dl[q];
+        su += du[q];
+    }
+    const double il = wave_incl_prefix_f64(sl);
+    const double iu = wave_incl_suffix_f64(su);
+    if (lane == kWave - 1) {
+        W.tot[wid] = il;
+        W.ref[wid] = ml;
+    }
+    if (lane == 0) {
+        W.tot[NW + wid] = iu;
+        W.ref[NW + wid] = mu;
+    }
+    __syncthreads();
+    // carries: the totals of the chunks before (lower) and after (upper)
+    Ext<double> CL = ext_zero<double>(), CU = ext_zero<double>();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wid) CL = ext_add(CL, Ext<double>{W.tot[w], W.ref[w]});
+        if (w > wid) CU = ext_add(CU, Ext<double>{W.tot[NW + w], W.ref[NW + w]});
+    }
+    // the chunk's final references: the larger of its own and the carry's
+    const int Rl = max(ml, CL.e), Ru = max(mu, CU.e);
+    const double cl_rel = __builtin_amdgcn_ldexp(CL.m, CL.e - Rl), cu_rel = __builtin_amdgcn_ldexp(CU.m, CU.e - Ru);
+    const double scl = __builtin_amdgcn_ldexp(1.0, ml - Rl), scu = __builtin_amdgcn_ldexp(1.0, mu - Ru);
+    double run = dpp_f64<0x138>(il);    // wave_shr:1 -> exclusive prefix
+    double runu = dpp_f64<0x130>(iu);   // wave_shl:1 -> exclusive suffix
+    // every entry was read before the barrier above: overwrite in place
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (base + q < C) dl_out[lx_pad(base + q)] = __builtin_fma(run, scl, cl_rel);
+        run += dl[q];
+    }
+#pragma unroll
+    for (int q = IPT - 1; q >= 0; --q) {
+        runu += du[q];
+        if (base + q < C) du_out[lx_pad(base + q)] = __builtin_fma(runu, scu, cu_rel);
+    }
+    if (lane == 0) {
+        W.R[wid] = Rl;
+        W.R[NW + wid] = Ru;
+    }
+    // entry C (a row above every column): in the chunk that holds position C
+    if (lane == 0 && wid == min(C / (kWave * IPT), NW - 1)) {
+        dl_out[lx_pad(C)] = __builtin_fma(readlane_f64(il, kWave - 1), scl, cl_rel);
+        du_out[lx_pad(C)] = 0.0;
+    }
+}
+
+// W = L + B R at a row with dividing index z (after either scan).
+template <int BLOCK, int IPT, bool S64>
+__device__ __forceinline__ Ext<float> lx_row_w(const Ext<float>* s_l, const Ext<float>* s_u,
+                                               const LxWaves<BLOCK / kWave>& Wv, int z, Ext<float> b)
+{
+    constexpr int NW = BLOCK / kWave;
+    if constexpr (S64) {
+        const int w = min(z / (kWave * IPT), NW - 1);
+        const double lm = reinterpret_cast<const double*>(s_l)[lx_pad(z)];
+        const double um = reinterpret_cast<const double*>(s_u)[lx_pad(z)];
+        const Ext<double> Wd = ext_add(Ext<double>{lm, Wv.R[w]}, Ext<double>{um * (double)b.m, Wv.R[NW + w] + b.e});
+        return Ext<float>{(float)__builtin_amdgcn_frexp_mant(Wd.m), Wd.e + __builtin_amdgcn_frexp_exp(Wd.m)};
+    } else {
+        const Ext<float> Lz = s_l[lx_pad(z)], Rz = s_u[lx_pad(z)];
+        return ext_norm(ext_add(Lz, Ext<float>{Rz.m * b.m, Rz.e + b.e}));
+    }
+}
+
+template <int BLOCK, int IPT, int EPI, bool S64>
 __global__ __launch_bounds__(BLOCK) void k_line_ext(PassExt d, ProbState* __restrict__ ps, int parity)
 {
     constexpr int T = BLOCK * IPT;
@@ -144,6 +313,7 @@ __global__ __launch_bounds__(BLOCK) void k_line_ext(PassExt d, ProbState* __rest
     __shared__ Ext<float> s_l[LxLen<T>::value];
     __shared__ Ext<float> s_u[LxLen<T>::value];
     __shared__ Ext<float> s_w[2 * NW];
+    __shared__ LxWaves<NW> s_wv;
     __shared__ double s_red[NW];
 
     const int l = xcd_block(blockIdx.x, gridDim.x);
@@ -207,7 +377,8 @@ __global__ __launch_bounds__(BLOCK) void k_line_ext(PassExt d, ProbState* __rest
         }
     }
     __syncthreads();
-    line_scan_ext<BLOCK, IPT>(s_l, s_u, C, s_w);
+    if constexpr (S64) line_scan_f64<BLOCK, IPT>(s_l, s_u, C, s_wv);
+    else line_scan_ext<BLOCK, IPT>(s_l, s_u, C, s_w);
     __syncthreads();
 
     // ---- rows: W = L + 2^{2 r kappa} R, then the epilogue
@@ -218,9 +389,7 @@ __global__ __launch_bounds__(BLOCK) void k_line_ext(PassExt d, ProbState* __rest
         if (q * BLOCK >= R) break;
         const int i = threadIdx.x + q * BLOCK;
         if (i < R) {
-            const int z = lx_pad(min(max(rz[q], 0), C));
-            const Ext<float> Lz = s_l[z], Rz = s_u[z];
-            const Ext<float> W = ext_norm(ext_add(Lz, Ext<float>{Rz.m * rb[q].m, Rz.e + rb[q].e}));
+            const Ext<float> W = lx_row_w<BLOCK, IPT, S64>(s_l, s_u, s_wv, min(max(rz[q], 0), C), rb[q]);
             if (!UPD) {
                 OUT[(long long)i * d.out_elem] = W;
             } else {
@@ -263,7 +432,7 @@ struct PairExt {
     int R2;
 };
 
-template <int BLOCK, int IPT, bool CHECK, bool DECIDE>
+template <int BLOCK, int IPT, bool CHECK, bool DECIDE, bool S64>
 __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* __restrict__ ps, int parity)
 {
     constexpr int T = BLOCK * IPT;
@@ -271,6 +440,7 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
     __shared__ Ext<float> s_l[LxLen<T>::value];
     __shared__ Ext<float> s_u[LxLen<T>::value];
     __shared__ Ext<float> s_w[2 * NW];
+    __shared__ LxWaves<NW> s_wv;
     __shared__ double s_red[NW];
 
     const PassExt& d = pr.p1;
@@ -340,7 +510,8 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
         }
     }
     __syncthreads();
-    line_scan_ext<BLOCK, IPT>(s_l, s_u, C, s_w);
+    if constexpr (S64) line_scan_f64<BLOCK, IPT>(s_l, s_u, C, s_wv);
+    else line_scan_ext<BLOCK, IPT>(s_l, s_u, C, s_w);
     __syncthreads();
     const gptr<Ext<float>> OUT = gbl(d.out) + (long long)l * d.out_line;
     Ext<float> un[IPT];
@@ -350,9 +521,7 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
         if (q * BLOCK >= R) break;
         const int i = threadIdx.x + q * BLOCK;
         if (i < R) {
-            const int z = lx_pad(min(max(rz[q], 0), C));
-            const Ext<float> Lz = s_l[z], Rz = s_u[z];
-            const Ext<float> W = ext_norm(ext_add(Lz, Ext<float>{Rz.m * rb[q].m, Rz.e + rb[q].e}));
+            const Ext<float> W = lx_row_w<BLOCK, IPT, S64>(s_l, s_u, s_wv, min(max(rz[q], 0), C), rb[q]);
             const Ext<float> A = ra[q];
             un[q] = ext_norm(Ext<float>{A.m * __builtin_amdgcn_rcpf(W.m), A.e - W.e});
             if (CHECK) {
@@ -383,18 +552,17 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
         }
     }
     __syncthreads();
-    line_scan_ext<BLOCK, IPT>(s_l, s_u, R, s_w);
+    if constexpr (S64) line_scan_f64<BLOCK, IPT>(s_l, s_u, R, s_wv);
+    else line_scan_ext<BLOCK, IPT>(s_l, s_u, R, s_w);
     __syncthreads();
     const gptr<Ext<float>> OUT2 = gbl(pr.out2) + (long long)l * pr.out2_line;
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         if (q * BLOCK >= R2) break;
         const int i = threadIdx.x + q * BLOCK;
-        if (i < R2) {
-            const int z = lx_pad(min(max(rz2[q], 0), R));
-            const Ext<float> Lz = s_l[z], Rz = s_u[z];
-            OUT2[(long long)i * pr.out2_elem] = ext_norm(ext_add(Lz, Ext<float>{Rz.m * rb2[q].m, Rz.e + rb2[q].e}));
-        }
+        if (i < R2)
+            OUT2[(long long)i * pr.out2_elem] = lx_row_w<BLOCK, IPT, S64>(s_l, s_u, s_wv, min(max(rz2[q], 0), R),
+                                                                          rb2[q]);
     }
 }
 
@@ -402,6 +570,7 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
 // (host side; filled by ext2d_bind / ext2d_setup in the library).
 struct Ext2D {
     int shape = -1;                     // line shape (-1: not eligible)
+    int s64 = 0;                        // every chunk of every axis mesh within kSpan64: the FP64 scan
     long long n1 = 0, m1 = 0, n2 = 0, m2 = 0;
     Ext<float>* UF = nullptr;           // phi's scalings, column-major n1 x m1
     Ext<float>* UG[2] = {nullptr, nullptr};   // psi's, row-major n2 x m2 (two buffers)

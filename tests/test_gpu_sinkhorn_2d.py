@@ -6,7 +6,9 @@
 * product measures: the 2D iterate equals the product of the two 1D
   iterates and the cost splits into the 1D costs;
 * unequal grids (n1 != n2, m1 != m2), FP32 scans at convergence;
-* the 1024 x 1024 tanh-stretched workload at a fixed iteration count.
+* the 1024 x 1024 tanh-stretched workload at a fixed iteration count;
+* the FP32 loop on extended-number state for every line shape and both
+  in-line scans, with small eps and zero masses, and on degenerate grids.
 """
 import numpy as np
 import pytest
@@ -142,9 +144,10 @@ def test_error_statuses_2d():
     assert e.value.status == FINOM_E_MASS
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("n1,m1,n2,m2", [(1, 5, 7, 1), (5, 1, 1, 6), (1, 1, 4, 3), (6, 4, 1, 1), (2, 300, 3, 257),
                                          (300, 2, 257, 3)])
-def test_degenerate_and_thin_grids(n1, m1, n2, m2):
+def test_degenerate_and_thin_grids(n1, m1, n2, m2, precision):
     """Grids of one row or one column and thin grids: psi is row-major inside
     the solver, so these are the cases where its transposes and the strides
     of the intermediates degenerate. Some of these problems are solved
@@ -154,10 +157,68 @@ def test_degenerate_and_thin_grids(n1, m1, n2, m2):
     x1, y1 = np.sort(rng.uniform(0, 1, n1)), np.sort(rng.uniform(0, 1, m1))
     x2, y2 = np.sort(rng.uniform(0, 1, n2)), np.sort(rng.uniform(0, 1, m2))
     u = wl.normalise(rng.uniform(0.1, 1, (n1, m1))); v = wl.normalise(rng.uniform(0.1, 1, (n2, m2)))
-    p = wl.Problem2D(x1, y1, x2, y2, u, v, 0.05, 1e-12, 12)
-    res, F, G = _solve(p)
-    ref = dense.sinkhorn_2d(x1, y1, x2, y2, u, v, 0.05, 1e-12, 12)
-    assert res["iters"] == ref.iters
-    assert np.max(np.abs(F - ref.f)) / 0.05 <= 1e-9
-    assert np.max(np.abs(G - ref.g)) / 0.05 <= 1e-9
-    assert abs(res["w1"] - ref.w1) <= 1e-10 * ref.w1
+    if precision == 0:
+        p = wl.Problem2D(x1, y1, x2, y2, u, v, 0.05, 1e-12, 12)
+        res, F, G = _solve(p)
+        ref = dense.sinkhorn_2d(x1, y1, x2, y2, u, v, 0.05, 1e-12, 12)
+        assert res["iters"] == ref.iters
+        tol, wtol = 1e-9, 1e-10
+    else:
+        # FP32 (the extended-state loop: lines of one point and thin lines):
+        # a fixed count, as its error floor is far above 1e-12 (the oracle
+        # stops early where one iteration solves the problem exactly: its
+        # error is then 0, and later iterations keep that fixed point)
+        p = wl.Problem2D(x1, y1, x2, y2, u, v, 0.05, 0.0, 12)
+        res, F, G = _solve(p, precision=1)
+        assert res["fast"] == 4 and res["iters"] == 12
+        ref = dense.sinkhorn_2d(x1, y1, x2, y2, u, v, 0.05, 0.0, 12)
+        assert ref.iters == 12 or ref.err == 0.0
+        tol, wtol = 2e-5, 1e-6
+    assert np.max(np.abs(F - ref.f)) / 0.05 <= tol
+    assert np.max(np.abs(G - ref.g)) / 0.05 <= tol
+    assert abs(res["w1"] - ref.w1) <= wtol * ref.w1
+
+
+@pytest.mark.parametrize("scan", ["f64", "ext"])
+@pytest.mark.parametrize("shape", [None, 0, 1, 2, 3, 4])
+def test_extended_state_loop_against_algorithm2(shape, scan, monkeypatch):
+    """The FP32 loop on extended-number state (result fast = 4) for every line
+    shape and both in-line scans (FP64 mantissas against a reference per wave,
+    and extended numbers), on unequal ragged grids (several waves per line, a
+    partial last one), at a fixed iteration count against Algorithm 2 in C."""
+    if shape is not None:
+        monkeypatch.setenv("FINOM_LINE_SHAPE", str(shape))
+    if scan == "ext":
+        monkeypatch.setenv("FINOM_LINE_SCAN", "ext")
+    rng = np.random.default_rng(17)
+    n1, m1, n2, m2 = 200, 131, 173, 250
+    p = wl.Problem2D(np.sort(rng.uniform(0, 1, n1)), np.sort(rng.uniform(0, 1, m1)),
+                     np.sort(rng.uniform(0, 1, n2)), np.sort(rng.uniform(0, 1, m2)),
+                     wl.normalise(rng.uniform(.1, 1, (n1, m1))),
+                     wl.normalise(rng.uniform(.1, 1, (n2, m2))), 0.02, 0.0, 40)
+    res, F, G = _solve(p, precision=1)
+    assert res["fast"] == 4 and res["iters"] == 40
+    Fo, Go, ito, erro = clib.sinkhorn_2d(p.x1, p.y1, p.x2, p.y2, p.u, p.v, p.eps, 0.0, 40)
+    assert np.max(np.abs(F - Fo)) / p.eps <= 2e-5
+    assert np.max(np.abs(G - Go)) / p.eps <= 2e-5
+    # the returned pair's error is the FP64 check's
+    assert abs(res["marginal_err"] - erro) <= 1e-5 * erro
+
+
+def test_extended_state_loop_small_eps():
+    """eps small enough that a wave's columns span far more than FP64's range
+    of kernel decay (the extended-number scan runs), masses spanning many
+    orders of magnitude."""
+    rng = np.random.default_rng(19)
+    n1, m1, n2, m2 = 300, 90, 120, 280
+    u = np.exp(rng.uniform(-40, 0, (n1, m1)))
+    v = np.exp(rng.uniform(-40, 0, (n2, m2)))
+    p = wl.Problem2D(np.sort(rng.uniform(0, 1, n1)), np.sort(rng.uniform(0, 1, m1)),
+                     np.sort(rng.uniform(0, 1, n2)), np.sort(rng.uniform(0, 1, m2)),
+                     wl.normalise(u), wl.normalise(v), 2e-3, 0.0, 30)
+    res, F, G = _solve(p, precision=1)
+    assert res["fast"] == 4 and res["iters"] == 30
+    Fo, Go, ito, erro = clib.sinkhorn_2d(p.x1, p.y1, p.x2, p.y2, p.u, p.v, p.eps, 0.0, 30)
+    assert np.max(np.abs(F - Fo)) / p.eps <= 2e-5
+    assert np.max(np.abs(G - Go)) / p.eps <= 2e-5
+    assert abs(res["marginal_err"] - erro) <= 1e-5 * erro
