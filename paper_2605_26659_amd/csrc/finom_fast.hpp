@@ -589,6 +589,10 @@ __device__ __forceinline__ void fast_fixed_loads(const LineDesc& L, const Ext<fl
     }
 }
 
+// The BIG loops request kFastBatch elements per thread before adding any of
+// them (one memory latency per batch, not per element), in the same order.
+constexpr int kFastBatch = 8;
+
 template <int BLOCK, bool BIG>
 __device__ __forceinline__ double fast_decision_sum(const LineDesc& L, const double* dec_partial, int np,
                                                     const double (&df)[kFastFix])
@@ -598,8 +602,17 @@ __device__ __forceinline__ double fast_decision_sum(const LineDesc& L, const dou
 #pragma unroll
         for (int f = 0; f < kFastFix; ++f)
             if ((int)threadIdx.x + f * BLOCK < np) dv += df[f];
-        if constexpr (BIG)
-            for (int k = threadIdx.x + kFastFix * BLOCK; k < np; k += BLOCK) dv += dec_partial[L.dec_part_off + k];
+        if constexpr (BIG) {
+            const gptr<const double> DP = gbl(dec_partial) + L.dec_part_off;
+            for (int k0 = threadIdx.x + kFastFix * BLOCK; k0 < np; k0 += kFastBatch * BLOCK) {
+                double v[kFastBatch];
+#pragma unroll
+                for (int u = 0; u < kFastBatch; ++u) v[u] = DP[min(k0 + u * BLOCK, np - 1)];
+#pragma unroll
+                for (int u = 0; u < kFastBatch; ++u)
+                    if (k0 + u * BLOCK < np) dv += v[u];
+            }
+        }
     }
     return dv;
 }
@@ -619,10 +632,20 @@ __device__ __forceinline__ void fast_carries(const LineDesc& L, const Ext<float>
         if (t < nt && t > tile) au = ext_add(au, af[f][1]);
     }
     if constexpr (BIG) {
-        for (int t = threadIdx.x + kFastFix * BLOCK; t < nt; t += BLOCK) {
-            const gptr<const Ext<float>> a = gbl(agg) + (long long)(L.agg_base + t) * 2;
-            if (t < tile) al = ext_add(al, a[0]);
-            else if (t > tile) au = ext_add(au, a[1]);
+        const gptr<const Ext<float>> AG = gbl(agg) + (long long)L.agg_base * 2;
+        for (int t0 = threadIdx.x + kFastFix * BLOCK; t0 < nt; t0 += kFastBatch * BLOCK) {
+            Ext<float> v[kFastBatch];
+#pragma unroll
+            for (int u = 0; u < kFastBatch; ++u) {
+                const int t = min(t0 + u * BLOCK, nt - 1);
+                v[u] = AG[2 * t + (t > tile ? 1 : 0)];   // lower total before the tile, upper after
+            }
+#pragma unroll
+            for (int u = 0; u < kFastBatch; ++u) {
+                const int t = t0 + u * BLOCK;
+                if (t < nt && t < tile) al = ext_add(al, v[u]);
+                else if (t < nt && t > tile) au = ext_add(au, v[u]);
+            }
         }
     }
     cl = RefAcc{al.m, al.e};
@@ -647,6 +670,83 @@ __device__ __forceinline__ double block_read_sum(const double* s)
 }
 
 // One tile per block.
+// Lines with more tiles than kFastFix per thread take their carries from
+// k_fast_carries (two numbers per tile, computed once per sweep) instead of
+// every tile's totals, and that kernel takes their stop decision.
+template <int BLOCK>
+__device__ __forceinline__ bool fast_carried(const LineDesc& L) { return L.ntiles > kFastFix * BLOCK; }
+
+// One block per carried line: the stop decision (with dec_partial) and the
+// carries of every tile, the exclusive prefix of the tiles' lower totals and
+// the exclusive suffix of their upper totals (carries laid out as agg).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fast_carries(const int* __restrict__ big, const LineDesc* __restrict__ lines,
+                                                       ProbState* __restrict__ ps, const Ext<float>* __restrict__ agg,
+                                                       Ext<float>* __restrict__ carries,
+                                                       const double* __restrict__ dec_partial, int parity)
+{
+    constexpr int NW = BLOCK / kWave;
+    constexpr int U = kFastBatch;
+    __shared__ Ext<float> s_tmp[2 * NW];
+    __shared__ double s_red[NW];
+    const LineDesc L = lines[big[blockIdx.x]];
+    ProbState* P = ps + L.prob;
+    if (P->done) return;
+    if (dec_partial && L.dec_part_off >= 0) {
+        const double err = block_sum_f64<BLOCK>(strided_sum<BLOCK>(dec_partial + L.dec_part_off, L.dec_nparts), s_red);
+        if (fast_decide(L, 0, P, err, parity)) return;
+    }
+    const int nt = L.ntiles;
+    const int ch = (nt + BLOCK - 1) / BLOCK;   // tiles per thread, consecutive
+    const int t0 = threadIdx.x * ch, t1 = min(t0 + ch, nt);
+    const gptr<const Ext<float>> AG = gbl(agg) + (long long)L.agg_base * 2;
+    const gptr<Ext<float>> CR = gbl(carries) + (long long)L.agg_base * 2;
+    // the chunk's totals (U tiles requested before any is added)
+    Ext<float> sl = ext_zero<float>(), su = ext_zero<float>();
+    for (int a = t0; a < t1; a += U) {
+        Ext<float> vl[U], vu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(a + u, t1 - 1);
+            vl[u] = AG[2 * t];
+            vu[u] = AG[2 * t + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (a + u < t1) {
+                sl = ext_add(sl, vl[u]);
+                su = ext_add(su, vu[u]);
+            }
+    }
+    Ext<float> el, eu, tl, tu;
+    block_scan_both<float, BLOCK>(sl, su, el, eu, tl, tu, s_tmp);
+    // per tile: the lower totals before it, the upper totals after it
+    Ext<float> run = el;
+    for (int a = t0; a < t1; a += U) {
+        Ext<float> vl[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) vl[u] = AG[2 * min(a + u, t1 - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (a + u < t1) {
+                CR[2 * (a + u)] = run;
+                run = ext_add(run, vl[u]);
+            }
+    }
+    Ext<float> runu = eu;
+    for (int b = t1 - 1; b >= t0; b -= U) {
+        Ext<float> vu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) vu[u] = AG[2 * max(b - u, t0) + 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b - u >= t0) {
+                CR[2 * (b - u) + 1] = runu;
+                runu = ext_add(runu, vu[u]);
+            }
+    }
+}
+
 template <int BLOCK, int IPT, int EPI, bool NEXT_AGG, bool BIG>
 __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict__ work,
                                                      const LineDesc* __restrict__ lines,
@@ -654,7 +754,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
                                                      const Ext<float>* __restrict__ agg,
                                                      double* __restrict__ partial,
                                                      const double* __restrict__ dec_partial, int parity,
-                                                     Ext<float>* __restrict__ agg_next)
+                                                     Ext<float>* __restrict__ agg_next,
+                                                     const Ext<float>* __restrict__ carries)
 {
     static_assert(IPT % 4 == 0, "chunks are read as float4");
     constexpr int T = BLOCK * IPT;
@@ -671,15 +772,22 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     ProbState* P = ps + L.prob;
     if (P->done) return;
     const gptr<const int> TRS = gbl(L.trs);
-    const bool decide = dec_partial && L.dec_part_off >= 0;
+    const bool carried = fast_carried<BLOCK>(L);
+    const bool decide = dec_partial && L.dec_part_off >= 0 && !carried;
     const int np = decide ? L.dec_nparts : 0;
-    const bool multi = L.ntiles > 1;
+    const bool multi = L.ntiles > 1 && !carried;
 
     // ---- loads, in the order they are consumed (the memory counter retires
     // them in issue order)
     Ext<float> af[kFastFix][2];
     double df[kFastFix];
-    fast_fixed_loads<BLOCK>(L, agg, dec_partial, np, af, df);
+    Ext<float> CL = ext_zero<float>(), CU = ext_zero<float>();
+    if (carried) {
+        CL = carries[(long long)(L.agg_base + w.tile) * 2];
+        CU = carries[(long long)(L.agg_base + w.tile) * 2 + 1];
+    } else {
+        fast_fixed_loads<BLOCK>(L, agg, dec_partial, np, af, df);
+    }
     FastTileIn<IPT> A;
     A.tg = fast_geom(L, w.tile, T, TRS[w.tile], TRS[w.tile + 1]);
     fast_tile_load<BLOCK, IPT>(A, L);
@@ -694,7 +802,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     if (decide) wave_sum_to<BLOCK>(dv, s_d);
     __syncthreads();
     if (decide && fast_decide(L, w.tile, P, block_read_sum<BLOCK>(s_d), parity)) return;
-    Ext<float> CL = ext_zero<float>(), CU = ext_zero<float>();
     if (multi) {
         CL = block_total_read<BLOCK>(s_f + 2 * NW, s_i + 2 * NW);
         CU = block_total_read<BLOCK>(s_f + 3 * NW, s_i + 3 * NW);
@@ -712,13 +819,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     fast_tile_store<BLOCK, IPT>(A, L, un);
 
     // ---- epilogue: the tile's check partial and next-sweep aggregates
+    const bool tiles = L.ntiles > 1;
     if (CHECK) wave_sum_to<BLOCK>(red, s_d);
-    if (NEXT_AGG && multi) block_total2_write<BLOCK>(n1, n2, s_f, s_i);
-    if (CHECK || (NEXT_AGG && multi)) {
+    if (NEXT_AGG && tiles) block_total2_write<BLOCK>(n1, n2, s_f, s_i);
+    if (CHECK || (NEXT_AGG && tiles)) {
         __syncthreads();
         if (threadIdx.x == 0) {
             if (CHECK) partial[L.part_base + w.tile] = block_read_sum<BLOCK>(s_d);
-            if (NEXT_AGG && multi) {
+            if (NEXT_AGG && tiles) {
                 agg_next[(long long)(L.agg_base + w.tile) * 2 + 0] = block_total_read<BLOCK>(s_f, s_i);
                 agg_next[(long long)(L.agg_base + w.tile) * 2 + 1] = block_total_read<BLOCK>(s_f + NW, s_i + NW);
             }

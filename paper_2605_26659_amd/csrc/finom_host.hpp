@@ -156,8 +156,11 @@ struct Alloc {
 struct SweepDev {
     const WorkItem* work = nullptr;        // all tiles
     int nwork = 0;
-    int max_tiles = 0;                     // largest tile count of a line
-    int max_dec = 0;                       // largest number of decision partials of a line
+    int max_tiles = 0;                     // largest tile count of a line (fast sweeps: of the uncarried)
+    int max_dec = 0;                       // largest number of decision partials of a line (idem)
+    const int* big = nullptr;              // fast sweeps: lines whose carries k_fast_carries forms
+    int nbig = 0;
+    void* carries = nullptr;               // their carries, laid out as agg
     const WorkItem* work_multi = nullptr;  // tiles of lines with more than one tile
     int nwork_multi = 0;
     const LineDesc* lines = nullptr;

@@ -80,6 +80,26 @@ __device__ __forceinline__ void column_terms(const LineDesc& L, long long j, Ext
     }
 }
 
+// A thread's sum of p[t], p[t + BLOCK], ... (t = threadIdx.x) below n, in that
+// order, with eight loads requested before any is added (one memory latency
+// per eight elements).
+template <int BLOCK>
+__device__ __forceinline__ double strided_sum(const double* p, int n)
+{
+    constexpr int U = 8;
+    const gptr<const double> P = gbl(p);
+    double s = 0.0;
+    for (int k0 = threadIdx.x; k0 < n; k0 += U * BLOCK) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = P[min(k0 + u * BLOCK, n - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u * BLOCK < n) s += v[u];
+    }
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // Stop decision of Algorithm 1's loop head, taken by every block of the first
 // kernel after a checking sweep from that sweep's per-tile partial errors.
@@ -92,8 +112,7 @@ __device__ __forceinline__ bool decide_stop(const LineDesc& L, int tile, ProbSta
                                             const double* __restrict__ partial, int parity,
                                             double* s_red)
 {
-    double v = 0.0;
-    for (int k = threadIdx.x; k < L.dec_nparts; k += BLOCK) v += partial[L.dec_part_off + k];
+    const double v = strided_sum<BLOCK>(partial + L.dec_part_off, L.dec_nparts);
     const double err = block_sum_f64<BLOCK>(v, s_red);
     const long long l = P->cnt[parity];
     const bool stop = (l >= P->itr_max) || !(err > P->tol);
@@ -215,20 +234,34 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
 #pragma unroll
     for (int s = 0; s < NS; ++s) cr[s] = ext_zero<M>();
     if (L.ntiles > 1) {
-        for (int t = threadIdx.x; t < L.ntiles; t += BLOCK) {
-            const Ext<M>* a = agg + (long long)(L.agg_base + t) * NS;
-            if (t < w.tile) {
-                cr[0] = ext_add(cr[0], a[0]);
-                if (MOMENT) cr[2] = ext_add(cr[2], a[2]);
-            } else if (t > w.tile) {
-                cr[1] = ext_add(cr[1], a[1]);
-                if (MOMENT) cr[3] = ext_add(cr[3], a[3]);
+        // eight tiles' totals requested before any is added, in tile order
+        constexpr int U = 8;
+        const int nt = L.ntiles;
+        const gptr<const Ext<M>> AG = gbl(agg) + (long long)L.agg_base * NS;
+        for (int t0 = threadIdx.x; t0 < nt; t0 += U * BLOCK) {
+            Ext<M> v0[U], v1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = min(t0 + u * BLOCK, nt - 1);
+                const int sel = t > w.tile ? 1 : 0;   // lower total before the tile, upper after
+                v0[u] = AG[(long long)t * NS + sel];
+                if (MOMENT) v1[u] = AG[(long long)t * NS + 2 + sel];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * BLOCK;
+                if (t < nt && t < w.tile) {
+                    cr[0] = ext_add(cr[0], v0[u]);
+                    if (MOMENT) cr[2] = ext_add(cr[2], v1[u]);
+                } else if (t < nt && t > w.tile) {
+                    cr[1] = ext_add(cr[1], v0[u]);
+                    if (MOMENT) cr[3] = ext_add(cr[3], v1[u]);
+                }
             }
         }
     }
     double dv = 0.0;
-    if (decide)
-        for (int k = threadIdx.x; k < L.dec_nparts; k += BLOCK) dv += dec_partial[L.dec_part_off + k];
+    if (decide) dv = strided_sum<BLOCK>(dec_partial + L.dec_part_off, L.dec_nparts);
 
     // ---- B. stop decision of the loop head (uniform across the block)
     if (decide) {

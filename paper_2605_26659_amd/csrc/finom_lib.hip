@@ -245,9 +245,29 @@ void upload_sweep(Alloc& al, Sweep& sw, size_t ext_b)
     HIPCHK(hipMemcpyAsync(dl, hl, sizeof(LineDesc) * sw.lines.size(), hipMemcpyHostToDevice, al.s));
     sw.dev.max_tiles = 0;
     sw.dev.max_dec = 0;
-    for (auto& L : sw.lines) {
+    // fast sweeps: lines with more tiles than two per thread get their carries
+    // from k_fast_carries (fast_carried in finom_fast.hpp)
+    const int carry_limit = sw.fast ? kFastFix * kCfgs[sw.cfg].block : INT32_MAX;
+    std::vector<int> big;
+    for (size_t li = 0; li < sw.lines.size(); ++li) {
+        const LineDesc& L = sw.lines[li];
+        if (L.ntiles > carry_limit) {
+            big.push_back((int)li);
+            continue;
+        }
         sw.dev.max_tiles = std::max(sw.dev.max_tiles, L.ntiles);
         if (L.dec_part_off >= 0) sw.dev.max_dec = std::max(sw.dev.max_dec, L.dec_nparts);
+    }
+    sw.dev.nbig = (int)big.size();
+    sw.dev.big = nullptr;
+    sw.dev.carries = nullptr;
+    if (!big.empty()) {
+        int* hb = al.host<int>(big.size());
+        std::copy(big.begin(), big.end(), hb);
+        int* db = al.dev<int>(big.size());
+        HIPCHK(hipMemcpyAsync(db, hb, sizeof(int) * big.size(), hipMemcpyHostToDevice, al.s));
+        sw.dev.big = db;
+        sw.dev.carries = al.dev<char>((size_t)std::max(mt, 1) * ns * ext_b);
     }
     sw.dev.work = dw;
     sw.dev.nwork = tt;
@@ -302,13 +322,19 @@ static void launch_fast_t(const Sweep& sw, ProbState* ps, double* partial, const
         hipLaunchKernelGGL((k_tile_aggregate_fast<B, I>), dim3(d.nwork_multi), dim3(B), 0, s, d.work_multi, d.lines,
                            ps, (Ext<float>*)d.agg);
     if (!agg_only) {
-        // two fixed slots per thread cover the carries and the decision
-        if (d.max_tiles > 2 * B || d.max_dec > 2 * B)
+        // the carried lines' carries (and their stop decision) first
+        if (d.nbig > 0)
+            hipLaunchKernelGGL((k_fast_carries<B>), dim3(d.nbig), dim3(B), 0, s, d.big, d.lines, ps,
+                               (const Ext<float>*)d.agg, (Ext<float>*)d.carries, dec, parity);
+        // two fixed slots per thread cover the other lines' carries and decision
+        if (d.max_tiles > kFastFix * B || d.max_dec > kFastFix * B)
             hipLaunchKernelGGL((k_sweep_fast<B, I, EPI, NA, true>), dim3(d.nwork), dim3(B), 0, s, d.work, d.lines,
-                               ps, (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next);
+                               ps, (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next,
+                               (const Ext<float>*)d.carries);
         else
             hipLaunchKernelGGL((k_sweep_fast<B, I, EPI, NA, false>), dim3(d.nwork), dim3(B), 0, s, d.work, d.lines,
-                               ps, (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next);
+                               ps, (const Ext<float>*)d.agg, partial, dec, parity, (Ext<float>*)sw.agg_next,
+                               (const Ext<float>*)d.carries);
     }
     HIPCHK(hipGetLastError());
 }
