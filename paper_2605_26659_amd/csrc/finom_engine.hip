@@ -1295,10 +1295,20 @@ std::vector<Job*> Engine::harvest()
         free_slots_.push(j->slot);
         j->slot = -1;
     }
-    std::vector<Job*> keep;
-    for (Job* j : active_)
-        if (j->slot >= 0) keep.push_back(j);
-    active_.swap(keep);
+    // The caller may free the finished jobs once this returns: no list keeps
+    // them. Their lines in the uploaded sweeps stay until the next rebuild and
+    // return at once (their slots are done, and a slot is reused only by add(),
+    // which forces that rebuild); the extended-state launches read the job
+    // itself on the host, so those go now.
+    auto live = [](std::vector<Job*>& v) {
+        std::vector<Job*> keep;
+        for (Job* j : v)
+            if (j->slot >= 0) keep.push_back(j);
+        v.swap(keep);
+    };
+    live(active_);
+    live(listed_);
+    live(lx_listed_);
     max_slot_ = -1;
     for (Job* j : active_) max_slot_ = std::max(max_slot_, j->slot);
     return fin;

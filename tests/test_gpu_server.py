@@ -101,3 +101,28 @@ def test_refusals_and_validation_statuses():
     assert st["rejected"] == 1
     assert done[tb]["status"] == FINOM_E_UNSORTED
     assert done[tg]["converged"]
+
+
+def test_2d_requests_finishing_in_different_rounds():
+    """2D FP32 requests on the extended-state loop admitted together, with
+    iteration counts far apart: the rounds after each completion run without
+    a rebuild (no new admission), and the completed requests' memory is freed
+    by then. Every result still equals its solve alone."""
+    from paper_2605_26659_amd import FinomServer
+    descs = [_desc_2d(wl.config_tanh_2d(side=s, eps=e), tol=1e-6, itr_max=it)
+             for s, e, it in ((64, 1e-2, 40), (96, 1e-2, 2000), (80, 3e-3, 160), (128, 3e-3, 3000),
+                              (72, 1e-2, 8))]
+    with FinomServer(1 << 30, precision=1, graph_iters=8) as srv:
+        tk = [srv.submit(d) for d in descs]
+        done = _drain(srv, len(descs))
+        st = srv.stats()
+    assert st["completed"] == len(descs) and st["admitted"] == len(descs)
+    assert st["rounds"] > 2
+    iters = set()
+    for c in done:
+        d = descs[tk.index(c["ticket"])]
+        ra, fa, ga = _alone(d, 1)
+        assert ra["fast"] == 4
+        _assert_same(c, d, ra, fa, ga)
+        iters.add(c["iters"])
+    assert len(iters) >= 3
