@@ -52,22 +52,25 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # recorded beside them; after any change to those sources the traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
-TRAFFIC_RESIDENT = {"sources_sha256": "2dc6ef27f1cc1f45772691da50b69210751ab5198347c5c5787aec6b6f7d0827",
-                    "fetch_kib": 452241.0, "write_kib": 188600.0, "n": 1 << 20}
+TRAFFIC_RESIDENT = {"sources_sha256": "1f7ee5c3ddbda8e23203f4410bd79ee9a0994c1013e54e891a362ab135ba01d1",
+                    "fetch_kib": 453175.0, "write_kib": 188601.0, "n": 1 << 20}
 # The resident kernel's instruction counters (rocprofv3 --pmc SQ_INSTS_VALU,
 # SQ_WAVES, per launch, same workload and sources as TRAFFIC_RESIDENT) and the
 # average launch of that run: VALU wave instructions issued, against one per
 # SIMD per 4 clocks (a wave64 instruction occupies a 16-lane SIMD for 4).
-RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.2907e10,
-                 "waves": 4096, "launch_us": 27967.01, "iters": 3117, "n": 1 << 20}
+RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.29073e10,
+                 "waves": 4096, "launch_us": 28030.69, "iters": 3117, "n": 1 << 20}
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4     # wave instructions per second
-TRAFFIC_STREAM = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
-                  "fetch_kib": (22818.1 + 18715.2) / 2, "write_kib": (8214.38 + 8195.85) / 2, "n": 1 << 20}
-# the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per sweep
-TRAFFIC_STREAM_2P24 = {"sources_sha256": None, "fetch_kib": 0.0, "write_kib": 0.0, "n": 1 << 24}
+TRAFFIC_STREAM = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
+                  "fetch_kib": (22189.0 + 18182.7) / 2, "write_kib": (8030.75 + 8011.59) / 2, "n": 1 << 20}
+# the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per
+# sweep (mean of the two variants, plus the carries pre-pass each sweep runs)
+TRAFFIC_STREAM_2P24 = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
+                       "fetch_kib": (298782.0 + 239890.0) / 2 + 71.97,
+                       "write_kib": (108710.0 + 106612.0) / 2 + 105.03, "n": 1 << 24}
 # the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
-TRAFFIC_FP64 = {"sources_sha256": "e9175166a1c260ada072b33f497e387c4493cdf918cdaeb005bd0a76aa8c2fc6",
-                "fetch_kib": (19660.5 + 28045.7) / 2, "write_kib": (8279.98 + 8346.41) / 2, "n": 1 << 20}
+TRAFFIC_FP64 = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
+                "fetch_kib": (27017.9 + 18907.7) / 2, "write_kib": (8251.39 + 8232.59) / 2, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
@@ -79,6 +82,15 @@ STREAM_SOURCES = RESIDENT_SOURCES[1:]
 TRAFFIC_PLAN = {"sources_sha256": "81b9b566466ba8e5e64e2344982331be9e619045dded8b616bc7067ae99449a2",
                 "fetch_kib": 1701.02, "write_kib": 5120010.0, "n": 25600}
 PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
+# The 2D FP32 loop on extended-number state (1024 x 1024 tanh): per iteration
+# the two fused launches (k_line_pair_ext: psi rows, phi columns) read the
+# intermediate, the masses and (psi rows) the checked psi, and write the new
+# state and the next intermediate, 8 bytes each: 40 + 32 bytes per grid point.
+BYTES_2D_ITER = 72
+# Measured per iteration (both launches, each averaged over its dispatches):
+TRAFFIC_2D = {"sources_sha256": "e6cf8cad64a665a1d57ed03b61921fc5f625910e8a3b7c80776e50a6dcec1cf1",
+              "fetch_kib": 11633.6 + 7841.67, "write_kib": 15291.6 + 15208.4, "n": 1 << 20}
+LINE2D_SOURCES = ("paper_2605_26659_amd/csrc/finom_line_ext.hpp",) + STREAM_SOURCES
 
 
 GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
@@ -283,7 +295,16 @@ def bench_tanh_2d(precision):
     r, _, _ = sinkhorn_w1_2d(*args2, precision=precision, want_potentials=False)
     dt = time.perf_counter() - t0
     dense2d = bench_dense_2d(p, r["iters"], p.points * r["iters"] / dt)
-    return {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s",
+    roof = None
+    if r["fast"] == 4:
+        it_s = r["loop_ms"] * 1e-3 / max(1, r["iters"])
+        gbs = BYTES_2D_ITER * p.points / it_s / 1e9
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                "traffic": measured_traffic(TRAFFIC_2D, LINE2D_SOURCES, p.points),
+                "kernel": "k_line_pair_ext<256, 4> x 2 per iteration (psi rows with the check, phi columns "
+                          "after the decision)", "iteration_us": it_s * 1e6,
+                "algorithmic_bytes_per_iteration": BYTES_2D_ITER * p.points}
+    return {"value": p.points * r["iters"] / dt, "unit": "grid-pt*iters/s", "roofline": roof,
             "solve_ms": dt * 1e3, "iters": r["iters"], "w1": r["w1"],
             "marginal_err": r["marginal_err"], "converged": r["converged"], "dense_2d": dense2d,
             "loop_ms": r["loop_ms"], "iteration_us": r["loop_ms"] * 1e3 / max(1, r["iters"]),
