@@ -47,9 +47,12 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # HBM traffic measured with rocprofv3 FETCH_SIZE and WRITE_SIZE at
 # n = m = 2^20 (KiB per dispatch), each scaled by the counter's reading for a
 # plain device copy of known size: for the resident kernel per launch (one
-# solve at eps = 1e-3, tol 1e-6), for the streaming sweeps per sweep (mean of
-# the two variants). Valid only for the kernel sources whose digest is
-# recorded beside them; after any change to those sources the traffic is null.
+# solve at eps = 1e-3, tol 1e-6), for the streaming sweeps per executed sweep
+# (mean of the two variants). The loops replay whole graphs, and the sweeps
+# after a stop exit at once, so a dispatch mean is scaled by dispatches /
+# executed sweeps of the profiled run. Valid only for the kernel sources whose
+# digest is recorded beside them; after any change to those sources the
+# traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
 TRAFFIC_RESIDENT = {"sources_sha256": "1f7ee5c3ddbda8e23203f4410bd79ee9a0994c1013e54e891a362ab135ba01d1",
@@ -62,15 +65,17 @@ RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_ins
                  "waves": 4096, "launch_us": 28030.69, "iters": 3117, "n": 1 << 20}
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4     # wave instructions per second
 TRAFFIC_STREAM = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
-                  "fetch_kib": (22189.0 + 18182.7) / 2, "write_kib": (8030.75 + 8011.59) / 2, "n": 1 << 20}
+                  "fetch_kib": (22189.0 + 18182.7) / 2 * 9648 / 9426,
+                  "write_kib": (8030.75 + 8011.59) / 2 * 9648 / 9426, "n": 1 << 20}
 # the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per
 # sweep (mean of the two variants, plus the carries pre-pass each sweep runs)
 TRAFFIC_STREAM_2P24 = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
-                       "fetch_kib": (298782.0 + 239890.0) / 2 + 71.97,
-                       "write_kib": (108710.0 + 106612.0) / 2 + 105.03, "n": 1 << 24}
+                       "fetch_kib": ((298782.0 + 239890.0) / 2 + 71.97) * 128 / 104,
+                       "write_kib": ((108710.0 + 106612.0) / 2 + 105.03) * 128 / 104, "n": 1 << 24}
 # the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
 TRAFFIC_FP64 = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
-                "fetch_kib": (27017.9 + 18907.7) / 2, "write_kib": (8251.39 + 8232.59) / 2, "n": 1 << 20}
+                "fetch_kib": (27017.9 + 18907.7) / 2 * 9408 / 9381,
+                "write_kib": (8251.39 + 8232.59) / 2 * 9408 / 9381, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
@@ -87,9 +92,11 @@ PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
 # intermediate, the masses and (psi rows) the checked psi, and write the new
 # state and the next intermediate, 8 bytes each: 40 + 32 bytes per grid point.
 BYTES_2D_ITER = 72
-# Measured per iteration (both launches, each averaged over its dispatches):
+# Measured per executed iteration (both launches; 1296 dispatches each for
+# 3 x 401 iterations):
 TRAFFIC_2D = {"sources_sha256": "e6cf8cad64a665a1d57ed03b61921fc5f625910e8a3b7c80776e50a6dcec1cf1",
-              "fetch_kib": 11633.6 + 7841.67, "write_kib": 15291.6 + 15208.4, "n": 1 << 20}
+              "fetch_kib": (11633.6 + 7841.67) * 1296 / 1203, "write_kib": (15291.6 + 15208.4) * 1296 / 1203,
+              "n": 1 << 20}
 LINE2D_SOURCES = ("paper_2605_26659_amd/csrc/finom_line_ext.hpp",) + STREAM_SOURCES
 
 
