@@ -6,7 +6,8 @@
 * FP32-mantissa scans: cost and marginals within 1e-6 of the FP64 oracle.
 * Iterate identity at fixed l against Algorithm 1 on the CPU, up to 2^20
   graded meshes.
-* Edge cases: itr_max 0 and 1, n != m, single points, error statuses.
+* Edge cases: itr_max 0 and 1, n != m, single points, error statuses (a marginal
+  error beyond the FP64 range included).
 """
 import numpy as np
 import pytest
@@ -182,6 +183,26 @@ def test_error_statuses():
     with pytest.raises(FinomError) as e:
         _solve(wl.Problem1D(p.x, p.y * 3e4, p.u, p.v, 1e-3, p.tol, 10))
     assert e.value.status == FINOM_E_ARG
+
+
+@pytest.mark.parametrize("precision,itr_max", [(0, 10), (1, 2)])
+def test_marginal_error_beyond_fp64_range(precision, itr_max):
+    """Masses of 1.5e308 (balanced and finite) at opposite ends, eps so small
+    that the kernel moves no mass between the two points: the loop head's
+    error sum_j |psi_j (K^T phi)_j - v_j| is about 2 x 1.5e308, beyond the
+    largest FP64 number, in the first iterations (the oracle's Algorithm 1
+    shows it), so the solve ends with FINOM_E_NUMERIC. The FP32 loop's own
+    estimate caps its terms; its stop at the cap is checked in FP64, which
+    sees the same overflow."""
+    from paper_2605_26659_amd import FINOM_E_NUMERIC, FinomError
+    x = np.array([0.0, 1.0]); y = np.array([0.0, 1.0])
+    u = np.array([1.5e308, 1e-300]); v = np.array([1e-300, 1.5e308])
+    assert u.sum() == v.sum() and np.isfinite(u.sum())
+    *_, trace = clib.sinkhorn_1d(x, y, u, v, 1e-4, 1e-6, itr_max, trace=True)
+    assert np.isinf(trace[1:3]).all()
+    with pytest.raises(FinomError) as e:
+        _solve(wl.Problem1D(x, y, u, v, 1e-4, 1e-6, itr_max), precision=precision)
+    assert e.value.status == FINOM_E_NUMERIC
 
 
 def test_repeated_calls_are_deterministic():
