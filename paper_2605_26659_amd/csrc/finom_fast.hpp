@@ -676,6 +676,11 @@ __device__ __forceinline__ double block_read_sum(const double* s)
 template <int BLOCK>
 __device__ __forceinline__ bool fast_carried(const LineDesc& L) { return L.ntiles > kFastFix * BLOCK; }
 
+// Tiles per thread whose totals the carries pre-pass keeps in registers:
+// lines of up to kCarryRegs x BLOCK tiles read their totals once, requested
+// together with the decision's partials; longer lines read them once per scan.
+constexpr int kCarryRegs = 16;
+
 // One block per carried line: the stop decision (with dec_partial) and the
 // carries of every tile, the exclusive prefix of the tiles' lower totals and
 // the exclusive suffix of their upper totals (carries laid out as agg).
@@ -687,41 +692,78 @@ __global__ __launch_bounds__(BLOCK) void k_fast_carries(const int* __restrict__ 
 {
     constexpr int NW = BLOCK / kWave;
     constexpr int U = kFastBatch;
+    constexpr int K = kCarryRegs;
     __shared__ Ext<float> s_tmp[2 * NW];
     __shared__ double s_red[NW];
     const LineDesc L = lines[big[blockIdx.x]];
     ProbState* P = ps + L.prob;
     if (P->done) return;
-    if (dec_partial && L.dec_part_off >= 0) {
-        const double err = block_sum_f64<BLOCK>(strided_sum<BLOCK>(dec_partial + L.dec_part_off, L.dec_nparts), s_red);
-        if (fast_decide(L, 0, P, err, parity)) return;
-    }
     const int nt = L.ntiles;
     const int ch = (nt + BLOCK - 1) / BLOCK;   // tiles per thread, consecutive
     const int t0 = threadIdx.x * ch, t1 = min(t0 + ch, nt);
     const gptr<const Ext<float>> AG = gbl(agg) + (long long)L.agg_base * 2;
     const gptr<Ext<float>> CR = gbl(carries) + (long long)L.agg_base * 2;
-    // the chunk's totals (U tiles requested before any is added)
-    Ext<float> sl = ext_zero<float>(), su = ext_zero<float>();
-    for (int a = t0; a < t1; a += U) {
-        Ext<float> vl[U], vu[U];
+    const bool inreg = ch <= K;   // block-uniform
+    // the chunk's totals, requested before the decision's partials so that
+    // both arrive in one round trip (indices clamped into the line)
+    Ext<float> rl[K], ru[K];
+    if (inreg) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = min(a + u, t1 - 1);
-            vl[u] = AG[2 * t];
-            vu[u] = AG[2 * t + 1];
+        for (int u = 0; u < K; ++u) {
+            const int t = min(t0 + u, nt - 1);
+            rl[u] = AG[2 * t];
+            ru[u] = AG[2 * t + 1];
         }
+    }
+    if (dec_partial && L.dec_part_off >= 0) {
+        const double err = block_sum_f64<BLOCK>(strided_sum<BLOCK>(dec_partial + L.dec_part_off, L.dec_nparts), s_red);
+        if (fast_decide(L, 0, P, err, parity)) return;
+    }
+    // the chunk's totals, in tile order
+    Ext<float> sl = ext_zero<float>(), su = ext_zero<float>();
+    if (inreg) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (a + u < t1) {
-                sl = ext_add(sl, vl[u]);
-                su = ext_add(su, vu[u]);
+        for (int u = 0; u < K; ++u)
+            if (t0 + u < t1) {
+                sl = ext_add(sl, rl[u]);
+                su = ext_add(su, ru[u]);
             }
+    } else {
+        for (int a = t0; a < t1; a += U) {
+            Ext<float> vl[U], vu[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = min(a + u, t1 - 1);
+                vl[u] = AG[2 * t];
+                vu[u] = AG[2 * t + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (a + u < t1) {
+                    sl = ext_add(sl, vl[u]);
+                    su = ext_add(su, vu[u]);
+                }
+        }
     }
     Ext<float> el, eu, tl, tu;
     block_scan_both<float, BLOCK>(sl, su, el, eu, tl, tu, s_tmp);
     // per tile: the lower totals before it, the upper totals after it
-    Ext<float> run = el;
+    Ext<float> run = el, runu = eu;
+    if (inreg) {
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            if (t0 + u < t1) {
+                CR[2 * (t0 + u)] = run;
+                run = ext_add(run, rl[u]);
+            }
+#pragma unroll
+        for (int u = K - 1; u >= 0; --u)
+            if (t0 + u < t1) {
+                CR[2 * (t0 + u) + 1] = runu;
+                runu = ext_add(runu, ru[u]);
+            }
+        return;
+    }
     for (int a = t0; a < t1; a += U) {
         Ext<float> vl[U];
 #pragma unroll
@@ -733,7 +775,6 @@ __global__ __launch_bounds__(BLOCK) void k_fast_carries(const int* __restrict__ 
                 run = ext_add(run, vl[u]);
             }
     }
-    Ext<float> runu = eu;
     for (int b = t1 - 1; b >= t0; b -= U) {
         Ext<float> vu[U];
 #pragma unroll
