@@ -409,6 +409,10 @@ Engine::Engine(int precision, hipStream_t stream, int capacity, bool use_graphs)
     HIPCHK(hipStreamCreateWithFlags(&cs_, hipStreamNonBlocking));
     HIPCHK(hipEventCreate(&ev0_));
     HIPCHK(hipEventCreate(&ev1_));
+    HIPCHK(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&ev2_));
+    HIPCHK(hipEventCreate(&ev3_));
+    HIPCHK(hipEventCreateWithFlags(&evu_, hipEventDisableTiming));
 }
 
 Engine::~Engine()
@@ -422,6 +426,13 @@ Engine::~Engine()
     arena_free(&ar_chk_);
     if (ev0_) hipEventDestroy(ev0_);
     if (ev1_) hipEventDestroy(ev1_);
+    if (s2_) {
+        hipStreamSynchronize(s2_);
+        hipStreamDestroy(s2_);
+    }
+    if (ev2_) hipEventDestroy(ev2_);
+    if (ev3_) hipEventDestroy(ev3_);
+    if (evu_) hipEventDestroy(evu_);
     if (cs_) hipStreamDestroy(cs_);
     hipFree(ps_);
     hipHostFree(hps_);
@@ -660,18 +671,47 @@ int resident_batch_capacity(bool gen)
 void Engine::solve_resident()
 {
     if (precision_ != 1 || !fast_allowed() || !resident_allowed()) return;
-    for (int gen = 0; gen < 2; ++gen) {
-        std::vector<Job*> rj;
+    std::vector<Job*> rj[2];
+    for (int gen = 0; gen < 2; ++gen)
         for (Job* j : pending_init_)
             if (gen ? j->gen : (j->d.dim == 1 && j->fast && resident_fits(j->p.na, j->p.nb, j->pk[0].T, false)))
-                rj.push_back(j);
-        if (!rj.empty()) run_resident_batch(rj, gen != 0);
+                rj[gen].push_back(j);
+    if (rj[0].empty() || rj[1].empty()) {
+        for (int gen = 0; gen < 2; ++gen)
+            if (!rj[gen].empty()) run_resident_batch(rj[gen], gen != 0);
+        return;
     }
+    // Both variants at once: the extended grid (cooperative, launched first,
+    // on the second stream) and the fast grid (an ordinary launch, which
+    // ROCm runs beside a cooperative one; cooperative launches run one at a
+    // time). The fast blocks take the CUs the extended grid's blocks leave.
+    // No wait can deadlock: a grid stalls only while fewer of its blocks are
+    // resident than its largest problem has tiles, both grids' largest
+    // problems together need far fewer CUs than the GPU has, and a grid that
+    // runs frees its CUs for the other (neither waits for the other's tiles).
+    Alloc al(&ar_res_, s_);
+    ResidentGrid g[2];
+    for (int gen = 0; gen < 2; ++gen) prepare_resident(al, rj[gen], gen != 0, false, g[gen]);
+    al.uploaded();
+    HIPCHK(hipEventRecord(evu_, s_));
+    HIPCHK(hipStreamWaitEvent(s2_, evu_, 0));
+    launch_resident(g[1], s2_, ev2_, ev3_, true);
+    launch_resident(g[0], s_, ev0_, ev1_, false);
+    HIPCHK(hipMemcpyAsync(g[1].hfail, g[1].flags, sizeof(int), hipMemcpyDeviceToHost, s2_));
+    HIPCHK(hipMemcpyAsync(g[0].hfail, g[0].flags, sizeof(int), hipMemcpyDeviceToHost, s_));
+    HIPCHK(hipStreamSynchronize(s2_));
+    read_states();
+    float ms[2] = {0.f, 0.f};
+    HIPCHK(hipEventElapsedTime(&ms[0], ev0_, ev1_));
+    HIPCHK(hipEventElapsedTime(&ms[1], ev2_, ev3_));
+    for (int gen = 0; gen < 2; ++gen) finish_resident(g[gen], ms[gen]);
 }
 
-void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen, bool resume)
+void Engine::prepare_resident(Alloc& al, const std::vector<Job*>& jobs, bool gen, bool resume, ResidentGrid& g)
 {
-    std::vector<Job*> rj = jobs;
+    std::vector<Job*>& rj = g.jobs;
+    rj = jobs;
+    g.gen = gen;
     // larger problems first: the tiles are handed out in this order
     std::stable_sort(rj.begin(), rj.end(), [](const Job* a, const Job* b) { return a->pk[0].ntiles > b->pk[0].ntiles; });
     if (!resume) {
@@ -680,8 +720,6 @@ void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen, bool re
             if (std::find(rj.begin(), rj.end(), j) == rj.end()) rest.push_back(j);
         pending_init_.swap(rest);
     }
-
-    Alloc al(&ar_res_, s_);
     std::vector<StateInit> ini;
     std::vector<int> first(1, 0);
     for (Job* j : rj) {
@@ -690,7 +728,8 @@ void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen, bool re
     }
     const int total = first.back();
     unsigned long long* rec = al.dev<unsigned long long>(5 * (size_t)total);
-    int* flags = al.dev<int>(2);   // fail, tile counter
+    g.flags = al.dev<int>(2);   // fail, tile counter
+    g.hfail = al.host<int>(1);
     unsigned spin = kResidentSpin;
     if (const char* e = getenv("FINOM_RESIDENT_SPIN")) spin = (unsigned)strtoul(e, nullptr, 10);
     std::vector<ResidentArgs> args(rj.size());
@@ -712,48 +751,64 @@ void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen, bool re
         a.ntiles = j->pk[0].ntiles;
         a.T = j->pk[0].T;
         a.rec = rec + 5 * (size_t)first[i];
-        a.fail = flags;
+        a.fail = g.flags;
         a.spin_limit = spin;
         a.ps = ps_ + j->slot;
     }
     const StateInit* d_ini = upload_vec(al, ini);
-    const ResidentArgs* d_args = upload_vec(al, args);
-    const int* d_first = upload_vec(al, first);
-    al.uploaded();
+    g.b.probs = upload_vec(al, args);
+    g.b.first = upload_vec(al, first);
+    g.b.nprob = (int)rj.size();
+    g.b.total = total;
+    g.b.next = g.flags + 1;
+    g.grid = std::min(total, resident_capacity(gen));
     if (!ini.empty())
         hipLaunchKernelGGL(k_init_states, dim3(blocks_for((long long)ini.size())), dim3(kBlock), 0, s_, d_ini,
                            (int)ini.size(), ps_);
     HIPCHK(hipGetLastError());
     // records start at zero (tag 0: written 0 times)
     HIPCHK(hipMemsetAsync(rec, 0, 5 * (size_t)total * sizeof(unsigned long long), s_));
-    HIPCHK(hipMemsetAsync(flags, 0, 2 * sizeof(int), s_));
-    ResidentBatch b;
-    b.probs = d_args;
-    b.first = d_first;
-    b.nprob = (int)rj.size();
-    b.total = total;
-    b.next = flags + 1;
-    const int grid = std::min(total, resident_capacity(gen));
-    void* kargs[] = {&b};
-    HIPCHK(hipEventRecord(ev0_, s_));
-    HIPCHK(hipLaunchCooperativeKernel(resident_batch_kernel(gen), dim3(grid), dim3(resident_block(gen)), kargs, 0,
-                                      s_));
-    HIPCHK(hipEventRecord(ev1_, s_));
-    int* hfail = al.host<int>(1);
-    HIPCHK(hipMemcpyAsync(hfail, flags, sizeof(int), hipMemcpyDeviceToHost, s_));
-    read_states();
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+    HIPCHK(hipMemsetAsync(g.flags, 0, 2 * sizeof(int), s_));
+}
+
+void Engine::launch_resident(ResidentGrid& g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, bool coop)
+{
+    void* kargs[] = {&g.b};
+    HIPCHK(hipEventRecord(e0, s));
+    if (coop)
+        HIPCHK(hipLaunchCooperativeKernel(resident_batch_kernel(g.gen), dim3(g.grid), dim3(resident_block(g.gen)),
+                                          kargs, 0, s));
+    else
+        HIPCHK(hipLaunchKernel(resident_batch_kernel(g.gen), dim3(g.grid), dim3(resident_block(g.gen)), kargs, 0, s));
+    HIPCHK(hipEventRecord(e1, s));
+}
+
+void Engine::finish_resident(const ResidentGrid& g, float ms)
+{
     loop_ms_total_ += ms;
-    for (Job* j : rj) {
+    for (Job* j : g.jobs) {
         j->resident = true;
         j->started = true;
         j->loop_ms += ms;
     }
-    if (*hfail) {
+    if (*g.hfail) {
         set_last_error("resident solver: a grid wait exceeded its bound");
         throw StatusError{FINOM_E_HIP};
     }
+}
+
+void Engine::run_resident_batch(const std::vector<Job*>& jobs, bool gen, bool resume)
+{
+    Alloc al(&ar_res_, s_);
+    ResidentGrid g;
+    prepare_resident(al, jobs, gen, resume, g);
+    al.uploaded();
+    launch_resident(g, s_, ev0_, ev1_, true);
+    HIPCHK(hipMemcpyAsync(g.hfail, g.flags, sizeof(int), hipMemcpyDeviceToHost, s_));
+    read_states();
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+    finish_resident(g, ms);
 }
 
 bool Engine::add(Job* j)

@@ -11,6 +11,7 @@
 
 #include "../../include/finom.h"
 #include "finom_host.hpp"
+#include "finom_resident.hpp"
 
 namespace finom {
 
@@ -82,6 +83,16 @@ struct Job {
     double points() const { return 0.5 * (double)(p.na + p.nb); }
 };
 
+// One persistent grid of the resident batch kernel, prepared for launch.
+struct ResidentGrid {
+    std::vector<Job*> jobs;   // in tile hand-out order
+    ResidentBatch b{};
+    int grid = 0;
+    bool gen = false;
+    int* flags = nullptr;     // device: fail flag, tile counter
+    int* hfail = nullptr;     // pinned copy of the fail flag
+};
+
 class Engine {
 public:
     Engine(int precision, hipStream_t stream, int capacity, bool use_graphs);
@@ -100,8 +111,8 @@ public:
     void enable_resident() { resident_ = true; }
     // Solves the 1D FP32 jobs that joined since the last round and fit the
     // resident solver, to the end of their loops, in one persistent launch per
-    // variant; they are then ready for harvest. The other jobs are left to
-    // round().
+    // variant (the two variants' grids run at the same time); they are then
+    // ready for harvest. The other jobs are left to round().
     void solve_resident();
     // k iterations (k even) of every live job; then reads their states.
     void round(int k);
@@ -121,6 +132,12 @@ private:
     // resume: the jobs' states are already armed (a stop the FP64 check
     // rejected); otherwise they are initialised
     void run_resident_batch(const std::vector<Job*>& rj, bool gen, bool resume = false);
+    // the parts of a resident batch launch: state initialisation, records and
+    // arguments (on s_), the launch (cooperative or not) between two events,
+    // and the jobs' bookkeeping once the grid has finished
+    void prepare_resident(Alloc& al, const std::vector<Job*>& jobs, bool gen, bool resume, ResidentGrid& g);
+    void launch_resident(ResidentGrid& g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, bool coop);
+    void finish_resident(const ResidentGrid& g, float ms);
     // FP32 mode: the FP64 check of every stopped job's returned pair; jobs
     // that fail it before their cap resume (the resident ones are solved on
     // here, the streaming ones go on in the next rounds) and leave `fin`
@@ -154,6 +171,8 @@ private:
     hipGraphExec_t exec_ = nullptr;
     int graph_k_ = 0;
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+    hipStream_t s2_ = nullptr;      // the second resident grid's stream
+    hipEvent_t ev2_ = nullptr, ev3_ = nullptr, evu_ = nullptr;
     double loop_ms_total_ = 0.0;
     void drop_graph();
 };
