@@ -51,6 +51,19 @@ using gptr = T*;
 template <typename T>
 __device__ __forceinline__ gptr<T> gbl(T* p) { return (gptr<T>)p; }
 
+// A sweep's updated state (always a contiguous run of each line's rows), read
+// by the next kernel only, on any XCD: stored non-temporally, so that its lines
+// need no write-back from L2 at the kernel's end.
+__device__ __forceinline__ void store_update(gptr<double> p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_update(gptr<Ext<float>> p, Ext<float> v)
+{
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 w;
+    w.x = v.m;
+    w.y = __int_as_float(v.e);
+    __builtin_nontemporal_store(w, (gptr<f2>)p);
+}
+
 // Workgroups go to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8), and
 // each XCD has an L2 of its own. xcd_block renumbers a grid of G workgroups so
 // that every XCD takes one contiguous range of work items: neighbouring lines

@@ -539,7 +539,7 @@ __device__ __forceinline__ void fast_tile_store(const FastTileIn<IPT>& t, const 
 #pragma unroll
     for (int q = 0; q < IPT; ++q) {
         const int k = threadIdx.x + q * BLOCK;
-        if (k >= t.tg.nc && k < t.tg.nc + t.tg.nr) OUT[(unsigned)(k - t.tg.nc)] = un[q];
+        if (k >= t.tg.nc && k < t.tg.nc + t.tg.nr) store_update(OUT + (unsigned)(k - t.tg.nc), un[q]);
     }
 }
 

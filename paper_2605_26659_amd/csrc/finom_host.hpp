@@ -416,27 +416,6 @@ inline void add_axis0_lines(Sweep& sw, const Part& p, double eps, const double* 
     }
 }
 
-// Lines along the second axis: every row k of an (nrows x ...) column-major
-// input is one line (stride nrows), written to row k of the output.
-inline void add_axis1_lines(Sweep& sw, const Part& p, double eps, const double* in, double* out,
-                            long long nrows, const double* a0, const double* a1, const double* a2,
-                            int prob = 0)
-{
-    for (long long k = 0; k < nrows; ++k) {
-        LineDesc L = make_line(p.xr, p.R, p.yc, p.C, p.zeta, p.trs, p.T, eps);
-        L.gin = in + k;
-        L.gstride = nrows;
-        L.out = out ? out + k : nullptr;
-        L.ostride = nrows;
-        L.a0 = a0 ? a0 + k : nullptr;
-        L.a1 = a1 ? a1 + k : nullptr;
-        L.a2 = a2 ? a2 + k : nullptr;
-        L.dec_part_off = -1;
-        L.prob = prob;
-        sw.lines.push_back(L);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // 2D solves keep psi (and the target-side masses the check reads) row-major,
 // element (l, j) of the n2 x m2 target grid at j + l m2, while phi stays

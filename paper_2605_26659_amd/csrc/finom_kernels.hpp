@@ -399,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
             if (live) OUT[o] = exp2(val);
         } else if (EPI == EPI_UPDATE) {
             pnew = a0q[q] - val;
-            if (live) OUT[o] = pnew;
+            if (live) store_update(OUT + o, pnew);
         } else if (CHECK) {
             // marginal error of the pair checked at the loop head:
             // |psi_old (K^T phi) - v| = v |2^{g_old + t - log2 v} - 1|; the
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
             const double d = dq[q] + val;
             if (live) red += (double)(vq[q] * fabs(expm1((M)(d * 0.69314718055994530942))));
             pnew = a0q[q] - val;
-            if (live) OUT[o] = pnew;
+            if (live) store_update(OUT + o, pnew);
         } else if (EPI == EPI_COST) {
             if (live) red += exp2(a0q[q] + val);
         }

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(BLOCK) void k_line_ext(PassExt d, ProbState* __rest
                     const float dd = __builtin_fmaf(ldexp_m(O.m, ep - re), W.m, -ldexp_m(A.m, A.e - re));
                     red += __builtin_amdgcn_ldexp((double)fabsf(dd), re);
                 }
-                OUT[i] = Un;
+                store_update(OUT + i, Un);
             }
         }
     }
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
                 const float dd = __builtin_fmaf(ldexp_m(O.m, ep - re), W.m, -ldexp_m(A.m, A.e - re));
                 red += __builtin_amdgcn_ldexp((double)fabsf(dd), re);
             }
-            OUT[i] = un[q];
+            store_update(OUT + i, un[q]);
         }
     }
     if (CHECK) {
