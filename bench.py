@@ -55,27 +55,27 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
-TRAFFIC_RESIDENT = {"sources_sha256": "1f7ee5c3ddbda8e23203f4410bd79ee9a0994c1013e54e891a362ab135ba01d1",
-                    "fetch_kib": 453175.0, "write_kib": 188601.0, "n": 1 << 20}
+TRAFFIC_RESIDENT = {"sources_sha256": "5aa9fdd44ddd44bb420049876a5345424fbfba6ea64f0c01aa7a554c4a09e2cd",
+                    "fetch_kib": 452354.0, "write_kib": 188601.0, "n": 1 << 20}
 # The resident kernel's instruction counters (rocprofv3 --pmc SQ_INSTS_VALU,
 # SQ_WAVES, per launch, same workload and sources as TRAFFIC_RESIDENT) and the
 # average launch of that run: VALU wave instructions issued, against one per
 # SIMD per 4 clocks (a wave64 instruction occupies a 16-lane SIMD for 4).
-RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.29073e10,
-                 "waves": 4096, "launch_us": 28030.69, "iters": 3117, "n": 1 << 20}
+RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.29075e10,
+                 "waves": 4096, "launch_us": 28490.38, "iters": 3117, "n": 1 << 20}
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4     # wave instructions per second
-TRAFFIC_STREAM = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
-                  "fetch_kib": (22189.0 + 18182.7) / 2 * 9648 / 9426,
-                  "write_kib": (8030.75 + 8011.59) / 2 * 9648 / 9426, "n": 1 << 20}
+TRAFFIC_STREAM = {"sources_sha256": "cda2df7821875d77c6056acf7a41d1ae80fe527d2060aa965181ee764b29937c",
+                  "fetch_kib": (22187.4 + 18182.0) / 2 * 9648 / 9426,
+                  "write_kib": (8418.37 + 8421.32) / 2 * 9648 / 9426, "n": 1 << 20}
 # the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per
 # sweep (mean of the two variants, plus the carries pre-pass each sweep runs)
-TRAFFIC_STREAM_2P24 = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
-                       "fetch_kib": ((298782.0 + 239890.0) / 2 + 71.97) * 128 / 104,
-                       "write_kib": ((108710.0 + 106612.0) / 2 + 105.03) * 128 / 104, "n": 1 << 24}
+TRAFFIC_STREAM_2P24 = {"sources_sha256": "cda2df7821875d77c6056acf7a41d1ae80fe527d2060aa965181ee764b29937c",
+                       "fetch_kib": ((298779.0 + 239887.0) / 2 + 75.44) * 128 / 104,
+                       "write_kib": ((113050.0 + 111347.0) / 2 + 105.03) * 128 / 104, "n": 1 << 24}
 # the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
-TRAFFIC_FP64 = {"sources_sha256": "b80dff84fca4c601ce8c73a8bb19b954594397242d57a3f75918068d33efa2b5",
-                "fetch_kib": (27017.9 + 18907.7) / 2 * 9408 / 9381,
-                "write_kib": (8251.39 + 8232.59) / 2 * 9408 / 9381, "n": 1 << 20}
+TRAFFIC_FP64 = {"sources_sha256": "cda2df7821875d77c6056acf7a41d1ae80fe527d2060aa965181ee764b29937c",
+                "fetch_kib": (27018.9 + 18895.4) / 2 * 9408 / 9381,
+                "write_kib": (8774.7 + 8703.61) / 2 * 9408 / 9381, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
@@ -94,8 +94,8 @@ PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
 BYTES_2D_ITER = 72
 # Measured per executed iteration (both launches; 1296 dispatches each for
 # 3 x 401 iterations):
-TRAFFIC_2D = {"sources_sha256": "e6cf8cad64a665a1d57ed03b61921fc5f625910e8a3b7c80776e50a6dcec1cf1",
-              "fetch_kib": (11633.6 + 7841.67) * 1296 / 1203, "write_kib": (15291.6 + 15208.4) * 1296 / 1203,
+TRAFFIC_2D = {"sources_sha256": "758f1305c3594f1c28911ffc5f3d75c4369dd90c6cd3f7a5ce52092ee49616cd",
+              "fetch_kib": (11633.1 + 7841.65) * 1296 / 1203, "write_kib": (15291.6 + 15208.4) * 1296 / 1203,
               "n": 1 << 20}
 LINE2D_SOURCES = ("paper_2605_26659_amd/csrc/finom_line_ext.hpp",) + STREAM_SOURCES
 

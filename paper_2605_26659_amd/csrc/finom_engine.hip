@@ -668,6 +668,21 @@ int resident_batch_capacity(bool gen)
     return cus * per_cu;
 }
 
+// Waits (one lane, at most max_ticks of the 100 MHz real-time counter) until
+// a persistent grid's tile counter shows that `target` blocks have taken their
+// first tile; the launches behind it on the stream then find those blocks
+// resident. A bound, not a condition: the next launch is correct either way.
+constexpr long long kStartWaitTicks = 5000000;   // 50 ms
+
+__global__ void k_wait_started(const int* __restrict__ counter, int target, long long max_ticks)
+{
+    if (threadIdx.x != 0) return;
+    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+           (long long)__builtin_amdgcn_s_memrealtime() - t0 < max_ticks)
+        __builtin_amdgcn_s_sleep(2);
+}
+
 void Engine::solve_resident()
 {
     if (precision_ != 1 || !fast_allowed() || !resident_allowed()) return;
@@ -681,10 +696,12 @@ void Engine::solve_resident()
             if (!rj[gen].empty()) run_resident_batch(rj[gen], gen != 0);
         return;
     }
-    // Both variants at once: the extended grid (cooperative, launched first,
-    // on the second stream) and the fast grid (an ordinary launch, which
-    // ROCm runs beside a cooperative one; cooperative launches run one at a
-    // time). The fast blocks take the CUs the extended grid's blocks leave.
+    // Both variants at once: the extended grid (cooperative, on the engine's
+    // stream) and the fast grid (an ordinary launch on the second stream,
+    // which ROCm runs beside a cooperative one; cooperative launches run one
+    // at a time). A fast block does not fit beside an extended one, so the
+    // fast grid starts once every extended block has taken its first tile
+    // (k_wait_started), and its blocks take the CUs the extended blocks leave.
     // No wait can deadlock: a grid stalls only while fewer of its blocks are
     // resident than its largest problem has tiles, both grids' largest
     // problems together need far fewer CUs than the GPU has, and a grid that
@@ -695,15 +712,18 @@ void Engine::solve_resident()
     al.uploaded();
     HIPCHK(hipEventRecord(evu_, s_));
     HIPCHK(hipStreamWaitEvent(s2_, evu_, 0));
-    launch_resident(g[1], s2_, ev2_, ev3_, true);
-    launch_resident(g[0], s_, ev0_, ev1_, false);
-    HIPCHK(hipMemcpyAsync(g[1].hfail, g[1].flags, sizeof(int), hipMemcpyDeviceToHost, s2_));
-    HIPCHK(hipMemcpyAsync(g[0].hfail, g[0].flags, sizeof(int), hipMemcpyDeviceToHost, s_));
+    launch_resident(g[1], s_, ev0_, ev1_, true);
+    hipLaunchKernelGGL(k_wait_started, dim3(1), dim3(kWave), 0, s2_, (const int*)g[1].b.next, g[1].grid,
+                       kStartWaitTicks);
+    HIPCHK(hipGetLastError());
+    launch_resident(g[0], s2_, ev2_, ev3_, false);
+    HIPCHK(hipMemcpyAsync(g[0].hfail, g[0].flags, sizeof(int), hipMemcpyDeviceToHost, s2_));
+    HIPCHK(hipMemcpyAsync(g[1].hfail, g[1].flags, sizeof(int), hipMemcpyDeviceToHost, s_));
     HIPCHK(hipStreamSynchronize(s2_));
     read_states();
     float ms[2] = {0.f, 0.f};
-    HIPCHK(hipEventElapsedTime(&ms[0], ev0_, ev1_));
-    HIPCHK(hipEventElapsedTime(&ms[1], ev2_, ev3_));
+    HIPCHK(hipEventElapsedTime(&ms[0], ev2_, ev3_));
+    HIPCHK(hipEventElapsedTime(&ms[1], ev0_, ev1_));
     for (int gen = 0; gen < 2; ++gen) finish_resident(g[gen], ms[gen]);
 }
 
