@@ -102,7 +102,8 @@ typedef struct {
                              points: one block per line holds the whole line, each pair
                              of products along one axis in one launch), else 0. 0 for
                              precision 0 and d >= 3 (sinkhorn_w1_nd with one or two axes
-                             reports as sinkhorn_w1_1d / _2d); the server runs 0, 1 or 4. */
+                             reports as sinkhorn_w1_1d / _2d). finom_batch members and
+                             server requests report what their single calls report. */
     int32_t resumes;      /* precision 1: stops of the FP32 loop that the FP64 check of
                              the returned pair rejected (the loop then went on); 0 for
                              precision 0                                               */
@@ -314,8 +315,11 @@ typedef struct {
  * lines of all live problems share each sweep launch, every problem keeps its
  * own iteration counter, loop-head check and stop decision (the iteration of
  * Algorithm 1 / Algorithm 2 is unchanged), and stopped problems retire from
- * the launches. A problem's results equal those of sinkhorn_w1_1d /
- * sinkhorn_w1_2d on it alone.
+ * the launches. In precision 1, the 1D problems that fit the resident solver
+ * run first on persistent grids (one per variant, the two at the same time),
+ * and 2D problems on the extended-state loop each run their own line-pair
+ * launches within the rounds. A problem's results equal those of
+ * sinkhorn_w1_1d / sinkhorn_w1_2d on it alone.
  *   probs: HOST array of count descriptors; res: HOST array of count results
  *   (res[i].status per problem). Problems that fail validation are skipped
  *   (their status says why); the others are solved.
