@@ -1061,6 +1061,36 @@ void Engine::rebuild()
         listed_tiles_ += groups[gi].sw[0]->total_tiles();
     }
     partial_ = al.dev<double>(std::max(nparts, 1));
+    // the extended-state 2D jobs: one launch per pass for all jobs of a line
+    // shape and scan
+    lx_groups_.clear();
+    std::map<std::pair<int, int>, std::vector<Job*>> lx_by;
+    for (Job* j : lx_listed_) lx_by[std::make_pair(j->lx.shape, j->lx.s64)].push_back(j);
+    for (const auto& kv : lx_by) {
+        Ext2DGroup g;
+        g.shape = kv.first.first;
+        g.s64 = kv.first.second;
+        g.nprob = (int)kv.second.size();
+        std::vector<PairExt> pr[4];
+        std::vector<int> fy(1, 0), fx(1, 0);
+        for (const Job* j : kv.second) {
+            for (int b = 0; b < 2; ++b) {
+                pr[b].push_back(j->lx.y[b]);
+                pr[2 + b].push_back(j->lx.x[b]);
+            }
+            fy.push_back(fy.back() + (int)j->lx.n2);
+            fx.push_back(fx.back() + (int)j->lx.m1);
+        }
+        for (int b = 0; b < 2; ++b) {
+            g.y[b] = upload_vec(al, pr[b]);
+            g.x[b] = upload_vec(al, pr[2 + b]);
+        }
+        g.fy = upload_vec(al, fy);
+        g.fx = upload_vec(al, fx);
+        g.ny = fy.back();
+        g.nx = fx.back();
+        lx_groups_.push_back(g);
+    }
     al.uploaded();
     // aggregates of the current phi for the first K^T phi of the next round
     for (int gi : order)
@@ -1081,7 +1111,7 @@ void Engine::launch_iterations(int k, hipStream_t s)
         const int b = it & 1;
         for (size_t q = 0; q < seq_[b].size(); ++q)
             launch_sweep(precision_, IN_LOG2, *seq_[b][q], ps_, partial_, dec_[b][q] ? partial_ : nullptr, b, s);
-        for (Job* j : lx_listed_) ext2d_iteration(j->lx, b, ps_, s);
+        for (const Ext2DGroup& g : lx_groups_) ext2d_group_iteration(g, b, ps_, s);
     }
 }
 

@@ -393,6 +393,8 @@ void ext2d_init(Ext2D& e, const double* x1, const double* x2, const double* y1, 
                 const double* lu, const double* lvr, double kappa, hipStream_t s);
 void ext2d_prologue(const Ext2D& e, ProbState* ps, hipStream_t s);
 void ext2d_iteration(const Ext2D& e, int parity, ProbState* ps, hipStream_t s);
+// One iteration of every problem of a group: two launches in all.
+void ext2d_group_iteration(const Ext2DGroup& g, int parity, ProbState* ps, hipStream_t s);
 // phi and psi (buffer bo) as log2 potentials into F (column-major) and G (row-major).
 void ext2d_to_log2(const Ext2D& e, int bo, double* F, double* G, const double* x1, const double* x2,
                    const double* y1, const double* y2, double kappa, hipStream_t s);

@@ -859,6 +859,27 @@ static void launch_line_pair_t(const PairExt& pr, bool s64, bool check, int nlin
     HIPCHK(hipGetLastError());
 }
 
+template <int B, int I, bool S64>
+static void launch_line_pair_jobs_s(const PairExt* pairs, const int* first, int nprob, bool check, int nlines,
+                                    ProbState* ps, int parity, hipStream_t s)
+{
+    if (check)
+        hipLaunchKernelGGL((k_line_pair_ext_jobs<B, I, true, false, S64>), dim3(nlines), dim3(B), 0, s, pairs, first,
+                           nprob, ps, parity);
+    else
+        hipLaunchKernelGGL((k_line_pair_ext_jobs<B, I, false, true, S64>), dim3(nlines), dim3(B), 0, s, pairs, first,
+                           nprob, ps, parity);
+}
+
+template <int B, int I>
+static void launch_line_pair_jobs_t(const PairExt* pairs, const int* first, int nprob, bool s64, bool check,
+                                    int nlines, ProbState* ps, int parity, hipStream_t s)
+{
+    if (s64) launch_line_pair_jobs_s<B, I, true>(pairs, first, nprob, check, nlines, ps, parity, s);
+    else launch_line_pair_jobs_s<B, I, false>(pairs, first, nprob, check, nlines, ps, parity, s);
+    HIPCHK(hipGetLastError());
+}
+
 // One product storing W (the loop's prologue).
 static void launch_line_ext(int shape, bool s64, const PassExt& d, int nlines, ProbState* ps, hipStream_t s)
 {
@@ -882,6 +903,19 @@ static void launch_line_pair(int shape, bool s64, const PairExt& pr, bool check,
         case 2: launch_line_pair_t<256, 8>(pr, s64, check, nlines, ps, parity, s); break;
         case 3: launch_line_pair_t<128, 8>(pr, s64, check, nlines, ps, parity, s); break;
         default: launch_line_pair_t<64, 16>(pr, s64, check, nlines, ps, parity, s); break;
+    }
+}
+
+// The pairs of several problems of one line shape (k_line_pair_ext_jobs).
+static void launch_line_pair_jobs(int shape, bool s64, const PairExt* pairs, const int* first, int nprob, bool check,
+                                  int nlines, ProbState* ps, int parity, hipStream_t s)
+{
+    switch (shape) {
+        case 0: launch_line_pair_jobs_t<64, 4>(pairs, first, nprob, s64, check, nlines, ps, parity, s); break;
+        case 1: launch_line_pair_jobs_t<256, 4>(pairs, first, nprob, s64, check, nlines, ps, parity, s); break;
+        case 2: launch_line_pair_jobs_t<256, 8>(pairs, first, nprob, s64, check, nlines, ps, parity, s); break;
+        case 3: launch_line_pair_jobs_t<128, 8>(pairs, first, nprob, s64, check, nlines, ps, parity, s); break;
+        default: launch_line_pair_jobs_t<64, 16>(pairs, first, nprob, s64, check, nlines, ps, parity, s); break;
     }
 }
 
@@ -1043,6 +1077,13 @@ void ext2d_init(Ext2D& e, const double* x1, const double* x2, const double* y1, 
 void ext2d_prologue(const Ext2D& e, ProbState* ps, hipStream_t s)
 {
     launch_line_ext(e.shape, e.s64 != 0, e.pro, (int)e.m1, ps, s);
+}
+
+void ext2d_group_iteration(const Ext2DGroup& g, int parity, ProbState* ps, hipStream_t s)
+{
+    if (g.nprob == 0) return;
+    launch_line_pair_jobs(g.shape, g.s64 != 0, g.y[parity], g.fy, g.nprob, true, g.ny, ps, parity, s);
+    launch_line_pair_jobs(g.shape, g.s64 != 0, g.x[parity], g.fx, g.nprob, false, g.nx, ps, parity, s);
 }
 
 void ext2d_iteration(const Ext2D& e, int parity, ProbState* ps, hipStream_t s)

@@ -432,8 +432,9 @@ struct PairExt {
     int R2;
 };
 
+// The pair of products of line l (the body of both kernels below).
 template <int BLOCK, int IPT, bool CHECK, bool DECIDE, bool S64>
-__global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* __restrict__ ps, int parity)
+__device__ __forceinline__ void line_pair(const PairExt& pr, const int l, ProbState* __restrict__ ps, int parity)
 {
     constexpr int T = BLOCK * IPT;
     constexpr int NW = BLOCK / kWave;
@@ -444,7 +445,6 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
     __shared__ double s_red[NW];
 
     const PassExt& d = pr.p1;
-    const int l = xcd_block(blockIdx.x, gridDim.x);
     ProbState* P = ps + d.prob;
     if (P->done) return;
     const int R = d.R, C = d.C, R2 = pr.R2;
@@ -566,6 +566,32 @@ __global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* 
     }
 }
 
+// One problem: block b takes line xcd_block(b).
+template <int BLOCK, int IPT, bool CHECK, bool DECIDE, bool S64>
+__global__ __launch_bounds__(BLOCK) void k_line_pair_ext(PairExt pr, ProbState* __restrict__ ps, int parity)
+{
+    line_pair<BLOCK, IPT, CHECK, DECIDE, S64>(pr, xcd_block(blockIdx.x, gridDim.x), ps, parity);
+}
+
+// Several problems of one line shape in one launch (a batch or the server):
+// work item w = xcd_block(b) is line w - first[j] of problem j, where
+// first[j] <= w < first[j + 1] (first: nprob + 1 prefix sums of the line
+// counts). Each line computes exactly what it computes alone.
+template <int BLOCK, int IPT, bool CHECK, bool DECIDE, bool S64>
+__global__ __launch_bounds__(BLOCK) void k_line_pair_ext_jobs(const PairExt* __restrict__ pairs,
+                                                              const int* __restrict__ first, int nprob,
+                                                              ProbState* __restrict__ ps, int parity)
+{
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nprob;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    line_pair<BLOCK, IPT, CHECK, DECIDE, S64>(pairs[lo], w - first[lo], ps, parity);
+}
+
 // A 2D problem's arrays and launch descriptors for the extended-state loop
 // (host side; filled by ext2d_bind / ext2d_setup in the library).
 struct Ext2D {
@@ -582,6 +608,20 @@ struct Ext2D {
     double* part = nullptr;             // the check's partial error per psi row
     PassExt pro;                        // prologue: SX from the initial phi
     PairExt y[2], x[2];                 // per parity: psi rows, phi columns
+};
+
+// The extended-state 2D problems of one line shape and scan in a batch: per
+// parity, their psi-row and phi-column pair descriptors (device arrays) and
+// the prefix sums of their line counts (host side; filled by the engine).
+struct Ext2DGroup {
+    int shape = -1;
+    int s64 = 0;
+    int nprob = 0;
+    const PairExt* y[2] = {nullptr, nullptr};
+    const PairExt* x[2] = {nullptr, nullptr};
+    const int* fy = nullptr;   // nprob + 1: prefix sums of n2 (psi rows)
+    const int* fx = nullptr;   // nprob + 1: prefix sums of m1 (phi columns)
+    int ny = 0, nx = 0;        // lines of each pass
 };
 
 // Conversions between a grid's log2 potentials (FP64) and its extended
