@@ -94,8 +94,8 @@ PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
 BYTES_2D_ITER = 72
 # Measured per executed iteration (both launches; 1296 dispatches each for
 # 3 x 401 iterations):
-TRAFFIC_2D = {"sources_sha256": "758f1305c3594f1c28911ffc5f3d75c4369dd90c6cd3f7a5ce52092ee49616cd",
-              "fetch_kib": (11633.1 + 7841.65) * 1296 / 1203, "write_kib": (15291.6 + 15208.4) * 1296 / 1203,
+TRAFFIC_2D = {"sources_sha256": "1075294fe6939e5f30ed32e7bef654f1cb3446c2035926dbaa2db136935adc25",
+              "fetch_kib": (11631.9 + 7841.2) * 1296 / 1203, "write_kib": (15291.6 + 15208.4) * 1296 / 1203,
               "n": 1 << 20}
 LINE2D_SOURCES = ("paper_2605_26659_amd/csrc/finom_line_ext.hpp",) + STREAM_SOURCES
 
