@@ -143,6 +143,30 @@ def test_degenerate_2d_members_equal_alone_solves():
         _assert_same(r, d, ra, fa, ga)
 
 
+def test_2d_members_of_several_line_shapes_and_scans():
+    """2D FP32 members on the extended-state loop, grouped into shared
+    launches by line shape (axes up to 256 points, up to 1024) and in-line
+    scan (FP64 mantissas per wave; extended numbers where eps is small), with
+    iteration counts far apart: each equals its single call bit for bit."""
+    from paper_2605_26659_amd import finom_batch
+    descs = []
+    for k, (side, eps, it) in enumerate([(64, 1e-2, 300), (200, 1e-2, 40), (300, 1e-2, 120), (700, 1e-2, 60),
+                                         (90, 1e-3, 200), (260, 1e-3, 80)]):
+        descs.append(_desc_2d(wl.config_tanh_2d(side, eps, seed=300 + k), tol=1e-6, itr_max=it))
+    rng = np.random.default_rng(23)
+    n1, m1, n2, m2 = 150, 80, 120, 140
+    p = wl.Problem2D(np.sort(rng.uniform(0, 1, n1)), np.sort(rng.uniform(0, 1, m1)),
+                     np.sort(rng.uniform(0, 1, n2)), np.sort(rng.uniform(0, 1, m2)),
+                     wl.normalise(np.exp(rng.uniform(-30, 0, (n1, m1)))),
+                     wl.normalise(np.exp(rng.uniform(-30, 0, (n2, m2)))), 2e-3, 0.0, 25)
+    descs.append(_desc_2d(p))
+    st, res = finom_batch(descs, precision=1)
+    assert all(r["fast"] == 4 for r in res)
+    for d, r in zip(descs, res):
+        ra, fa, ga = _alone(d, 1)
+        _assert_same(r, d, ra, fa, ga)
+
+
 def test_members_against_the_oracle():
     from paper_2605_26659_amd import finom_batch
     probs = [wl.config_batch_problem(i, n) for i, n in enumerate([256, 700, 2000])]
