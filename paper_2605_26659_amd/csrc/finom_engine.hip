@@ -941,7 +941,7 @@ void Engine::rebuild()
     };
 
     std::vector<LineRange> chk(listed_.size()), dcd(listed_.size());
-    lx_listed_.clear();
+    std::vector<Job*> lx_listed;   // the jobs on the extended-state 2D loop
     for (size_t ji = 0; ji < listed_.size(); ++ji) {
         Job* j = listed_[ji];
         const JobDesc& d = j->d;
@@ -949,7 +949,7 @@ void Engine::rebuild()
         if (j->ext2d) {
             // its own launches (ext2d_iteration), decision included
             ext2d_setup(j->lx, j->pk[0], j->pkt[0], j->pk[1], j->pkt[1], j->slot);
-            lx_listed_.push_back(j);
+            lx_listed.push_back(j);
             chk[ji] = dcd[ji] = LineRange{-1, 0, 0};
             continue;
         }
@@ -1065,7 +1065,7 @@ void Engine::rebuild()
     // shape and scan
     lx_groups_.clear();
     std::map<std::pair<int, int>, std::vector<Job*>> lx_by;
-    for (Job* j : lx_listed_) lx_by[std::make_pair(j->lx.shape, j->lx.s64)].push_back(j);
+    for (Job* j : lx_listed) lx_by[std::make_pair(j->lx.shape, j->lx.s64)].push_back(j);
     for (const auto& kv : lx_by) {
         Ext2DGroup g;
         g.shape = kv.first.first;
@@ -1401,10 +1401,10 @@ std::vector<Job*> Engine::harvest()
         j->slot = -1;
     }
     // The caller may free the finished jobs once this returns: no list keeps
-    // them. Their lines in the uploaded sweeps stay until the next rebuild and
-    // return at once (their slots are done, and a slot is reused only by add(),
-    // which forces that rebuild); the extended-state launches read the job
-    // itself on the host, so those go now.
+    // them. Their lines in the uploaded sweeps and the extended-state launch
+    // descriptors (device copies) stay until the next rebuild and return at
+    // once (their slots are done, and a slot is reused only by add(), which
+    // forces that rebuild).
     auto live = [](std::vector<Job*>& v) {
         std::vector<Job*> keep;
         for (Job* j : v)
@@ -1413,7 +1413,6 @@ std::vector<Job*> Engine::harvest()
     };
     live(active_);
     live(listed_);
-    live(lx_listed_);
     max_slot_ = -1;
     for (Job* j : active_) max_slot_ = std::max(max_slot_, j->slot);
     return fin;

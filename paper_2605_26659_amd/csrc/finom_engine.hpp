@@ -157,8 +157,8 @@ private:
     std::vector<Job*> active_;      // live jobs, in join order
     std::vector<Job*> pending_init_;   // joined since the last rebuild
     std::vector<Job*> listed_;      // jobs in the current launch lists
-    std::vector<Job*> lx_listed_;   // of them, the jobs on the extended-state 2D loop
-    std::vector<Ext2DGroup> lx_groups_;   // and their launches, by line shape and scan
+    std::vector<Ext2DGroup> lx_groups_;   // launches of the listed jobs on the extended-state 2D loop,
+                                          // by line shape and scan
     Arena ar_setup_, ar_loop_, ar_cost_, ar_res_, ar_chk_;
     std::vector<std::unique_ptr<Sweep>> sweeps_;
     std::vector<Sweep*> seq_[2];
