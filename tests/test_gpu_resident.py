@@ -141,6 +141,28 @@ def test_resident_solve_matches_batch_member():
     _assert_same(res[0], d, ra, fa, ga)
 
 
+def test_resident_batch_wait_bound_with_both_grids(monkeypatch):
+    """Members within and beyond the fast bound: the two persistent grids run
+    at the same time (the extended one cooperative, the fast one behind a wait
+    for the extended blocks' start). With a bound of zero polls both give up,
+    every block leaves and the call reports FINOM_E_HIP; the next call runs
+    both grids normally."""
+    from paper_2605_26659_amd import FINOM_E_HIP, FINOM_NOT_CONVERGED, FINOM_OK, FinomError, finom_batch
+    from test_gpu_batch import _desc_1d
+    probs = [wl.config_batch_problem(100 + i, 20000 + 700 * i) for i in range(12)]
+    descs = [_desc_1d(p, tol=1e-6, itr_max=300) for p in probs]
+    monkeypatch.setenv("FINOM_RESIDENT_SPIN", "0")
+    with pytest.raises(FinomError) as e:
+        finom_batch(descs, precision=1)
+    assert e.value.status == FINOM_E_HIP
+    assert "grid wait" in str(e.value)
+    monkeypatch.delenv("FINOM_RESIDENT_SPIN")
+    st, res = finom_batch(descs, precision=1)
+    assert st in (FINOM_OK, FINOM_NOT_CONVERGED)
+    kinds = {r["fast"] for r in res}
+    assert kinds == {2, 3}, kinds
+
+
 def test_batch_with_more_tiles_than_the_grid():
     """Forty multi-tile members (about a thousand tiles in all, more than the
     grid holds) share the persistent grid: blocks take tiles in order and wait
