@@ -747,7 +747,7 @@ static int run_loop_fn(const std::function<void(int, hipStream_t)>& body, ProbSt
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evs = nullptr;
     int st = FINOM_OK;
     try {
         HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -757,22 +757,35 @@ static int run_loop_fn(const std::function<void(int, hipStream_t)>& body, ProbSt
         HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         HIPCHK(hipEventCreate(&ev0));
         HIPCHK(hipEventCreate(&ev1));
+        HIPCHK(hipEventCreateWithFlags(&evs, hipEventDisableTiming));
         HIPCHK(hipEventRecord(ev0, s));
-        long long max_launches = itr_max / k + 2;
+        // One replay stays queued behind each state read, so the GPU runs it
+        // while the host reads the state after the previous one. Once that
+        // state records a stop, the queued replay changes nothing: every
+        // kernel of the loop returns at once for a stopped problem.
+        long long max_launches = itr_max / k + 3;
         long long launches = 0;
-        for (;;) {
+        auto replay = [&] {
             HIPCHK(hipGraphLaunch(exec, s));
             ++launches;
+        };
+        replay();
+        for (;;) {
             HIPCHK(hipMemcpyAsync(hps, ps, sizeof(ProbState), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipEventRecord(evs, s));
+            replay();
+            HIPCHK(hipEventSynchronize(evs));
             if (hps->done) {
+                HIPCHK(hipStreamSynchronize(s));   // the queued replay has run before the state is touched
                 if (on_stop && on_stop()) {
                     ++max_launches;   // the resumed iteration may start a replay of its own
+                    replay();
                     continue;
                 }
                 break;
             }
             if (launches > max_launches) {   // only if the device state were corrupt
+                HIPCHK(hipStreamSynchronize(s));
                 st = FINOM_E_HIP;
                 break;
             }
@@ -784,6 +797,7 @@ static int run_loop_fn(const std::function<void(int, hipStream_t)>& body, ProbSt
         res->loop_ms = ms;
     } catch (...) {
         st = map_exception();
+        hipStreamSynchronize(s);   // no replay may still run once its graph is destroyed
         if (cs) {
             hipStreamCaptureStatus cst;
             if (hipStreamIsCapturing(cs, &cst) == hipSuccess && cst == hipStreamCaptureStatusActive) {
@@ -795,6 +809,7 @@ static int run_loop_fn(const std::function<void(int, hipStream_t)>& body, ProbSt
     }
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
+    if (evs) hipEventDestroy(evs);
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
     if (cs) hipStreamDestroy(cs);
