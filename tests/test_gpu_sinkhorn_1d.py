@@ -119,6 +119,9 @@ def test_full_size_graded_iterates(eps, precision):
     res, f, g = _solve(p, precision=precision, tol=0.0, itr_max=L)
     fo, go, ito, erro = clib.sinkhorn_1d(p.x, p.y, p.u, p.v, eps, 0.0, L)
     assert res["iters"] == L
+    # n + m = 2^21 merged points: 512 tiles of 4096, the resident solver's
+    # full grid in FP32; FP64 runs the streaming general sweeps
+    assert res["fast"] == (2 if precision == 1 else 0)
     tol = 1e-9 if precision == 0 else 2e-5
     df = np.max(np.abs(f - fo)) / eps
     dg = np.max(np.abs(g - go)) / eps
@@ -129,6 +132,26 @@ def test_full_size_graded_iterates(eps, precision):
     t = clib.finom_logmatvec(p.y, p.x, f, eps)
     err_r = np.sum(np.abs(np.exp((g + t) / eps) - p.v))
     assert abs(res["marginal_err"] - err_r) <= check_slack(g, t, eps, p.v)
+
+
+def test_one_point_past_the_resident_grid():
+    """n = 2^20 + 1, m = 2^20: one tile more than the resident grid holds,
+    so the FP32 solve takes the streaming fast sweeps; 6 iterations against
+    Algorithm 1 on the CPU."""
+    q = wl.config_graded_1d(1 << 20, 1e-2)
+    rng = np.random.default_rng(41)
+    x = np.sort(np.concatenate([q.x, [rng.uniform(q.x[0], q.x[-1])]]))
+    u = np.concatenate([q.u, [q.u.mean()]])
+    u *= q.v.sum() / u.sum()
+    p = wl.Problem1D(x, q.y, u, q.v, q.eps, 0.0, 0)
+    L = 6
+    res, f, g = _solve(p, precision=1, tol=0.0, itr_max=L)
+    assert res["fast"] == 1 and res["iters"] == L
+    fo, go, ito, erro = clib.sinkhorn_1d(p.x, p.y, p.u, p.v, p.eps, 0.0, L)
+    df = np.max(np.abs(f - fo)) / p.eps
+    dg = np.max(np.abs(g - go)) / p.eps
+    assert df <= 2e-5 and dg <= 2e-5, (df, dg)
+    assert abs(res["marginal_err"] - erro) <= 1e-5 * max(erro, 1e-3)
 
 
 def test_streaming_beyond_the_llc_iterates():
