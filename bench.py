@@ -698,6 +698,13 @@ def main():
         print(json.dumps({"copy_bytes": 8 * n, "copies": 10}), flush=True)
         return
 
+    # the tile table of every record (the single-record modes below included,
+    # so that their profiles run the shapes the full run times)
+    if not args.no_autotune:
+        from paper_2605_26659_amd import finom_autotune
+        for p in (1, 0):
+            finom_autotune(p, args.tune_cache or None)
+
     if args.plan_only:
         print(json.dumps(bench_plan(args.steps)), flush=True)
         return
@@ -710,11 +717,6 @@ def main():
     if args.random_3d_only:
         print(json.dumps(bench_random_3d(1 if args.precision == "fp32" else 0)), flush=True)
         return
-
-    if not args.no_autotune:
-        from paper_2605_26659_amd import finom_autotune
-        for p in (1, 0):
-            finom_autotune(p, args.tune_cache or None)
 
     prob = wl.config_graded_1d(args.n, args.eps, tol=args.tol)
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
