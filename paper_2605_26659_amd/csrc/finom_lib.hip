@@ -2023,21 +2023,22 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         ProbState* hps = al.host<ProbState>(2);
         init_state(al, ps, hps, 2, itr_max, tol);
 
-        // Step k of a product (axis a): line L runs over the other axes in the
-        // input's order, the first fastest, and reads in[L n_in + i]; it
-        // writes at the output offset of the same multi-index with the stride
-        // of axis a in the output layout. The epilogue operands of the last
-        // step are indexed as its output.
+        // Step k of a product (axis a): a line is one multi-index over the
+        // other axes; it reads its contiguous run of the input (axis a
+        // fastest there) and writes at the output offset of the same
+        // multi-index with the stride of axis a in the output layout. The
+        // epilogue operands of the last step are indexed as its output.
         auto add_product = [&](Sweep* sw, bool to_target, const std::vector<Part>& parts, const double* in,
                                double* out, const double* a0, const double* a1, const double* a2, int prob) {
-            std::vector<long long> sz(d), st_out, idx(d);
+            std::vector<long long> sz(d), st_in, st_out, idx(d);
             for (int q = 0; q < d; ++q) sz[q] = to_target ? n_src[q] : n_tgt[q];
             for (int k = 0; k < d; ++k) {
                 const int a = to_target ? k : d - 1 - k;
                 const bool last = k == d - 1;
-                const long long nin = sz[a];
+                strides_of(sz, a, st_in);   // the input: axis a fastest (contiguous lines)
                 sz[a] = to_target ? n_tgt[a] : n_src[a];
-                strides_of(sz, last ? a : (to_target ? a + 1 : a - 1), st_out);
+                const int r = last ? a : (to_target ? (a + 1) % d : (a + d - 1) % d);
+                strides_of(sz, r, st_out);
                 long long nlines = 1;
                 for (int q = 0; q < d; ++q)
                     if (q != a) nlines *= sz[q];
@@ -2050,13 +2051,23 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
                 base.dec_part_off = -1;
                 base.prob = prob;
                 sw[k].lines.reserve(sw[k].lines.size() + (size_t)nlines);
+                // lines in the order of the output's layout (its stride-one axis
+                // fastest), so that neighbouring workgroups store neighbouring
+                // elements and fill cache lines together in one L2; each line
+                // reads its input, a contiguous run, wherever it lies
+                std::vector<int> ord;
+                for (int q = 0; q < d; ++q)
+                    if ((r + q) % d != a) ord.push_back((r + q) % d);
                 std::fill(idx.begin(), idx.end(), 0);
                 for (long long L = 0; L < nlines; ++L) {
-                    long long oo = 0;
+                    long long oo = 0, io = 0;
                     for (int q = 0; q < d; ++q)
-                        if (q != a) oo += idx[q] * st_out[q];
+                        if (q != a) {
+                            oo += idx[q] * st_out[q];
+                            io += idx[q] * st_in[q];
+                        }
                     LineDesc Ld = base;
-                    Ld.gin = src + L * nin;
+                    Ld.gin = src + io;
                     Ld.out = dst ? dst + oo : nullptr;
                     if (last) {
                         Ld.a0 = a0 ? a0 + oo : nullptr;
@@ -2064,8 +2075,7 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
                         Ld.a2 = a2 ? a2 + oo : nullptr;
                     }
                     sw[k].lines.push_back(Ld);
-                    for (int q = 1; q < d; ++q) {
-                        const int ax = (a + q) % d;
+                    for (const int ax : ord) {
                         if (++idx[ax] < sz[ax]) break;
                         idx[ax] = 0;
                     }
