@@ -374,8 +374,14 @@ void finom_server_destroy(finom_server* srv);
 
 /*
  * Tile-shape autotuner: times every tile shape on merged-line lengths of
- * 2^9 .. 2^21 elements (batches that fill the GPU, update sweeps) and keeps the
- * fastest per size class for all later calls in the process. With cache_path,
+ * 2^9 .. 2^21 elements (batches that fill the GPU) and keeps the fastest per
+ * size class for all later calls in the process. A class is timed where its
+ * problems run: one iteration of the streaming sweeps, or, in precision 1 where
+ * some shape keeps the class's 1D problems on the resident solver, a batch of
+ * them through finom_batch (64 iterations at tol 0; only such shapes compete,
+ * and shapes that cut the lines into the same tiles are told apart by the
+ * streaming timing). Tuning calls finom_batch internally and synchronises
+ * `stream`. With cache_path,
  * results are read from that file if it exists and written to it otherwise.
  * The environment variable FINOM_TILE_CFG (0..4) overrides every choice.
  * The 2D extended-state loop takes its own line shape (threads per line x

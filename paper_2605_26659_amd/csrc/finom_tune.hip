@@ -1,15 +1,19 @@
 // Tile-shape autotuner. For each length class of merged lines (2^9 .. 2^21
-// elements) it times the update sweep of a batch of lines that fills the GPU
-// (2^22 merged elements in all, distinct meshes and potentials per line) with
-// every tile shape, and keeps the fastest shape for the class. In FP32, where
-// some shape lets a line of the class run on the resident solver, only such
-// shapes compete. The choice only changes how the work is tiled, never what is
-// computed.
+// elements) it times a batch of lines that fills the GPU (2^22 merged elements
+// in all, distinct meshes per line) with every tile shape, and keeps the
+// fastest shape for the class. A class runs where its problems will run: the
+// streaming sweeps (one iteration's two sweeps over all lines), or, in FP32
+// where some shape lets a line of the class run on the resident solver, the
+// resident batch grid (a fixed number of iterations of every line as one batch,
+// its grid timed by HIP events), among the shapes that keep it there. The
+// choice only changes how the work is tiled, never what is computed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/finom.h"
 #include "finom_host.hpp"
@@ -50,6 +54,7 @@ __global__ void k_tune_exp(const double* __restrict__ c, long long n, double kap
 
 struct TuneArrays {
     double *X, *Y, *F, *G0, *G1, *LU, *LV, *V;
+    double* M;   // masses of the resident timings
     Ext<float>*EX, *EY;
     ProbState* ps;
 };
@@ -178,6 +183,49 @@ void write_cache(const char* path)
     fclose(f);
 }
 
+// Iterations of each resident timing; even, so both sweeps of an iteration
+// and the loop head are timed alike for every shape.
+constexpr long long kTuneResidentIters = 64;
+
+// Seconds of the resident batch grid that runs kTuneResidentIters iterations
+// (tol 0) of `count` FP32 problems of n + n points, uniform masses `mass`, with
+// tile shape cfg for their size class cls: the best of two timed calls after
+// one warm-up. Every member of such a batch reports the grid's time.
+double time_resident(int cls, int cfg, long long n, long long count, const TuneArrays& A, const double* mass,
+                     hipStream_t s)
+{
+    set_tuned_cfg(1, cls, cfg);
+    std::vector<finom_problem> pr((size_t)count);
+    std::vector<finom_result> rs((size_t)count);
+    for (long long q = 0; q < count; ++q) {
+        finom_problem& p = pr[(size_t)q];
+        memset(&p, 0, sizeof(p));
+        p.dim = 1;
+        p.n1 = p.n2 = n;   // dim 1: x = x1, y = x2
+        p.x1 = A.X + q * n;
+        p.x2 = A.Y + q * n;
+        p.u = p.v = mass + q * n;
+        p.eps = 1.0;   // every tile inside the fast sweeps' range, as in time_pair
+        p.tol = 0.0;
+        p.itr_max = kTuneResidentIters;
+        p.f_out = A.F + q * n;
+        p.g_out = A.G0 + q * n;
+    }
+    finom_opts o;
+    memset(&o, 0, sizeof(o));
+    o.precision = 1;
+    o.skip_checks = 1;
+    double best = 0.0;
+    for (int trial = 0; trial < 3; ++trial) {
+        const int rc = finom_batch(pr.data(), count, &o, rs.data(), s);
+        if (rc < 0) throw StatusError{rc};
+        double ms = 0.0;
+        for (const finom_result& r : rs) ms = std::max(ms, r.loop_ms);
+        if (trial == 1 || (trial > 1 && ms < best)) best = ms;
+    }
+    return best * 1e-3;
+}
+
 }  // namespace
 
 extern "C" {
@@ -193,6 +241,7 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
         TuneArrays A;
         double** dbl[8] = {&A.X, &A.Y, &A.F, &A.G0, &A.G1, &A.LU, &A.LV, &A.V};
         for (double** d : dbl) *d = al.dev<double>(cap_n);
+        A.M = al.dev<double>(cap_n);
         A.EX = al.dev<Ext<float>>(cap_n);
         A.EY = al.dev<Ext<float>>(cap_n);
         A.ps = al.dev<ProbState>(1);
@@ -235,10 +284,37 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
                 allowed[cfg] = precision == 1 && fast_allowed() && resident_fits(n, n, kCfgs[cfg].T(), false);
                 any_resident = any_resident || allowed[cfg];
             }
+            // The resident solver sees a shape only through the tiles it cuts a
+            // line into: shapes that tile the class's lines alike (the whole
+            // line in one tile, or the same tile length) are timed there once.
+            // Among the shapes of the fastest tiling, the streaming sweeps
+            // decide, as they do for every class without a resident shape:
+            // the class's lines take them on the other paths (d-dimensional
+            // and general sweeps, problems beyond the resident bound).
+            int tiling[kNumCfg];
+            int win = -1;
+            if (any_resident) {
+                hipLaunchKernelGGL(k_tune_fill, dim3(blocks_for(count * n)), dim3(kBlock), 0, s, A.M, count * n,
+                                   1.0 / (double)n);
+                double twin = 0.0;
+                for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+                    const int T = kCfgs[cfg].T();
+                    tiling[cfg] = 2 * n <= T ? 0 : T;
+                    if (!allowed[cfg]) continue;
+                    bool seen = false;
+                    for (int o = 0; o < cfg; ++o) seen = seen || (allowed[o] && tiling[o] == tiling[cfg]);
+                    if (seen) continue;
+                    const double t = time_resident(c, cfg, n, count, A, A.M, s);
+                    if (win < 0 || t < twin) {
+                        twin = t;
+                        win = tiling[cfg];
+                    }
+                }
+            }
             double tbest = 0.0;
             best[c] = -1;
             for (int cfg = 0; cfg < kNumCfg; ++cfg) {
-                if (any_resident && !allowed[cfg]) continue;
+                if (any_resident && (!allowed[cfg] || tiling[cfg] != win)) continue;
                 const double t = time_pair(al, precision, cfg, n, count, A, s);
                 if (best[c] < 0 || t < tbest) {
                     tbest = t;
