@@ -81,12 +81,11 @@ __device__ __forceinline__ void column_terms(const LineDesc& L, long long j, Ext
 }
 
 // A thread's sum of p[t], p[t + BLOCK], ... (t = threadIdx.x) below n, in that
-// order, with eight loads requested before any is added (one memory latency
-// per eight elements).
-template <int BLOCK>
+// order, with U loads requested before any is added (one memory latency per U
+// elements; U does not change the result).
+template <int BLOCK, int U = 8>
 __device__ __forceinline__ double strided_sum(const double* p, int n)
 {
-    constexpr int U = 8;
     const gptr<const double> P = gbl(p);
     double s = 0.0;
     for (int k0 = threadIdx.x; k0 < n; k0 += U * BLOCK) {
@@ -434,16 +433,71 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
     }
 }
 
-// Sum of partial slots [off, off + n) into *out (one block).
+// Sum of partial slots [off, off + n) into *out (one block), in the order of
+// decide_stop with the same BLOCK: the value every deciding block would form.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_reduce_partials(const double* __restrict__ partial, int off,
                                                           int n, double* __restrict__ out)
 {
     __shared__ double s_red[BLOCK / kWave];
-    double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += BLOCK) v += partial[off + k];
-    v = block_sum_f64<BLOCK>(v, s_red);
+    const double v = block_sum_f64<BLOCK>(strided_sum<BLOCK>(partial + off, n), s_red);
     if (threadIdx.x == 0) *out = v;
+}
+
+// The same sum with the loads spread over a block of BLOCK > VB threads: the
+// partials pass through LDS in chunks, and the first VB threads add them in the
+// order of a VB-thread block, so *out is bit for bit k_reduce_partials<VB>'s.
+// One block of VB threads keeps too few loads in flight for tens of
+// thousands of partials.
+template <int VB, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_reduce_partials_wide(const double* __restrict__ partial, int off,
+                                                               int n, double* __restrict__ out)
+{
+    constexpr int CH = 8192;   // partials per chunk (64 KB of LDS)
+    constexpr int U = CH / BLOCK;
+    static_assert(CH % BLOCK == 0 && CH % VB == 0 && VB % kWave == 0 && VB <= BLOCK, "chunk shape");
+    __shared__ double s_v[CH];
+    __shared__ double s_red[VB / kWave];
+    const gptr<const double> P = gbl(partial) + off;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < n; c0 += CH) {
+        const int m = min(CH, n - c0);
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = P[c0 + min((int)threadIdx.x + u * BLOCK, m - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if ((int)threadIdx.x + u * BLOCK < m) s_v[threadIdx.x + u * BLOCK] = t[u];
+        __syncthreads();
+        // chunks start at multiples of VB: thread t's slots continue its
+        // sequence; sixteen LDS reads are requested before any is added
+        if (threadIdx.x < VB) {
+            constexpr int R = 16;
+            for (int k0 = threadIdx.x; k0 < m; k0 += R * VB) {
+                double r[R];
+#pragma unroll
+                for (int u = 0; u < R; ++u) r[u] = s_v[min(k0 + u * VB, m - 1)];
+#pragma unroll
+                for (int u = 0; u < R; ++u)
+                    if (k0 + u * VB < m) acc += r[u];
+            }
+        }
+        __syncthreads();
+    }
+    // block_sum_f64<VB> over the first VB threads (whole waves)
+    if (threadIdx.x < VB) {
+        double v = acc;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_down(v, d, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0) s_red[threadIdx.x / kWave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < VB / kWave; ++w) t += s_red[w];
+        *out = t;
+    }
 }
 
 }  // namespace finom

@@ -729,9 +729,25 @@ static int check_coord_range(Alloc& al, const double* const* meshes, const long 
 // ---------------------------------------------------------------------------
 // the iteration loop: k iterations per captured graph, one state read per graph
 // ---------------------------------------------------------------------------
+// Sums the first n partial slots into slot n in the order of a block of dec's
+// general sweep, so that the sum equals what each of its blocks would form
+// (the decision's pre-reduction, wire_decision below).
+static void launch_pre_reduce(const Sweep& dec, double* partial, int n, hipStream_t s)
+{
+    if (dec.cfg < 0 || dec.cfg >= kNumCfg) throw HipError{hipErrorInvalidValue};
+    switch (kCfgs[kCfgs[dec.cfg].general].block) {
+        case 128: hipLaunchKernelGGL((k_reduce_partials_wide<128, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
+        case 256: hipLaunchKernelGGL((k_reduce_partials_wide<256, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
+        case 512: hipLaunchKernelGGL((k_reduce_partials_wide<512, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
+        default: throw HipError{hipErrorInvalidValue};
+    }
+    HIPCHK(hipGetLastError());
+}
+
 struct LoopSpec {
     std::vector<Sweep*> seq[2];        // sweeps of one iteration, by iteration parity
     std::vector<bool> decides[2];      // sweep takes the stop decision
+    std::vector<int> pre[2];           // partials summed ahead of the sweep (wire_decision), or 0
 };
 
 // on_stop (optional) runs when the state reports a stop; it returns true
@@ -821,8 +837,10 @@ static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* pa
                     const std::function<bool()>& on_stop = {})
 {
     auto body = [&](int b, hipStream_t cs) {
-        for (size_t q = 0; q < lp.seq[b].size(); ++q)
+        for (size_t q = 0; q < lp.seq[b].size(); ++q) {
+            if (q < lp.pre[b].size() && lp.pre[b][q] > 0) launch_pre_reduce(*lp.seq[b][q], partial, lp.pre[b][q], cs);
             launch_sweep(precision, IN_LOG2, *lp.seq[b][q], ps, partial, lp.decides[b][q] ? partial : nullptr, b, cs);
+        }
     };
     return run_loop_fn(body, ps, itr_max, k, s, hps, res, on_stop);
 }
@@ -1166,6 +1184,23 @@ static void set_decision(Sweep& sw, int off, int n)
         sw.lines[i].writes_state = (i == 0) ? 1 : 0;
     }
 }
+
+// A checking sweep of many lines leaves one partial error per tile, and every
+// block of the deciding sweep would sum all of them (quadratic in the lines:
+// 16384 blocks x 16384 partials on a 128^3 grid). Beyond kPreReduceMin
+// partials one block sums them first, in the order a deciding block uses (the
+// same value), and the deciding sweep reads that single sum.
+constexpr int kPreReduceMin = 1024;
+
+// Wires the decision of sweep dec to the nchk partials of its checking sweep
+// (slots [0, nchk)). Returns how many to sum ahead of it into slot nchk, or 0.
+static int wire_decision(Sweep& dec, int nchk)
+{
+    const bool pre = nchk > kPreReduceMin && dec.kind == 0 && !dec.fast;
+    set_decision(dec, pre ? nchk : 0, pre ? 1 : nchk);
+    return pre ? nchk : 0;
+}
+
 
 // ---- resident solver: eligibility
 
@@ -1739,7 +1774,7 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
         const double kappa = 1.0 / (eps * kLn2);
 
         Sweep ktx[2], kty[2], ky[2], kx[2];
-        int nchk = 0;
+        int nchk = 0, pre2d = 0;
         if (!ext2d) {
             for (int b = 0; b < 2; ++b) {
                 ktx[b].cfg = kx[b].cfg = cfg_x;
@@ -1757,7 +1792,7 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
                 add_2d_k_x_lines(kx[b], px, eps, S, n2, F, n1, lu, m1);
             }
             for (int b = 0; b < 2; ++b) {
-                set_decision(ky[b], 0, nchk);
+                pre2d = wire_decision(ky[b], nchk);
                 upload_sweep(al, ktx[b], eb);
                 upload_sweep(al, kty[b], eb);
                 upload_sweep(al, ky[b], eb);
@@ -1783,7 +1818,7 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
             }
         }
         const long long ncost = 2LL * m1 * pxc.ntiles;
-        double* partial = al.dev<double>(std::max<long long>(std::max<long long>(nchk, ncost), n2));
+        double* partial = al.dev<double>(std::max<long long>(std::max<long long>(nchk + 1, ncost), n2));
         double* part64 = confirm ? al.dev<double>(nchk) : nullptr;
         double* err64_d = confirm ? al.dev<double>(1) : nullptr;
         double* err64_h = confirm ? al.host<double>(1) : nullptr;
@@ -1844,6 +1879,7 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
             for (int b = 0; b < 2; ++b) {
                 lp.seq[b] = {&ktx[b], &kty[b], &ky[b], &kx[b]};
                 lp.decides[b] = {false, false, true, false};
+                lp.pre[b] = {0, 0, pre2d, 0};
             }
             st = run_loop(lp, o.precision, ps, partial, itr_max, kit, s, hps, res,
                           confirm ? std::function<bool()>(on_stop) : std::function<bool()>());
@@ -2102,13 +2138,14 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
             nchk = assign_parts(kt[b][d - 1], 0);
             add_product(kp[b].data(), false, pk, G[1 - b], F, lu, nullptr, nullptr, 0);
         }
+        int prend = 0;
         for (int b = 0; b < 2; ++b) {
-            set_decision(kp[b][0], 0, nchk);
+            prend = wire_decision(kp[b][0], nchk);
             for (int k = 0; k < d; ++k) upload_sweep(al, kt[b][k], eb);
             for (int k = 0; k < d; ++k) upload_sweep(al, kp[b][k], eb);
         }
         const long long ncost = (long long)d * (na / n_src[0]) * pc[0].ntiles;
-        double* partial = al.dev<double>(std::max<long long>(nchk, ncost));
+        double* partial = al.dev<double>(std::max<long long>(nchk + 1, ncost));
 
         // FP32 mode: every stop is confirmed by the FP64 check of the pair it
         // returns (K^T phi along every axis with FP64 scans)
@@ -2161,9 +2198,11 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
                 lp.seq[b].push_back(&kt[b][a]);
                 lp.decides[b].push_back(false);
             }
+            lp.pre[b].assign(d, 0);
             for (int a = 0; a < d; ++a) {
                 lp.seq[b].push_back(&kp[b][a]);
                 lp.decides[b].push_back(a == 0);
+                lp.pre[b].push_back(a == 0 ? prend : 0);
             }
         }
         const int kit = o.graph_iters > 0 ? o.graph_iters : default_graph_iters((na + nb) / 2);

@@ -1,7 +1,8 @@
 """sinkhorn_w1_nd (HIP) on d-dimensional tensor meshes against the FP64 oracle.
 
 * d = 3 and d = 4 at fixed iteration counts against the oracle's loop with
-  products axis by axis, including axes of one point and unequal grids;
+  products axis by axis, including axes of one point, unequal grids and a
+  checking sweep of more lines than the deciding sweep sums itself;
 * d = 1 and d = 2 run sinkhorn_w1_1d / sinkhorn_w1_2d: the same bits;
 * d = 3 with FP32-mantissa scans to convergence;
 * argument errors.
@@ -35,7 +36,10 @@ def _solve(xs, xt, u, v, eps, tol, itr_max, precision=0):
 
 @pytest.mark.parametrize("ns,nt", [((6, 5, 4), (5, 7, 3)), ((9, 1, 8), (7, 3, 1)), ((3, 4, 2, 3), (2, 3, 4, 2)),
                                    ((40, 30, 20), (35, 25, 30)), ((3, 2, 4, 2, 3), (2, 3, 2, 3, 2)),
-                                   ((2,) * 8, (2, 3, 2, 1, 2, 2, 2, 2))])
+                                   ((2,) * 8, (2, 3, 2, 1, 2, 2, 2, 2)),
+                                   # 44 x 36 = 1584 checked lines: their partial errors are
+                                   # summed once ahead of the deciding sweep
+                                   ((48, 40, 24), (44, 36, 30))])
 def test_nd_fixed_iterations(ns, nt):
     xs, xt, u, v = _case(sum(ns) * 7 + sum(nt), ns, nt)
     eps, L = 0.05, 15
