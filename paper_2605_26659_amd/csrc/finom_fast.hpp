@@ -684,6 +684,11 @@ constexpr int kCarryRegs = 16;
 // One block per carried line: the stop decision (with dec_partial) and the
 // carries of every tile, the exclusive prefix of the tiles' lower totals and
 // the exclusive suffix of their upper totals (carries laid out as agg).
+// Each thread scans a run of consecutive tiles. On lines of up to
+// kCarryRegs x BLOCK tiles the totals and the carries pass through LDS, so
+// that global memory is read and written coalesced (lane k at tile k + u BLOCK,
+// both numbers of a tile in one 16-byte access): a wave's access to its
+// threads' runs directly would touch a separate cache line per lane.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_fast_carries(const int* __restrict__ big, const LineDesc* __restrict__ lines,
                                                        ProbState* __restrict__ ps, const Ext<float>* __restrict__ agg,
@@ -693,8 +698,11 @@ __global__ __launch_bounds__(BLOCK) void k_fast_carries(const int* __restrict__ 
     constexpr int NW = BLOCK / kWave;
     constexpr int U = kFastBatch;
     constexpr int K = kCarryRegs;
+    constexpr int NT = K * BLOCK;         // tiles the LDS path holds
+    constexpr int NP = NT + NT / 16;      // one pad slot after every 16 tiles
     __shared__ Ext<float> s_tmp[2 * NW];
     __shared__ double s_red[NW];
+    __shared__ Ext<float> s_lo[NP], s_up[NP];
     const LineDesc L = lines[big[blockIdx.x]];
     ProbState* P = ps + L.prob;
     if (P->done) return;
@@ -704,27 +712,37 @@ __global__ __launch_bounds__(BLOCK) void k_fast_carries(const int* __restrict__ 
     const gptr<const Ext<float>> AG = gbl(agg) + (long long)L.agg_base * 2;
     const gptr<Ext<float>> CR = gbl(carries) + (long long)L.agg_base * 2;
     const bool inreg = ch <= K;   // block-uniform
-    // the chunk's totals, requested before the decision's partials so that
-    // both arrive in one round trip (indices clamped into the line)
-    Ext<float> rl[K], ru[K];
+    auto pad = [](int t) { return t + (t >> 4); };
+    // the totals, requested before the decision's partials so that both arrive
+    // in one round trip (indices clamped into the line)
+    int4 q[K];
     if (inreg) {
+        const gptr<const int4> AG4 = (gptr<const int4>)AG;
 #pragma unroll
-        for (int u = 0; u < K; ++u) {
-            const int t = min(t0 + u, nt - 1);
-            rl[u] = AG[2 * t];
-            ru[u] = AG[2 * t + 1];
-        }
+        for (int u = 0; u < K; ++u) q[u] = AG4[min((int)threadIdx.x + u * BLOCK, nt - 1)];
     }
     if (dec_partial && L.dec_part_off >= 0) {
         const double err = block_sum_f64<BLOCK>(strided_sum<BLOCK>(dec_partial + L.dec_part_off, L.dec_nparts), s_red);
         if (fast_decide(L, 0, P, err, parity)) return;
     }
-    // the chunk's totals, in tile order
     Ext<float> sl = ext_zero<float>(), su = ext_zero<float>();
+    Ext<float> rl[K], ru[K];
     if (inreg) {
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int t = threadIdx.x + u * BLOCK;
+            if (t < nt) {
+                s_lo[pad(t)] = Ext<float>{__int_as_float(q[u].x), q[u].y};
+                s_up[pad(t)] = Ext<float>{__int_as_float(q[u].z), q[u].w};
+            }
+        }
+        __syncthreads();
+        // the thread's run of tiles, in tile order
 #pragma unroll
         for (int u = 0; u < K; ++u)
             if (t0 + u < t1) {
+                rl[u] = s_lo[pad(t0 + u)];
+                ru[u] = s_up[pad(t0 + u)];
                 sl = ext_add(sl, rl[u]);
                 su = ext_add(su, ru[u]);
             }
@@ -750,18 +768,29 @@ __global__ __launch_bounds__(BLOCK) void k_fast_carries(const int* __restrict__ 
     // per tile: the lower totals before it, the upper totals after it
     Ext<float> run = el, runu = eu;
     if (inreg) {
+        // each thread overwrites only its own run's slots, read above
 #pragma unroll
         for (int u = 0; u < K; ++u)
             if (t0 + u < t1) {
-                CR[2 * (t0 + u)] = run;
+                s_lo[pad(t0 + u)] = run;
                 run = ext_add(run, rl[u]);
             }
 #pragma unroll
         for (int u = K - 1; u >= 0; --u)
             if (t0 + u < t1) {
-                CR[2 * (t0 + u) + 1] = runu;
+                s_up[pad(t0 + u)] = runu;
                 runu = ext_add(runu, ru[u]);
             }
+        __syncthreads();
+        const gptr<int4> CR4 = (gptr<int4>)CR;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int t = threadIdx.x + u * BLOCK;
+            if (t < nt) {
+                const Ext<float> a = s_lo[pad(t)], b = s_up[pad(t)];
+                CR4[t] = int4{__float_as_int(a.m), a.e, __float_as_int(b.m), b.e};
+            }
+        }
         return;
     }
     for (int a = t0; a < t1; a += U) {
