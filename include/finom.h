@@ -383,6 +383,8 @@ void finom_server_destroy(finom_server* srv);
  * streaming timing). Tuning calls finom_batch internally and synchronises
  * `stream`. With cache_path,
  * results are read from that file if it exists and written to it otherwise.
+ * The general sweeps of 2D and d-dimensional problems run lines of at most
+ * 256 merged points as one tile of an untuned one-wave shape (64 threads x 4).
  * The environment variable FINOM_TILE_CFG (0..4) overrides every choice.
  * The 2D extended-state loop takes its own line shape (threads per line x
  * points per thread: 64x4, 256x4, 256x8 by the longest axis mesh, <= 256,

@@ -343,7 +343,7 @@ JobPlan plan_job(const JobDesc& d, int precision)
         if (p.lx_shape >= 0) p.o_lx = take(ext2d_bytes(d.n1, d.m1, d.n2, d.m2));
     }
     for (int a = 0; a < d.dim; ++a) {
-        p.cfg[a] = tuned_cfg(precision, p.R[a] + p.C[a]);
+        p.cfg[a] = d.dim == 2 ? short_line_cfg(precision, p.R[a] + p.C[a]) : tuned_cfg(precision, p.R[a] + p.C[a]);
         const int T = kCfgs[p.cfg[a]].T();
         p.ntiles[a] = ntiles_for(p.R[a], p.C[a], T);
         p.ntiles_c[a] = ntiles_for(p.R[a], p.C[a], Tc);

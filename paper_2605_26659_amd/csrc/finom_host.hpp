@@ -31,8 +31,13 @@ struct TileCfg {
     int general;
     int T() const { return block * ipt; }
 };
-constexpr int kNumCfg = 5;
-constexpr TileCfg kCfgs[kNumCfg] = {{256, 4, 0}, {256, 8, 1}, {512, 8, 2}, {128, 4, 3}, {512, 4, 1}};
+// The first kNumTunedCfg shapes are the tuner's (and FINOM_TILE_CFG's);
+// kShortCfg, one wave per block, only takes general-sweep lines that fit one
+// of its tiles whole (short_line_cfg).
+constexpr int kNumTunedCfg = 5;
+constexpr int kShortCfg = 5;
+constexpr int kNumCfg = 6;
+constexpr TileCfg kCfgs[kNumCfg] = {{256, 4, 0}, {256, 8, 1}, {512, 8, 2}, {128, 4, 3}, {512, 4, 1}, {64, 4, 5}};
 constexpr int kCostBlock = 256, kCostIpt = 2;
 
 struct HipError {
@@ -63,6 +68,10 @@ inline size_t ext_bytes(int precision) { return precision == 1 ? sizeof(Ext<floa
 // last class everything longer).
 int default_cfg(int precision, long long merged);
 int tuned_cfg(int precision, long long merged);
+// Shape of the lines of a 2D or d-dimensional problem's general sweeps: a
+// line of at most 256 merged points runs as one tile of the one-wave shape
+// (no cross-wave steps), others take tuned_cfg. FINOM_TILE_CFG overrides both.
+int short_line_cfg(int precision, long long merged);
 constexpr int kTuneClasses = 13;
 int tune_class(long long merged);
 void set_tuned_cfg(int precision, int cls, int cfg);

@@ -404,6 +404,7 @@ static void dispatch(int precision, int inm, const Sweep& sw, ProbState* ps, dou
             case 1: FINOM_VARIANTS(float, 256, 8) break;
             case 2: FINOM_VARIANTS(float, 512, 8) break;
             case 3: FINOM_VARIANTS(float, 128, 4) break;
+            case 5: FINOM_VARIANTS(float, 64, 4) break;
         }
     } else {
         switch (gcfg) {
@@ -411,6 +412,7 @@ static void dispatch(int precision, int inm, const Sweep& sw, ProbState* ps, dou
             case 1: FINOM_VARIANTS(double, 256, 8) break;
             case 2: FINOM_VARIANTS(double, 512, 8) break;
             case 3: FINOM_VARIANTS(double, 128, 4) break;
+            case 5: FINOM_VARIANTS(double, 64, 4) break;
         }
     }
     throw HipError{hipErrorInvalidValue};
@@ -449,7 +451,7 @@ void set_tuned_cfg(int precision, int cls, int cfg)
 {
     std::call_once(g_tuned_once, tuned_init);
     if (precision < 0 || precision > 1 || cls < 0 || cls >= kTuneClasses) return;
-    g_tuned[precision][cls].store((cfg >= 0 && cfg < kNumCfg) ? cfg : -1);
+    g_tuned[precision][cls].store((cfg >= 0 && cfg < kNumTunedCfg) ? cfg : -1);
 }
 
 int get_tuned_cfg(int precision, int cls)
@@ -459,13 +461,25 @@ int get_tuned_cfg(int precision, int cls)
     return g_tuned[precision][cls].load();
 }
 
-int tuned_cfg(int precision, long long merged)
+static int forced_cfg()
 {
     const char* e = getenv("FINOM_TILE_CFG");
     if (e && *e) {
         const int c = atoi(e);
-        if (c >= 0 && c < kNumCfg) return c;
+        if (c >= 0 && c < kNumTunedCfg) return c;
     }
+    return -1;
+}
+
+int short_line_cfg(int precision, long long merged)
+{
+    if (forced_cfg() < 0 && merged <= kCfgs[kShortCfg].T()) return kShortCfg;
+    return tuned_cfg(precision, merged);
+}
+
+int tuned_cfg(int precision, long long merged)
+{
+    if (const int c = forced_cfg(); c >= 0) return c;
     const int t = get_tuned_cfg(precision, tune_class(merged));
     if (t >= 0) return t;
     return default_cfg(precision, merged);
@@ -736,6 +750,7 @@ static void launch_pre_reduce(const Sweep& dec, double* partial, int n, hipStrea
 {
     if (dec.cfg < 0 || dec.cfg >= kNumCfg) throw HipError{hipErrorInvalidValue};
     switch (kCfgs[kCfgs[dec.cfg].general].block) {
+        case 64: hipLaunchKernelGGL((k_reduce_partials_wide<64, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
         case 128: hipLaunchKernelGGL((k_reduce_partials_wide<128, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
         case 256: hipLaunchKernelGGL((k_reduce_partials_wide<256, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
         case 512: hipLaunchKernelGGL((k_reduce_partials_wide<512, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
@@ -1713,8 +1728,8 @@ int sinkhorn_w1_2d(const double* x1, int64_t n1, const double* y1, int64_t m1, c
     hipStream_t s = (hipStream_t)stream;
     try {
         Alloc al(stream);
-        const int cfg_x = tuned_cfg(o.precision, n1 + n2);
-        const int cfg_y = tuned_cfg(o.precision, m1 + m2);
+        const int cfg_x = short_line_cfg(o.precision, n1 + n2);
+        const int cfg_y = short_line_cfg(o.precision, m1 + m2);
         const int Tx = kCfgs[cfg_x].T(), Ty = kCfgs[cfg_y].T();
         const int Tc = cost_tile_size();
         const size_t eb = ext_bytes(o.precision);
@@ -2008,7 +2023,7 @@ int sinkhorn_w1_nd(int32_t d, const int64_t* n_src, const double* const* x_src, 
         std::vector<int> cfg(d);
         std::vector<Part> pk(d), pkt(d), pc(d);
         for (int a = 0; a < d; ++a) {
-            cfg[a] = tuned_cfg(o.precision, n_src[a] + n_tgt[a]);
+            cfg[a] = short_line_cfg(o.precision, n_src[a] + n_tgt[a]);
             pk[a] = make_part(al, x_src[a], n_src[a], x_tgt[a], n_tgt[a], kCfgs[cfg[a]].T(), s);
             pkt[a] = make_part_transposed(al, pk[a], s);
             pc[a] = make_part_like(al, pk[a], Tc, s);

@@ -155,7 +155,7 @@ bool read_cache(const char* path, int precision)
     int p, c, v;
     while (ok && fscanf(f, "%d %d %d", &p, &c, &v) == 3) {
         if (p != precision) continue;
-        if (c < 0 || c >= kTuneClasses || v < 0 || v >= kNumCfg) {
+        if (c < 0 || c >= kTuneClasses || v < 0 || v >= kNumTunedCfg) {
             ok = false;
             break;
         }
@@ -235,8 +235,13 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
     if (precision != 0 && precision != 1) return FINOM_E_ARG;
     if (cache_path && *cache_path && read_cache(cache_path, precision)) return FINOM_OK;
     hipStream_t s = (hipStream_t)stream;
+    // The tuner's buffers come from a workspace of its own: the resident
+    // timings call finom_batch on the same stream, and a call restarts the
+    // stream's workspace from its first block.
+    Arena own;
+    int rc = FINOM_OK;
     try {
-        Alloc al(stream);
+        Alloc al(&own, s);
         const long long cap_n = kTuneTotal / 2;
         TuneArrays A;
         double** dbl[8] = {&A.X, &A.Y, &A.F, &A.G0, &A.G1, &A.LU, &A.LV, &A.V};
@@ -278,9 +283,9 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
             // there (one launch per solve): where some shape lets a line of this
             // class fit, only such shapes are candidates, so that tuning never
             // moves a problem off the resident solver
-            bool allowed[kNumCfg];
+            bool allowed[kNumTunedCfg];
             bool any_resident = false;
-            for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+            for (int cfg = 0; cfg < kNumTunedCfg; ++cfg) {
                 allowed[cfg] = precision == 1 && fast_allowed() && resident_fits(n, n, kCfgs[cfg].T(), false);
                 any_resident = any_resident || allowed[cfg];
             }
@@ -291,13 +296,13 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
             // decide, as they do for every class without a resident shape:
             // the class's lines take them on the other paths (d-dimensional
             // and general sweeps, problems beyond the resident bound).
-            int tiling[kNumCfg];
+            int tiling[kNumTunedCfg];
             int win = -1;
             if (any_resident) {
                 hipLaunchKernelGGL(k_tune_fill, dim3(blocks_for(count * n)), dim3(kBlock), 0, s, A.M, count * n,
                                    1.0 / (double)n);
                 double twin = 0.0;
-                for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+                for (int cfg = 0; cfg < kNumTunedCfg; ++cfg) {
                     const int T = kCfgs[cfg].T();
                     tiling[cfg] = 2 * n <= T ? 0 : T;
                     if (!allowed[cfg]) continue;
@@ -313,7 +318,7 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
             }
             double tbest = 0.0;
             best[c] = -1;
-            for (int cfg = 0; cfg < kNumCfg; ++cfg) {
+            for (int cfg = 0; cfg < kNumTunedCfg; ++cfg) {
                 if (any_resident && (!allowed[cfg] || tiling[cfg] != win)) continue;
                 const double t = time_pair(al, precision, cfg, n, count, A, s);
                 if (best[c] < 0 || t < tbest) {
@@ -326,10 +331,12 @@ int finom_autotune(int32_t precision, const char* cache_path, void* stream)
         HIPCHK(hipStreamSynchronize(s));
         for (int c = 0; c < kTuneClasses; ++c) set_tuned_cfg(precision, c, best[c]);
         if (cache_path && *cache_path) write_cache(cache_path);
-        return FINOM_OK;
     } catch (...) {
-        return map_exception();
+        rc = map_exception();
     }
+    hipStreamSynchronize(s);
+    arena_free(&own);
+    return rc;
 }
 
 int finom_tile_config(int32_t precision, int64_t merged)
