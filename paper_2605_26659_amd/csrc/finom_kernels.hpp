@@ -112,8 +112,10 @@ __device__ __forceinline__ bool decide_stop(const LineDesc& L, int tile, ProbSta
                                             double* s_red)
 {
     const double v = strided_sum<BLOCK>(partial + L.dec_part_off, L.dec_nparts);
-    const double err = block_sum_f64<BLOCK>(v, s_red);
+    // the count was written by an earlier kernel: read with the partials, not
+    // after the barrier of the block sum
     const long long l = P->cnt[parity];
+    const double err = block_sum_f64<BLOCK>(v, s_red);
     const bool stop = (l >= P->itr_max) || !(err > P->tol);
     if (L.writes_state && tile == 0 && threadIdx.x == 0) {
         P->err = err;
@@ -260,12 +262,15 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
         }
     }
     double dv = 0.0;
-    if (decide) dv = strided_sum<BLOCK>(dec_partial + L.dec_part_off, L.dec_nparts);
+    long long l = 0;
+    if (decide) {
+        dv = strided_sum<BLOCK>(dec_partial + L.dec_part_off, L.dec_nparts);
+        l = P->cnt[parity];   // written by an earlier kernel: requested with the partials
+    }
 
     // ---- B. stop decision of the loop head (uniform across the block)
     if (decide) {
         const double err = block_sum_f64<BLOCK>(dv, s_red);
-        const long long l = P->cnt[parity];
         const bool stop = (l >= P->itr_max) || !(err > P->tol);
         if (L.writes_state && w.tile == 0 && threadIdx.x == 0) {
             P->err = err;
@@ -453,7 +458,7 @@ template <int VB, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_reduce_partials_wide(const double* __restrict__ partial, int off,
                                                                int n, double* __restrict__ out)
 {
-    constexpr int CH = 8192;   // partials per chunk (64 KB of LDS)
+    constexpr int CH = 16384;   // partials per chunk (128 KB of LDS), loaded in one round trip
     constexpr int U = CH / BLOCK;
     static_assert(CH % BLOCK == 0 && CH % VB == 0 && VB % kWave == 0 && VB <= BLOCK, "chunk shape");
     __shared__ double s_v[CH];
