@@ -55,27 +55,27 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
-TRAFFIC_RESIDENT = {"sources_sha256": "5aa9fdd44ddd44bb420049876a5345424fbfba6ea64f0c01aa7a554c4a09e2cd",
-                    "fetch_kib": 452354.0, "write_kib": 188601.0, "n": 1 << 20}
+TRAFFIC_RESIDENT = {"sources_sha256": "7f3cd5a3deec04fd81c2451cd0a53d19e6b2cce90f3467e2fc8e6e3dc272fcee",
+                    "fetch_kib": 452847.0, "write_kib": 188601.0, "n": 1 << 20}
 # The resident kernel's instruction counters (rocprofv3 --pmc SQ_INSTS_VALU,
 # SQ_WAVES, per launch, same workload and sources as TRAFFIC_RESIDENT) and the
 # average launch of that run: VALU wave instructions issued, against one per
 # SIMD per 4 clocks (a wave64 instruction occupies a 16-lane SIMD for 4).
-RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.29075e10,
-                 "waves": 4096, "launch_us": 28490.38, "iters": 3117, "n": 1 << 20}
+RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.29072e10,
+                 "waves": 4096, "launch_us": 27964.87, "iters": 3117, "n": 1 << 20}
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4     # wave instructions per second
-TRAFFIC_STREAM = {"sources_sha256": "cda2df7821875d77c6056acf7a41d1ae80fe527d2060aa965181ee764b29937c",
-                  "fetch_kib": (22187.4 + 18182.0) / 2 * 9648 / 9426,
-                  "write_kib": (8418.37 + 8421.32) / 2 * 9648 / 9426, "n": 1 << 20}
+TRAFFIC_STREAM = {"sources_sha256": "6f162e0ef2c33b4df2d5ddfacd8ef061015769e64ae0c92c3a4c2a305e5f6630",
+                  "fetch_kib": (21547.8 + 17656.2) / 2 * 9936 / 9426,
+                  "write_kib": (8159.32 + 8167.27) / 2 * 9936 / 9426, "n": 1 << 20}
 # the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per
 # sweep (mean of the two variants, plus the carries pre-pass each sweep runs)
-TRAFFIC_STREAM_2P24 = {"sources_sha256": "cda2df7821875d77c6056acf7a41d1ae80fe527d2060aa965181ee764b29937c",
-                       "fetch_kib": ((298779.0 + 239887.0) / 2 + 75.44) * 128 / 104,
-                       "write_kib": ((113050.0 + 111347.0) / 2 + 105.03) * 128 / 104, "n": 1 << 24}
+TRAFFIC_STREAM_2P24 = {"sources_sha256": "6f162e0ef2c33b4df2d5ddfacd8ef061015769e64ae0c92c3a4c2a305e5f6630",
+                       "fetch_kib": ((239039.0 + 191925.0) / 2 + 62.54) * 160 / 104,
+                       "write_kib": ((90407.8 + 89019.2) / 2 + 84.02) * 160 / 104, "n": 1 << 24}
 # the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
-TRAFFIC_FP64 = {"sources_sha256": "cda2df7821875d77c6056acf7a41d1ae80fe527d2060aa965181ee764b29937c",
-                "fetch_kib": (27018.9 + 18895.4) / 2 * 9408 / 9381,
-                "write_kib": (8774.7 + 8703.61) / 2 * 9408 / 9381, "n": 1 << 20}
+TRAFFIC_FP64 = {"sources_sha256": "6f162e0ef2c33b4df2d5ddfacd8ef061015769e64ae0c92c3a4c2a305e5f6630",
+                "fetch_kib": (26874.9 + 18810.1) / 2 * 9456 / 9381,
+                "write_kib": (8714.52 + 8662.78) / 2 * 9456 / 9381, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
@@ -92,10 +92,10 @@ PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
 # intermediate, the masses and (psi rows) the checked psi, and write the new
 # state and the next intermediate, 8 bytes each: 40 + 32 bytes per grid point.
 BYTES_2D_ITER = 72
-# Measured per executed iteration (both launches; 1296 dispatches each for
+# Measured per executed iteration (both launches; 1392 dispatches each for
 # 3 x 401 iterations):
-TRAFFIC_2D = {"sources_sha256": "1075294fe6939e5f30ed32e7bef654f1cb3446c2035926dbaa2db136935adc25",
-              "fetch_kib": (11631.9 + 7841.2) * 1296 / 1203, "write_kib": (15291.6 + 15208.4) * 1296 / 1203,
+TRAFFIC_2D = {"sources_sha256": "e20a0d41e2f26609b11f9df87018251076d52451e4342c0a38811b9c9f5ab909",
+              "fetch_kib": (10830.6 + 7298.53) * 1392 / 1203, "write_kib": (14237.0 + 14159.5) * 1392 / 1203,
               "n": 1 << 20}
 LINE2D_SOURCES = ("paper_2605_26659_amd/csrc/finom_line_ext.hpp",) + STREAM_SOURCES
 
