@@ -347,10 +347,10 @@ __global__ __launch_bounds__(BLOCK) void k_line_ext(PassExt d, ProbState* __rest
     // ---- stop decision of the loop head (every block sums the same partials
     // in the same order; line 0 records it)
     if (d.dec) {
-        double v = 0.0;
-        for (int k = threadIdx.x; k < d.dec_n; k += BLOCK) v += d.dec[k];
-        const double err = block_sum_f64<BLOCK>(v, s_red);
+        // the partials and the count (written by earlier kernels) in one round trip
+        const double v = strided_sum<BLOCK>(d.dec, d.dec_n);
         const long long it = P->cnt[parity];
+        const double err = block_sum_f64<BLOCK>(v, s_red);
         const bool stop = (it >= P->itr_max) || !(err > P->tol);
         if (l == 0 && threadIdx.x == 0) {
             P->err = err;
@@ -446,10 +446,11 @@ __device__ __forceinline__ void line_pair(const PairExt& pr, const int l, ProbSt
 
     const PassExt& d = pr.p1;
     ProbState* P = ps + d.prob;
-    if (P->done) return;
     const int R = d.R, C = d.C, R2 = pr.R2;
 
-    // ---- loads of both products (tail slots re-read the last element)
+    // ---- loads of both products (tail slots re-read the last element),
+    // requested before the stopped-problem test so that the two round trips
+    // overlap: a stopped problem's line is still allocated and in bounds
     const gptr<const Ext<float>> UI = gbl(d.uin) + (long long)l * d.uin_line;
     const gptr<const Ext<float>> BC = gbl(d.bc), BR = gbl(d.br), BR2 = gbl(pr.br2);
     const gptr<const int> Z = gbl(d.zeta), Z2 = gbl(pr.zeta2);
@@ -478,12 +479,13 @@ __device__ __forceinline__ void line_pair(const PairExt& pr, const int l, ProbSt
         rz2[q] = Z2[i];
         rb2[q] = BR2[i];
     }
+    if (P->done) return;
 
     if (DECIDE) {
-        double v = 0.0;
-        for (int k = threadIdx.x; k < d.dec_n; k += BLOCK) v += d.dec[k];
-        const double err = block_sum_f64<BLOCK>(v, s_red);
+        // the partials and the count (written by earlier kernels) in one round trip
+        const double v = strided_sum<BLOCK>(d.dec, d.dec_n);
         const long long it = P->cnt[parity];
+        const double err = block_sum_f64<BLOCK>(v, s_red);
         const bool stop = (it >= P->itr_max) || !(err > P->tol);
         if (l == 0 && threadIdx.x == 0) {
             P->err = err;
