@@ -94,8 +94,8 @@ PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
 BYTES_2D_ITER = 72
 # Measured per executed iteration (both launches; 1392 dispatches each for
 # 3 x 401 iterations):
-TRAFFIC_2D = {"sources_sha256": "e20a0d41e2f26609b11f9df87018251076d52451e4342c0a38811b9c9f5ab909",
-              "fetch_kib": (10830.6 + 7298.53) * 1392 / 1203, "write_kib": (14237.0 + 14159.5) * 1392 / 1203,
+TRAFFIC_2D = {"sources_sha256": "2188cc6e95bccf8041de96b1a39b3f2cd8974f150ac56d6e3cb632d33bac78d1",
+              "fetch_kib": (10830.6 + 7303.76) * 1392 / 1203, "write_kib": (14237.0 + 14159.5) * 1392 / 1203,
               "n": 1 << 20}
 LINE2D_SOURCES = ("paper_2605_26659_amd/csrc/finom_line_ext.hpp",) + STREAM_SOURCES
 

@@ -840,9 +840,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     const WorkItem w = work[xcd_block(blockIdx.x, gridDim.x)];
     const LineDesc L = lines[w.line];
     ProbState* P = ps + L.prob;
-    // tested once the tile's loads are issued, so that the round trips overlap
-    // (a stopped problem's lines stay allocated, and the loads stay in bounds)
-    const int stopped = P->done;
+    if (P->done) return;
     const gptr<const int> TRS = gbl(L.trs);
     const bool carried = fast_carried<BLOCK>(L);
     const bool decide = dec_partial && L.dec_part_off >= 0 && !carried;
@@ -863,7 +861,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep_fast(const WorkItem* __restrict
     FastTileIn<IPT> A;
     A.tg = fast_geom(L, w.tile, T, TRS[w.tile], TRS[w.tile + 1]);
     fast_tile_load<BLOCK, IPT>(A, L);
-    if (stopped) return;
     RefAcc cl{0.f, kZeroExp}, cu{0.f, kZeroExp};
     if (multi) fast_carries<BLOCK, BIG>(L, agg, w.tile, af, cl, cu);
     const double dv = fast_decision_sum<BLOCK, BIG>(L, dec_partial, np, df);

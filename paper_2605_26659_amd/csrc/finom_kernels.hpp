@@ -204,9 +204,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
     const WorkItem w = work[xcd_block(blockIdx.x, gridDim.x)];
     const LineDesc L = lines[w.line];
     ProbState* P = ps + L.prob;
-    // tested once the tile's loads are issued, so that the round trips overlap
-    // (a stopped problem's lines stay allocated, and the loads stay in bounds)
-    const int stopped = P->done;
+    if (P->done) return;
     const TileGeom<double> tg = tile_geom(L, w.tile, T);
     const int nc = (int)(tg.c1 - tg.c0);
     const int nr = (int)(tg.r1 - tg.r0);
@@ -233,7 +231,6 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const WorkItem* __restrict__ wo
         zq[q] = gbl(L.zeta)[i];
         if (EPI == EPI_UPDATE || CHECK || EPI == EPI_COST) a0q[q] = gbl(L.a0)[i * L.ostride];
     }
-    if (stopped) return;
     Ext<M> cr[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) cr[s] = ext_zero<M>();

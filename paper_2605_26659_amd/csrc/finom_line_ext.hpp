@@ -446,11 +446,10 @@ __device__ __forceinline__ void line_pair(const PairExt& pr, const int l, ProbSt
 
     const PassExt& d = pr.p1;
     ProbState* P = ps + d.prob;
+    if (P->done) return;
     const int R = d.R, C = d.C, R2 = pr.R2;
 
-    // ---- loads of both products (tail slots re-read the last element),
-    // requested before the stopped-problem test so that the two round trips
-    // overlap: a stopped problem's line is still allocated and in bounds
+    // ---- loads of both products (tail slots re-read the last element)
     const gptr<const Ext<float>> UI = gbl(d.uin) + (long long)l * d.uin_line;
     const gptr<const Ext<float>> BC = gbl(d.bc), BR = gbl(d.br), BR2 = gbl(pr.br2);
     const gptr<const int> Z = gbl(d.zeta), Z2 = gbl(pr.zeta2);
@@ -479,7 +478,6 @@ __device__ __forceinline__ void line_pair(const PairExt& pr, const int l, ProbSt
         rz2[q] = Z2[i];
         rb2[q] = BR2[i];
     }
-    if (P->done) return;
 
     if (DECIDE) {
         // the partials and the count (written by earlier kernels) in one round trip
