@@ -454,10 +454,15 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_partials(const double* __restr
 // order of a VB-thread block, so *out is bit for bit k_reduce_partials<VB>'s.
 // One block of VB threads keeps too few loads in flight for tens of
 // thousands of partials.
+// With st it also takes the loop head's decision from that sum, as decide_stop
+// would in each block of the deciding sweep (same value, same rule), so that
+// sweep's blocks only test whether the problem has stopped.
 template <int VB, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_reduce_partials_wide(const double* __restrict__ partial, int off,
-                                                               int n, double* __restrict__ out)
+                                                               int n, double* __restrict__ out,
+                                                               ProbState* __restrict__ st, int parity)
 {
+    if (st && st->done) return;   // a stopped problem's state stays as it is
     constexpr int CH = 16384;   // partials per chunk (128 KB of LDS), loaded in one round trip
     constexpr int U = CH / BLOCK;
     static_assert(CH % BLOCK == 0 && CH % VB == 0 && VB % kWave == 0 && VB <= BLOCK, "chunk shape");
@@ -502,6 +507,19 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_partials_wide(const double* __
 #pragma unroll
         for (int w = 0; w < VB / kWave; ++w) t += s_red[w];
         *out = t;
+        if (st) {
+            const long long l = st->cnt[parity];
+            const bool stop = (l >= st->itr_max) || !(t > st->tol);
+            st->err = t;
+            if (!(t == t) || t == __builtin_inf()) st->status = 1;
+            if (stop) {
+                st->iters = l;
+                st->converged = (t <= st->tol) ? 1 : 0;
+                st->done = 1;
+            } else {
+                st->cnt[parity ^ 1] = l + 1;
+            }
+        }
     }
 }
 

@@ -746,14 +746,15 @@ static int check_coord_range(Alloc& al, const double* const* meshes, const long 
 // Sums the first n partial slots into slot n in the order of a block of dec's
 // general sweep, so that the sum equals what each of its blocks would form
 // (the decision's pre-reduction, wire_decision below).
-static void launch_pre_reduce(const Sweep& dec, double* partial, int n, hipStream_t s)
+static void launch_pre_reduce(const Sweep& dec, double* partial, int n, ProbState* ps, int parity, hipStream_t s)
 {
-    if (dec.cfg < 0 || dec.cfg >= kNumCfg) throw HipError{hipErrorInvalidValue};
+    if (dec.cfg < 0 || dec.cfg >= kNumCfg || dec.lines.empty()) throw HipError{hipErrorInvalidValue};
+    ProbState* P = ps + dec.lines[0].prob;
     switch (kCfgs[kCfgs[dec.cfg].general].block) {
-        case 64: hipLaunchKernelGGL((k_reduce_partials_wide<64, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
-        case 128: hipLaunchKernelGGL((k_reduce_partials_wide<128, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
-        case 256: hipLaunchKernelGGL((k_reduce_partials_wide<256, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
-        case 512: hipLaunchKernelGGL((k_reduce_partials_wide<512, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n); break;
+        case 64: hipLaunchKernelGGL((k_reduce_partials_wide<64, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n, P, parity); break;
+        case 128: hipLaunchKernelGGL((k_reduce_partials_wide<128, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n, P, parity); break;
+        case 256: hipLaunchKernelGGL((k_reduce_partials_wide<256, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n, P, parity); break;
+        case 512: hipLaunchKernelGGL((k_reduce_partials_wide<512, 1024>), dim3(1), dim3(1024), 0, s, partial, 0, n, partial + n, P, parity); break;
         default: throw HipError{hipErrorInvalidValue};
     }
     HIPCHK(hipGetLastError());
@@ -853,7 +854,7 @@ static int run_loop(const LoopSpec& lp, int precision, ProbState* ps, double* pa
 {
     auto body = [&](int b, hipStream_t cs) {
         for (size_t q = 0; q < lp.seq[b].size(); ++q) {
-            if (q < lp.pre[b].size() && lp.pre[b][q] > 0) launch_pre_reduce(*lp.seq[b][q], partial, lp.pre[b][q], cs);
+            if (q < lp.pre[b].size() && lp.pre[b][q] > 0) launch_pre_reduce(*lp.seq[b][q], partial, lp.pre[b][q], ps, b, cs);
             launch_sweep(precision, IN_LOG2, *lp.seq[b][q], ps, partial, lp.decides[b][q] ? partial : nullptr, b, cs);
         }
     };
@@ -1204,7 +1205,8 @@ static void set_decision(Sweep& sw, int off, int n)
 // block of the deciding sweep would sum all of them (quadratic in the lines:
 // 16384 blocks x 16384 partials on a 128^3 grid). Beyond kPreReduceMin
 // partials one block sums them first, in the order a deciding block uses (the
-// same value), and the deciding sweep reads that single sum.
+// same value), and takes the decision from it as every deciding block would;
+// the deciding sweep's blocks then only test whether the problem has stopped.
 constexpr int kPreReduceMin = 1024;
 
 // Wires the decision of sweep dec to the nchk partials of its checking sweep
@@ -1212,7 +1214,8 @@ constexpr int kPreReduceMin = 1024;
 static int wire_decision(Sweep& dec, int nchk)
 {
     const bool pre = nchk > kPreReduceMin && dec.kind == 0 && !dec.fast;
-    set_decision(dec, pre ? nchk : 0, pre ? 1 : nchk);
+    // pre-reduced: the summing kernel takes the decision, the sweep none
+    set_decision(dec, pre ? -1 : 0, pre ? 0 : nchk);
     return pre ? nchk : 0;
 }
 
