@@ -55,27 +55,27 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # traffic is null.
 FETCH_SCALE = 262144 / 131084
 WRITE_SCALE = 262144 / 262144
-TRAFFIC_RESIDENT = {"sources_sha256": "7f3cd5a3deec04fd81c2451cd0a53d19e6b2cce90f3467e2fc8e6e3dc272fcee",
-                    "fetch_kib": 452847.0, "write_kib": 188601.0, "n": 1 << 20}
+TRAFFIC_RESIDENT = {"sources_sha256": "f987251bc05ecf3aa06c84eec559cd50e57b120a468c3c99c9d7d178a6a3581c",
+                    "fetch_kib": 452901.0, "write_kib": 188601.0, "n": 1 << 20}
 # The resident kernel's instruction counters (rocprofv3 --pmc SQ_INSTS_VALU,
 # SQ_WAVES, per launch, same workload and sources as TRAFFIC_RESIDENT) and the
 # average launch of that run: VALU wave instructions issued, against one per
 # SIMD per 4 clocks (a wave64 instruction occupies a 16-lane SIMD for 4).
-RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.29072e10,
-                 "waves": 4096, "launch_us": 27964.87, "iters": 3117, "n": 1 << 20}
+RESIDENT_VALU = {"sources_sha256": TRAFFIC_RESIDENT["sources_sha256"], "valu_insts": 1.29069e10,
+                 "waves": 4096, "launch_us": 27832.53, "iters": 3117, "n": 1 << 20}
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4     # wave instructions per second
-TRAFFIC_STREAM = {"sources_sha256": "6f162e0ef2c33b4df2d5ddfacd8ef061015769e64ae0c92c3a4c2a305e5f6630",
-                  "fetch_kib": (21547.8 + 17656.2) / 2 * 9936 / 9426,
-                  "write_kib": (8159.32 + 8167.27) / 2 * 9936 / 9426, "n": 1 << 20}
+TRAFFIC_STREAM = {"sources_sha256": "897fa852bd2807115cca2e6024c5992448a766042d1bad9cc5a2105c92f2d4de",
+                  "fetch_kib": (21545.0 + 17655.4) / 2 * 9936 / 9426,
+                  "write_kib": (8146.69 + 8186.06) / 2 * 9936 / 9426, "n": 1 << 20}
 # the streaming fast sweeps at n = m = 2^24 (beyond the Infinity Cache), per
 # sweep (mean of the two variants, plus the carries pre-pass each sweep runs)
-TRAFFIC_STREAM_2P24 = {"sources_sha256": "6f162e0ef2c33b4df2d5ddfacd8ef061015769e64ae0c92c3a4c2a305e5f6630",
-                       "fetch_kib": ((239039.0 + 191925.0) / 2 + 62.54) * 160 / 104,
-                       "write_kib": ((90407.8 + 89019.2) / 2 + 84.02) * 160 / 104, "n": 1 << 24}
+TRAFFIC_STREAM_2P24 = {"sources_sha256": "897fa852bd2807115cca2e6024c5992448a766042d1bad9cc5a2105c92f2d4de",
+                       "fetch_kib": ((239037.0 + 191924.0) / 2 + 62.36) * 160 / 104,
+                       "write_kib": ((90425.1 + 89067.5) / 2 + 84.02) * 160 / 104, "n": 1 << 24}
 # the FP64-scan loop's general sweeps, per sweep (mean of the two variants)
-TRAFFIC_FP64 = {"sources_sha256": "6f162e0ef2c33b4df2d5ddfacd8ef061015769e64ae0c92c3a4c2a305e5f6630",
-                "fetch_kib": (26874.9 + 18810.1) / 2 * 9456 / 9381,
-                "write_kib": (8714.52 + 8662.78) / 2 * 9456 / 9381, "n": 1 << 20}
+TRAFFIC_FP64 = {"sources_sha256": "897fa852bd2807115cca2e6024c5992448a766042d1bad9cc5a2105c92f2d4de",
+                "fetch_kib": (26881.8 + 18799.6) / 2 * 9456 / 9381,
+                "write_kib": (8732.28 + 8657.67) / 2 * 9456 / 9381, "n": 1 << 20}
 RESIDENT_SOURCES = ("paper_2605_26659_amd/csrc/finom_resident.hpp",
                     "paper_2605_26659_amd/csrc/finom_fast.hpp",
                     "paper_2605_26659_amd/csrc/finom_kernels.hpp",
@@ -94,8 +94,8 @@ PLAN_SOURCES = ("paper_2605_26659_amd/csrc/finom_plan.hip",)
 BYTES_2D_ITER = 72
 # Measured per executed iteration (both launches; 1392 dispatches each for
 # 3 x 401 iterations):
-TRAFFIC_2D = {"sources_sha256": "2188cc6e95bccf8041de96b1a39b3f2cd8974f150ac56d6e3cb632d33bac78d1",
-              "fetch_kib": (10830.6 + 7303.76) * 1392 / 1203, "write_kib": (14237.0 + 14159.5) * 1392 / 1203,
+TRAFFIC_2D = {"sources_sha256": "bcc64cacd4602208390755fecd1d818826ac16f345f0533ffdc9bbbbc98302b9",
+              "fetch_kib": (10830.1 + 7303.75) * 1392 / 1203, "write_kib": (14237.0 + 14159.5) * 1392 / 1203,
               "n": 1 << 20}
 LINE2D_SOURCES = ("paper_2605_26659_amd/csrc/finom_line_ext.hpp",) + STREAM_SOURCES
 
